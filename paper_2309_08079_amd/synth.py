@@ -1,0 +1,102 @@
+"""Seeded synthetic LQ subproblems shaped like the paper's Kuka IIWA-14 workload.
+
+The paper measures on linearisations of a 7-joint arm (state dimension 14, control
+dimension 7, horizons of 32 to 512 knots; Section V).  Those trajectories are not
+available, so these seeded problems stand in for them.  This module only draws random
+numbers and packs arrays: it holds none of the solver's arithmetic and is the one
+module shared by the GPU path, the CPU oracle and the tests.
+
+Draw recipe (numpy PCG64, float64 draws, then rounded to float32):
+    An ~ N(0,1)^(N-1,nx,nx)      A_k = I + 0.01 An_k
+    Bn ~ N(0,1)^(N-1,nx,nu)      B_k = 0.01 Bn_k
+    Qd ~ U[lo,hi]^(N,nx)         Q_k = diag(Qd_k) + 0.1 W_k W_k^T
+    W  ~ N(0,1)^(N,nx,4)
+    Rd ~ U[0.1,1]^(N-1,nu)       R_k = diag(Rd_k)
+    q  ~ N(0,1)^(N,nx), r ~ N(0,1)^(N-1,nu), x0 ~ N(0,1)^nx, e = 0.
+
+N is the number of state knots (block rows of the Schur complement); there are N-1
+controls and N-1 dynamics constraints.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+FIELDS = ("Q", "R", "A", "B", "q", "r", "x0", "e")
+
+
+def problem(N: int, nx: int = 14, nu: int = 7, seed: int = 1, q_lo: float = 1.0,
+            q_hi: float = 10.0, defects: bool = False) -> dict:
+    """One LQ subproblem as a dict of contiguous float32 arrays.
+
+    Shapes: Q [N,nx,nx], R [N-1,nu,nu], A [N-1,nx,nx], B [N-1,nx,nu], q [N,nx],
+    r [N-1,nu], x0 [nx], e [N-1,nx] (zeros unless ``defects``).
+    """
+    if N < 1:
+        raise ValueError("N must be >= 1")
+    g = np.random.default_rng(seed)
+    M = N - 1
+    An = g.standard_normal((M, nx, nx))
+    Bn = g.standard_normal((M, nx, nu))
+    Qd = g.uniform(q_lo, q_hi, (N, nx))
+    W = g.standard_normal((N, nx, 4))
+    Rd = g.uniform(0.1, 1.0, (M, nu))
+    q = g.standard_normal((N, nx))
+    r = g.standard_normal((M, nu))
+    x0 = g.standard_normal(nx)
+    e = 0.01 * g.standard_normal((M, nx)) if defects else np.zeros((M, nx))
+    A = np.eye(nx)[None] + 0.01 * An
+    B = 0.01 * Bn
+    Q = np.zeros((N, nx, nx))
+    for k in range(N):
+        Q[k] = np.diag(Qd[k]) + 0.1 * (W[k] @ W[k].T)
+    R = np.zeros((M, nu, nu))
+    for k in range(M):
+        R[k] = np.diag(Rd[k])
+    out = dict(Q=Q, R=R, A=A, B=B, q=q, r=r, x0=x0, e=e)
+    return {k: np.ascontiguousarray(v, dtype=np.float32) for k, v in out.items()}
+
+
+def horizons_uniform_choice(batch: int, choices=(32, 64, 128, 256, 512), seed: int = 3000):
+    """Per-problem horizons drawn uniformly from ``choices`` (the mixed-length batch)."""
+    return [int(n) for n in np.random.default_rng(seed).choice(np.asarray(choices), batch)]
+
+
+def horizons_uniform_int(batch: int, lo: int, hi: int, seed: int, first: int | None = None):
+    """Per-problem horizons uniform on the integers [lo, hi]; optionally force the first."""
+    Ns = [int(n) for n in np.random.default_rng(seed).integers(lo, hi + 1, batch)]
+    if first is not None and batch:
+        Ns[0] = int(first)
+    return Ns
+
+
+def batch(Ns, nx: int = 14, nu: int = 7, seed0: int = 0, q_lo: float = 1.0, q_hi: float = 10.0,
+          defects: bool = False):
+    """Problems b = 0..len(Ns)-1 drawn with seed ``seed0 + b`` (list of dicts)."""
+    return [problem(int(n), nx, nu, seed0 + b, q_lo, q_hi, defects) for b, n in enumerate(Ns)]
+
+
+def pack(probs):
+    """Concatenate problems into the packed layout of the batched entry points.
+
+    Knot-indexed arrays (Q, q) are stacked over knots; control-indexed arrays
+    (R, A, B, r, e) over controls; x0 is [batch, nx].  Returns (packed dict, knot_off)
+    where knot_off is int64 [batch+1] with knot_off[b+1]-knot_off[b] = N_b.  Problem b's
+    control-indexed rows start at knot_off[b] - b.
+    """
+    off = np.zeros(len(probs) + 1, dtype=np.int64)
+    for b, p in enumerate(probs):
+        off[b + 1] = off[b] + p["Q"].shape[0]
+    cat = lambda key: np.ascontiguousarray(np.concatenate([p[key] for p in probs], axis=0))
+    packed = {k: cat(k) for k in ("Q", "R", "A", "B", "q", "r", "e")}
+    packed["x0"] = np.ascontiguousarray(np.stack([p["x0"] for p in probs]))
+    return packed, off
+
+
+def unpack_knots(arr, off):
+    """Split a knot-indexed packed array back into per-problem views."""
+    return [arr[off[b]:off[b + 1]] for b in range(len(off) - 1)]
+
+
+def unpack_controls(arr, off):
+    """Split a control-indexed packed array back into per-problem views."""
+    return [arr[off[b] - b:off[b + 1] - b - 1] for b in range(len(off) - 1)]
