@@ -1,0 +1,163 @@
+/*
+ * libmpcpcg -- Schur-complement + preconditioned-conjugate-gradient solve of the
+ * linear-quadratic subproblem of one nonlinear MPC step, on AMD Instinct MI355X (gfx950).
+ *
+ * The problem (MPCGPU, Section III-A, the QP of "Step 1" and the KKT system of
+ * "Step 2") has N state knots x_0..x_{N-1} and N-1 controls u_0..u_{N-2}:
+ *
+ *   min  sum_k 1/2 dx_k^T Q_k dx_k + q_k^T dx_k  +  sum_k 1/2 du_k^T R_k du_k + r_k^T du_k
+ *   s.t. dx_0 = x0,   dx_{k+1} = A_k dx_k + B_k du_k - e_k      (k = 0..N-2)
+ *
+ * whose KKT system [G C^T; C 0][-dZ; lambda] = [g; c] is solved by the Schur complement
+ * method (Section III-B): S lambda = gamma, then dZ = -G^-1 (g - C^T lambda).  The
+ * library forms S = C G^-1 C^T (block tridiagonal, nx x nx blocks; the paper writes
+ * -C G^-1 C^T with gamma negated as well, which is the same equation) and
+ * gamma = C G^-1 g - c, the symmetric stair preconditioner Phi^-1 (Section IV-A,
+ * Phi^-1 = D^-1 - D^-1 E D^-1 with D the block diagonal of S and E = S - D), and runs
+ * PCG (Algorithm 1) until sqrt(eta / eta_ref) < eps, where eta = r^T Phi^-1 r and
+ * eta_ref = gamma^T Phi^-1 gamma.
+ *
+ * Conventions shared by every entry point
+ *  - All array arguments are DEVICE pointers owned by the caller (e.g. torch tensors),
+ *    FP32, row-major, contiguous.  The library never frees or retains caller memory.
+ *    The context owns only its workspace, schedules and captured graphs.
+ *  - Every call is asynchronous on the given hipStream_t (0 = the null stream).  The
+ *    return value reports synchronous errors only (argument validation, a failed
+ *    launch).  Per-problem outcomes are written to a device array of mpcpcg_stats.
+ *  - Supported (nx, nu): (14, 7).  Others return MPCPCG_EUNSUPPORTED.
+ *  - A context is not thread safe; calls that share a context must be serialised by
+ *    the caller and must not overlap on different streams.
+ *  - Calls never abort or throw across the ABI.  mpcpcg_last_error() describes the
+ *    last synchronous failure.
+ */
+#ifndef MPCPCG_H
+#define MPCPCG_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes (negative) and per-problem statuses (non-negative, in mpcpcg_stats). */
+enum {
+  MPCPCG_OK = 0,             /* converged: sqrt(eta/eta_ref) < eps                      */
+  MPCPCG_NOT_CONVERGED = 1,  /* stats only: max_iter reached; lambda/dZ still written    */
+  MPCPCG_BREAKDOWN = 2,      /* stats only: p^T S p <= 0 or a non-finite value (input   *
+                              * not positive definite, NaN/Inf in the data)              */
+  MPCPCG_TIMEOUT = 3,        /* stats only: workgroups of one problem could not meet;   *
+                              * outputs of that problem are undefined                    */
+  MPCPCG_EINVAL = -1,        /* bad argument (null pointer, N < 1, size beyond limits)  */
+  MPCPCG_EUNSUPPORTED = -2,  /* (nx, nu) not compiled into this library                 */
+  MPCPCG_ENOMEM = -3,        /* workspace allocation failed                             */
+  MPCPCG_EHIP = -4           /* a HIP runtime call failed (message in last_error)       */
+};
+
+typedef struct mpcpcg_ctx mpcpcg_ctx;
+
+/* One LQ subproblem (or, for the batched calls, many packed back to back).
+ *   Q  [N][nx][nx]  state cost Hessians (symmetric positive definite)
+ *   R  [N-1][nu][nu] control cost Hessians (symmetric positive definite)
+ *   A  [N-1][nx][nx], B [N-1][nx][nu]  dynamics Jacobians
+ *   q  [N][nx], r [N-1][nu]            cost gradients
+ *   x0 [nx]                             required value of dx_0 (c_0 = -x0)
+ *   e  [N-1][nx] dynamics defects, or NULL for zero.
+ * For packed batches, knot-indexed arrays (Q, q) of problem b start at row
+ * knot_off[b], control-indexed arrays (R, A, B, r, e) at row knot_off[b] - b, and x0 is
+ * [batch][nx]; N is ignored (knot_off defines every horizon). */
+typedef struct {
+  int32_t nx, nu, N;
+  const float *Q, *R, *A, *B, *q, *r, *x0, *e;
+} mpcpcg_problem;
+
+typedef struct {
+  float eps;          /* stopping tolerance on sqrt(eta/eta_ref); e.g. 1e-6           */
+  int32_t max_iter;   /* main-loop iteration cap; 0 means N*nx                         */
+  int32_t warm_start; /* non-zero: lambda (in/out) holds the start iterate on entry     */
+  int32_t reserved;   /* must be 0                                                     */
+} mpcpcg_opts;
+
+typedef struct {
+  int32_t iters;      /* main-loop iterations executed (0 if the start already passed) */
+  int32_t status;     /* MPCPCG_OK / NOT_CONVERGED / BREAKDOWN / TIMEOUT                */
+  float final_ratio;  /* sqrt(eta/eta_ref) at exit                                      */
+  int32_t reserved;
+} mpcpcg_stats;
+
+/* Output of mpcpcg_form_schur: S and Phi^-1 as [N][3][nx][nx] with slot 0 = block
+ * (b, b-1), slot 1 = (b, b), slot 2 = (b, b+1) (blocks outside the matrix are zero), and
+ * gamma [N][nx].  Any of the three pointers may be NULL to skip it. */
+typedef struct {
+  float *S, *Pinv, *gamma;
+} mpcpcg_schur;
+
+/* Create a context for problems of dimension (nx, nu).  max_total_knots bounds the
+ * knots of one call (sum of N over a batch); max_batch bounds the problems of one call.
+ * Allocates device workspace proportional to both on the current device. */
+int mpcpcg_create(mpcpcg_ctx **ctx, int32_t nx, int32_t nu, int64_t max_total_knots,
+                  int32_t max_batch);
+
+/* Release the context's workspace and graphs.  NULL is accepted. */
+int mpcpcg_destroy(mpcpcg_ctx *ctx);
+
+/* Text of the last synchronous error on this context ("" if none; never NULL). */
+const char *mpcpcg_last_error(const mpcpcg_ctx *ctx);
+
+/* Form S, gamma and Phi^-1 of one problem (Section III-B, eq. for theta_k, phi_k,
+ * zeta_k; Section IV-A for Phi^-1).  S and gamma use the positive-definite sign
+ * convention stated at the top of this header. */
+int mpcpcg_form_schur(mpcpcg_ctx *ctx, const mpcpcg_problem *prob, mpcpcg_schur *out,
+                      hipStream_t stream);
+
+/* Solve one problem: formation, PCG (Algorithm 1) and the primal step
+ * dZ = -G^-1 (g - C^T lambda), fused in one launch.
+ *   lambda [N][nx] (out; in as well when opts->warm_start), dx [N][nx], du [N-1][nu],
+ *   stats: device pointer to one mpcpcg_stats. */
+int mpcpcg_solve(mpcpcg_ctx *ctx, const mpcpcg_problem *prob, const mpcpcg_opts *opts,
+                 float *lambda, float *dx, float *du, mpcpcg_stats *stats, hipStream_t stream);
+
+/* Solve `batch` independent problems packed as described for mpcpcg_problem, in one
+ * persistent launch (replayed from a captured hipGraph when the same pointers and
+ * horizons are seen again).  knot_off is a HOST array [batch+1] of prefix sums of the
+ * horizons (knot_off[0] = 0).  lambda/dx use knot rows, du control rows, stats [batch]. */
+int mpcpcg_solve_batched(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
+                         const mpcpcg_problem *packed, const mpcpcg_opts *opts, float *lambda,
+                         float *dx, float *du, mpcpcg_stats *stats, hipStream_t stream);
+
+/* Adjoint (reverse-mode) solve of the batched forward solve for a scalar loss
+ * L(lambda, dx, du).  Given the saved forward outputs and dL/dlambda (and optionally
+ * dL/ddx, dL/ddu, NULL = 0), solves S mu = dL/dlambda + C G^-1 dL/ddZ with the same PCG
+ * and stopping rule, forms nu_1 = -G^-1 (dL/ddZ - C^T mu), and writes the gradients
+ * restricted to the block sparsity of the inputs:
+ *   dQ_k = sym(nu1x_k dx_k^T), dR_k = sym(nu1u_k du_k^T),
+ *   dA_k = lambda_{k+1} nu1x_k^T + mu_{k+1} dx_k^T, dB_k = lambda_{k+1} nu1u_k^T + mu_{k+1} du_k^T,
+ *   dq_k = nu1x_k, dr_k = nu1u_k, dx0 = mu_0, de_k = -mu_{k+1}, dgamma = mu.
+ * Layouts equal those of the corresponding inputs; de and dgamma may be NULL.
+ * stats [batch] report the adjoint PCG. */
+int mpcpcg_backward(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
+                    const mpcpcg_problem *packed, const mpcpcg_opts *opts, const float *lambda,
+                    const float *dx, const float *du, const float *dL_dlambda,
+                    const float *dL_ddx, const float *dL_ddu, float *dQ, float *dR, float *dA,
+                    float *dB, float *dq, float *dr, float *dx0, float *de, float *dgamma,
+                    mpcpcg_stats *stats, hipStream_t stream);
+
+/* Schedule control for the batched calls.
+ * mpcpcg_set_knots_per_group fixes the knots handled by one workgroup (a multiple of 4
+ * from 4 to 32; 0 restores the automatic choice).  mpcpcg_autotune times every
+ * candidate shape on the given batch (running real solves, outputs overwritten) and
+ * caches the fastest for that batch signature; it synchronises the stream.  The chosen
+ * value is returned in *knots_per_group (may be NULL). */
+int mpcpcg_set_knots_per_group(mpcpcg_ctx *ctx, int32_t knots_per_group);
+int mpcpcg_autotune(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
+                    const mpcpcg_problem *packed, const mpcpcg_opts *opts, float *lambda,
+                    float *dx, float *du, mpcpcg_stats *stats, hipStream_t stream,
+                    int32_t *knots_per_group);
+
+/* Enable (1, default) or disable (0) hipGraph capture/replay in mpcpcg_solve_batched. */
+int mpcpcg_set_graph(mpcpcg_ctx *ctx, int32_t enable);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPCPCG_H */

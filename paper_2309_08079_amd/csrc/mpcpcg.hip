@@ -1,0 +1,467 @@
+// Host side of libmpcpcg: argument validation, workspace, schedules, launches, graphs.
+// The C ABI is declared in include/mpcpcg.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "mpcpcg.h"
+#include "pcg_kernel.h"
+
+namespace {
+
+using mpc::Gang;
+using mpc::KArgs;
+using mpc::ProbDesc;
+using mpc::Task;
+
+constexpr int kNX = 14, kNU = 7;
+constexpr int kKpwChoices[] = {4, 8, 16, 32};
+
+// One schedule per (horizon signature, knots per workgroup): problem descriptors and the
+// task list in longest-first order, resident on the device, plus the graph execs that
+// replay the persistent launch for it.
+struct Schedule {
+  std::vector<int64_t> off;
+  int kpw = 0;
+  int ntasks = 0;
+  int nprobs = 0;
+  ProbDesc *d_probs = nullptr;
+  Task *d_tasks = nullptr;
+  hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
+  hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
+  hipGraphNode_t node[3] = {nullptr, nullptr, nullptr};
+  KArgs args[3];
+  int grid[3] = {0, 0, 0};
+};
+
+}  // namespace
+
+struct mpcpcg_ctx {
+  int nx = 0, nu = 0, device = 0, cus = 0;
+  int64_t max_knots = 0;
+  int max_batch = 0;
+  int64_t max_tasks = 0;
+  int kpw_override = 0;
+  int use_graph = 1;
+  double *qinv_ws = nullptr, *rinv_ws = nullptr;
+  void *tws = nullptr;
+  Gang *gang = nullptr;
+  int *queue = nullptr;
+  std::map<std::pair<std::vector<int64_t>, int>, std::unique_ptr<Schedule>> sched;
+  std::map<std::vector<int64_t>, int> tuned;  // horizon signature -> knots per workgroup
+  std::string err;
+};
+
+namespace {
+
+int fail(mpcpcg_ctx *c, int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                                 \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(ctx, MPCPCG_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));      \
+  } while (0)
+
+using KernelFn = void (*)(KArgs);
+
+template <int KPW>
+KernelFn kernel_for(int mode) {
+  switch (mode) {
+    case mpc::kForm: return mpc::pcg_kernel<kNX, kNU, KPW, mpc::kForm>;
+    case mpc::kForward: return mpc::pcg_kernel<kNX, kNU, KPW, mpc::kForward>;
+    default: return mpc::pcg_kernel<kNX, kNU, KPW, mpc::kAdjoint>;
+  }
+}
+
+KernelFn kernel_for(int kpw, int mode) {
+  switch (kpw) {
+    case 4: return kernel_for<4>(mode);
+    case 8: return kernel_for<8>(mode);
+    case 16: return kernel_for<16>(mode);
+    default: return kernel_for<32>(mode);
+  }
+}
+
+bool valid_kpw(int k) {
+  for (int c : kKpwChoices)
+    if (c == k) return true;
+  return false;
+}
+
+// resident workgroups of this kernel on the whole device
+int capacity(mpcpcg_ctx *c, int kpw, int mode, int *out) {
+  int nb = 0;
+  HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, reinterpret_cast<const void *>(kernel_for(kpw, mode)), kpw * mpc::kGroup, 0));
+  *out = nb * c->cus;
+  return MPCPCG_OK;
+}
+
+size_t tws_bytes() { return sizeof(mpc::TaskWS<kNX>); }
+
+int check_problem_ptrs(mpcpcg_ctx *c, const mpcpcg_problem *p, bool need_ctrl) {
+  if (!p) return fail(c, MPCPCG_EINVAL, "problem is NULL");
+  if (p->nx != c->nx || p->nu != c->nu)
+    return fail(c, MPCPCG_EINVAL, "problem (nx, nu) = (%d, %d) differs from the context (%d, %d)",
+                p->nx, p->nu, c->nx, c->nu);
+  if (!p->Q || !p->q || !p->x0) return fail(c, MPCPCG_EINVAL, "Q, q and x0 must be non-NULL");
+  if (need_ctrl && (!p->R || !p->A || !p->B || !p->r))
+    return fail(c, MPCPCG_EINVAL, "R, A, B and r must be non-NULL when a horizon exceeds one knot");
+  return MPCPCG_OK;
+}
+
+int check_opts(mpcpcg_ctx *c, const mpcpcg_opts *o) {
+  if (!o) return fail(c, MPCPCG_EINVAL, "opts is NULL");
+  if (!(o->eps >= 0.0f) || o->max_iter < 0)
+    return fail(c, MPCPCG_EINVAL, "eps must be >= 0 and max_iter >= 0");
+  return MPCPCG_OK;
+}
+
+KArgs base_args(mpcpcg_ctx *c, const mpcpcg_problem *p, const mpcpcg_opts *o) {
+  KArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.Q = p->Q; a.R = p->R; a.A = p->A; a.B = p->B;
+  a.q = p->q; a.r = p->r; a.x0 = p->x0; a.e = p->e;
+  a.tws = c->tws; a.gang = c->gang; a.queue = c->queue;
+  a.qinv_ws = c->qinv_ws; a.rinv_ws = c->rinv_ws;
+  if (o) { a.eps = o->eps; a.max_iter = o->max_iter; a.warm = o->warm_start; }
+  return a;
+}
+
+int single_kpw(mpcpcg_ctx *c, int N) {
+  if (c->kpw_override) return c->kpw_override;
+  return N <= 32 ? 32 : 16;
+}
+
+int launch_single(mpcpcg_ctx *c, KArgs &a, int N, int kpw, int mode, hipStream_t s) {
+  const int g = (N + kpw - 1) / kpw;
+  int cap = 0;
+  int st = capacity(c, kpw, mode, &cap);
+  if (st) return st;
+  if (g > cap)
+    return fail(c, MPCPCG_EINVAL, "horizon N=%d needs %d co-resident workgroups; the device holds %d", N, g, cap);
+  if (g > c->max_tasks) return fail(c, MPCPCG_EINVAL, "N=%d exceeds the context's task workspace", N);
+  a.single.k0 = 0; a.single.N = N; a.single.t0 = 0; a.single.nparts = g; a.single.id = 0;
+  a.probs = nullptr; a.tasks = nullptr; a.ntasks = g; a.persistent = 0;
+  hipLaunchKernelGGL(kernel_for(kpw, mode), dim3(g), dim3(kpw * mpc::kGroup), 0, s, a);
+  HIPCHK(c, hipGetLastError());
+  return MPCPCG_OK;
+}
+
+int validate_batch(mpcpcg_ctx *c, int batch, const int64_t *off, const mpcpcg_problem *p) {
+  if (batch < 1) return fail(c, MPCPCG_EINVAL, "batch must be >= 1");
+  if (batch > c->max_batch) return fail(c, MPCPCG_EINVAL, "batch %d exceeds the context limit %d", batch, c->max_batch);
+  if (!off) return fail(c, MPCPCG_EINVAL, "knot_off is NULL");
+  if (off[0] != 0) return fail(c, MPCPCG_EINVAL, "knot_off[0] must be 0");
+  bool ctrl = false;
+  for (int b = 0; b < batch; ++b) {
+    const int64_t n = off[b + 1] - off[b];
+    if (n < 1) return fail(c, MPCPCG_EINVAL, "problem %d has N=%lld < 1", b, (long long)n);
+    if (n > (int64_t)1 << 30) return fail(c, MPCPCG_EINVAL, "problem %d horizon too long", b);
+    if (n > 1) ctrl = true;
+  }
+  if (off[batch] > c->max_knots)
+    return fail(c, MPCPCG_EINVAL, "total knots %lld exceed the context limit %lld", (long long)off[batch], (long long)c->max_knots);
+  return check_problem_ptrs(c, p, ctrl);
+}
+
+int pick_kpw(mpcpcg_ctx *c, const std::vector<int64_t> &off) {
+  if (c->kpw_override) return c->kpw_override;
+  auto it = c->tuned.find(off);
+  if (it != c->tuned.end()) return it->second;
+  return 16;
+}
+
+int get_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, int kpw, Schedule **out) {
+  auto key = std::make_pair(off, kpw);
+  auto it = c->sched.find(key);
+  if (it != c->sched.end()) { *out = it->second.get(); return MPCPCG_OK; }
+  const int B = (int)off.size() - 1;
+  // longest-processing-time first: every problem runs ~the same number of iterations, so
+  // its work is proportional to N; parts of one problem stay adjacent in the queue so a
+  // gang is always completed by the next free workgroups
+  std::vector<int> order(B);
+  for (int b = 0; b < B; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return off[x + 1] - off[x] > off[y + 1] - off[y];
+  });
+  std::vector<ProbDesc> probs(B);
+  std::vector<Task> tasks;
+  for (int b : order) {
+    ProbDesc d;
+    d.k0 = off[b];
+    d.N = (int32_t)(off[b + 1] - off[b]);
+    d.nparts = (d.N + kpw - 1) / kpw;
+    d.t0 = (int32_t)tasks.size();
+    d.id = b;
+    probs[b] = d;
+    for (int j = 0; j < d.nparts; ++j) tasks.push_back(Task{b, j});
+  }
+  if ((int64_t)tasks.size() > c->max_tasks)
+    return fail(c, MPCPCG_EINVAL, "batch needs %zu workgroup tasks; the context holds %lld", tasks.size(), (long long)c->max_tasks);
+  int cap = 0;
+  int st = capacity(c, kpw, mpc::kForward, &cap);
+  if (st) return st;
+  int capb = 0;
+  st = capacity(c, kpw, mpc::kAdjoint, &capb);
+  if (st) return st;
+  cap = std::min(cap, capb);
+  for (const auto &d : probs)
+    if (d.nparts > cap)
+      return fail(c, MPCPCG_EINVAL, "a horizon of %d knots needs %d co-resident workgroups; the device holds %d", d.N, d.nparts, cap);
+  auto s = std::make_unique<Schedule>();
+  s->off = off;
+  s->kpw = kpw;
+  s->ntasks = (int)tasks.size();
+  s->nprobs = B;
+  HIPCHK(c, hipMalloc(&s->d_probs, sizeof(ProbDesc) * B));
+  HIPCHK(c, hipMalloc(&s->d_tasks, sizeof(Task) * tasks.size()));
+  HIPCHK(c, hipMemcpy(s->d_probs, probs.data(), sizeof(ProbDesc) * B, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(s->d_tasks, tasks.data(), sizeof(Task) * tasks.size(), hipMemcpyHostToDevice));
+  for (int m = 0; m < 3; ++m) s->grid[m] = std::min(s->ntasks, cap);
+  *out = s.get();
+  c->sched.emplace(key, std::move(s));
+  return MPCPCG_OK;
+}
+
+void free_schedule(Schedule *s) {
+  for (int m = 0; m < 3; ++m) {
+    if (s->exec[m]) (void)hipGraphExecDestroy(s->exec[m]);
+    if (s->graph[m]) (void)hipGraphDestroy(s->graph[m]);
+  }
+  if (s->d_probs) (void)hipFree(s->d_probs);
+  if (s->d_tasks) (void)hipFree(s->d_tasks);
+}
+
+int launch_batched(mpcpcg_ctx *c, Schedule *s, KArgs &a, int mode, hipStream_t stream) {
+  a.probs = s->d_probs;
+  a.tasks = s->d_tasks;
+  a.ntasks = s->ntasks;
+  a.persistent = 1;
+  const int grid = s->grid[mode];
+  const dim3 block(s->kpw * mpc::kGroup);
+  if (!c->use_graph) {
+    hipLaunchKernelGGL(kernel_for(s->kpw, mode), dim3(grid), block, 0, stream, a);
+    HIPCHK(c, hipGetLastError());
+    return MPCPCG_OK;
+  }
+  void *params[] = {&s->args[mode]};
+  hipKernelNodeParams kp;
+  std::memset(&kp, 0, sizeof kp);
+  kp.func = reinterpret_cast<void *>(kernel_for(s->kpw, mode));
+  kp.gridDim = dim3(grid);
+  kp.blockDim = block;
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = params;
+  kp.extra = nullptr;
+  if (!s->exec[mode]) {
+    s->args[mode] = a;
+    HIPCHK(c, hipGraphCreate(&s->graph[mode], 0));
+    HIPCHK(c, hipGraphAddKernelNode(&s->node[mode], s->graph[mode], nullptr, 0, &kp));
+    HIPCHK(c, hipGraphInstantiate(&s->exec[mode], s->graph[mode], nullptr, nullptr, 0));
+  } else if (std::memcmp(&s->args[mode], &a, sizeof a) != 0) {
+    s->args[mode] = a;
+    HIPCHK(c, hipGraphExecKernelNodeSetParams(s->exec[mode], s->node[mode], &kp));
+  }
+  HIPCHK(c, hipGraphLaunch(s->exec[mode], stream));
+  return MPCPCG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpcpcg_create(mpcpcg_ctx **out, int32_t nx, int32_t nu, int64_t max_total_knots, int32_t max_batch) {
+  if (!out) return MPCPCG_EINVAL;
+  *out = nullptr;
+  if (nx != kNX || nu != kNU) return MPCPCG_EUNSUPPORTED;
+  if (max_total_knots < 1 || max_batch < 1 || max_batch > max_total_knots) return MPCPCG_EINVAL;
+  auto c = std::make_unique<mpcpcg_ctx>();
+  c->nx = nx;
+  c->nu = nu;
+  c->max_knots = max_total_knots;
+  c->max_batch = max_batch;
+  c->max_tasks = max_total_knots / 4 + max_batch;
+  if (hipGetDevice(&c->device) != hipSuccess) return MPCPCG_EHIP;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return MPCPCG_EHIP;
+  c->cus = prop.multiProcessorCount;
+  const size_t qb = sizeof(double) * (size_t)max_total_knots * nx * nx;
+  const size_t rb = sizeof(double) * (size_t)max_total_knots * nu * (nu + nx);
+  const size_t tb = tws_bytes() * (size_t)c->max_tasks;
+  const size_t gb = sizeof(Gang) * (size_t)max_batch;
+  if (hipMalloc(&c->qinv_ws, qb) != hipSuccess || hipMalloc(&c->rinv_ws, rb) != hipSuccess ||
+      hipMalloc(&c->tws, tb) != hipSuccess || hipMalloc(&c->gang, gb) != hipSuccess ||
+      hipMalloc(&c->queue, 2 * sizeof(int)) != hipSuccess) {
+    mpcpcg_destroy(c.release());
+    return MPCPCG_ENOMEM;
+  }
+  if (hipMemset(c->gang, 0, gb) != hipSuccess || hipMemset(c->queue, 0, 2 * sizeof(int)) != hipSuccess ||
+      hipMemset(c->tws, 0, tb) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    mpcpcg_destroy(c.release());
+    return MPCPCG_EHIP;
+  }
+  *out = c.release();
+  return MPCPCG_OK;
+}
+
+int mpcpcg_destroy(mpcpcg_ctx *c) {
+  if (!c) return MPCPCG_OK;
+  (void)hipDeviceSynchronize();
+  for (auto &kv : c->sched) free_schedule(kv.second.get());
+  if (c->qinv_ws) (void)hipFree(c->qinv_ws);
+  if (c->rinv_ws) (void)hipFree(c->rinv_ws);
+  if (c->tws) (void)hipFree(c->tws);
+  if (c->gang) (void)hipFree(c->gang);
+  if (c->queue) (void)hipFree(c->queue);
+  delete c;
+  return MPCPCG_OK;
+}
+
+const char *mpcpcg_last_error(const mpcpcg_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int mpcpcg_form_schur(mpcpcg_ctx *c, const mpcpcg_problem *p, mpcpcg_schur *out, hipStream_t s) {
+  if (!c) return MPCPCG_EINVAL;
+  if (!p || !out) return fail(c, MPCPCG_EINVAL, "problem and out must be non-NULL");
+  if (p->N < 1) return fail(c, MPCPCG_EINVAL, "N must be >= 1");
+  if (p->N > c->max_knots) return fail(c, MPCPCG_EINVAL, "N exceeds the context limit");
+  int st = check_problem_ptrs(c, p, p->N > 1);
+  if (st) return st;
+  KArgs a = base_args(c, p, nullptr);
+  a.S_out = out->S;
+  a.P_out = out->Pinv;
+  a.gam_out = out->gamma;
+  return launch_single(c, a, p->N, 16, mpc::kForm, s);
+}
+
+int mpcpcg_solve(mpcpcg_ctx *c, const mpcpcg_problem *p, const mpcpcg_opts *o, float *lambda,
+                 float *dx, float *du, mpcpcg_stats *stats, hipStream_t s) {
+  if (!c) return MPCPCG_EINVAL;
+  if (!p) return fail(c, MPCPCG_EINVAL, "problem is NULL");
+  if (p->N < 1) return fail(c, MPCPCG_EINVAL, "N must be >= 1");
+  if (p->N > c->max_knots) return fail(c, MPCPCG_EINVAL, "N exceeds the context limit");
+  int st = check_problem_ptrs(c, p, p->N > 1);
+  if (st) return st;
+  if ((st = check_opts(c, o))) return st;
+  if (!lambda || !dx || !stats || (p->N > 1 && !du))
+    return fail(c, MPCPCG_EINVAL, "lambda, dx, du and stats must be non-NULL");
+  KArgs a = base_args(c, p, o);
+  a.lam = lambda; a.dx = dx; a.du = du; a.stats = stats;
+  return launch_single(c, a, p->N, single_kpw(c, p->N), mpc::kForward, s);
+}
+
+int mpcpcg_solve_batched(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const mpcpcg_problem *p,
+                         const mpcpcg_opts *o, float *lambda, float *dx, float *du,
+                         mpcpcg_stats *stats, hipStream_t s) {
+  if (!c) return MPCPCG_EINVAL;
+  int st = validate_batch(c, batch, off, p);
+  if (st) return st;
+  if ((st = check_opts(c, o))) return st;
+  if (!lambda || !dx || !stats || (off[batch] > batch && !du))
+    return fail(c, MPCPCG_EINVAL, "lambda, dx, du and stats must be non-NULL");
+  std::vector<int64_t> key(off, off + batch + 1);
+  Schedule *sc = nullptr;
+  if ((st = get_schedule(c, key, pick_kpw(c, key), &sc))) return st;
+  KArgs a = base_args(c, p, o);
+  a.lam = lambda; a.dx = dx; a.du = du; a.stats = stats;
+  return launch_batched(c, sc, a, mpc::kForward, s);
+}
+
+int mpcpcg_backward(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const mpcpcg_problem *p,
+                    const mpcpcg_opts *o, const float *lambda, const float *dx, const float *du,
+                    const float *gl, const float *gx, const float *gu, float *dQ, float *dR,
+                    float *dA, float *dB, float *dq, float *dr, float *dx0, float *de,
+                    float *dgamma, mpcpcg_stats *stats, hipStream_t s) {
+  if (!c) return MPCPCG_EINVAL;
+  int st = validate_batch(c, batch, off, p);
+  if (st) return st;
+  if ((st = check_opts(c, o))) return st;
+  const bool ctrl = off[batch] > batch;
+  if (!lambda || !dx || !gl || !dQ || !dq || !dx0 || !stats)
+    return fail(c, MPCPCG_EINVAL, "lambda, dx, dL_dlambda, dQ, dq, dx0 and stats must be non-NULL");
+  if (ctrl && (!du || !dR || !dA || !dB || !dr))
+    return fail(c, MPCPCG_EINVAL, "du, dR, dA, dB and dr must be non-NULL when a horizon exceeds one knot");
+  std::vector<int64_t> key(off, off + batch + 1);
+  Schedule *sc = nullptr;
+  if ((st = get_schedule(c, key, pick_kpw(c, key), &sc))) return st;
+  KArgs a = base_args(c, p, o);
+  a.warm = 0;
+  a.lam_in = lambda; a.dx_in = dx; a.du_in = du;
+  a.gl = gl; a.gx = gx; a.gu = gu;
+  a.dQ = dQ; a.dR = dR; a.dA = dA; a.dB = dB; a.dq = dq; a.dr = dr; a.dx0 = dx0; a.de = de;
+  a.dgamma = dgamma; a.stats = stats;
+  return launch_batched(c, sc, a, mpc::kAdjoint, s);
+}
+
+int mpcpcg_set_knots_per_group(mpcpcg_ctx *c, int32_t k) {
+  if (!c) return MPCPCG_EINVAL;
+  if (k != 0 && !valid_kpw(k)) return fail(c, MPCPCG_EINVAL, "knots per group must be 0, 4, 8, 16 or 32");
+  c->kpw_override = k;
+  return MPCPCG_OK;
+}
+
+int mpcpcg_set_graph(mpcpcg_ctx *c, int32_t enable) {
+  if (!c) return MPCPCG_EINVAL;
+  c->use_graph = enable ? 1 : 0;
+  return MPCPCG_OK;
+}
+
+int mpcpcg_autotune(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const mpcpcg_problem *p,
+                    const mpcpcg_opts *o, float *lambda, float *dx, float *du, mpcpcg_stats *stats,
+                    hipStream_t s, int32_t *kpw_out) {
+  if (!c) return MPCPCG_EINVAL;
+  int st = validate_batch(c, batch, off, p);
+  if (st) return st;
+  if ((st = check_opts(c, o))) return st;
+  if (o->warm_start) return fail(c, MPCPCG_EINVAL, "autotune runs cold solves (warm_start must be 0)");
+  std::vector<int64_t> key(off, off + batch + 1);
+  const int saved = c->kpw_override;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  int best = 0;
+  float best_ms = 0.f;
+  for (int k : kKpwChoices) {
+    c->kpw_override = k;
+    Schedule *sc = nullptr;
+    if (get_schedule(c, key, k, &sc) != MPCPCG_OK) continue;  // shape cannot hold a horizon
+    float ms_min = 0.f;
+    bool okk = true;
+    for (int rep = 0; rep < 4 && okk; ++rep) {
+      HIPCHK(c, hipEventRecord(e0, s));
+      if (mpcpcg_solve_batched(c, batch, off, p, o, lambda, dx, du, stats, s) != MPCPCG_OK) okk = false;
+      HIPCHK(c, hipEventRecord(e1, s));
+      HIPCHK(c, hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+      if (rep > 0 && (ms_min == 0.f || ms < ms_min)) ms_min = ms;
+    }
+    if (okk && (best == 0 || ms_min < best_ms)) { best = k; best_ms = ms_min; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->kpw_override = saved;
+  if (!best) return fail(c, MPCPCG_EINVAL, "no workgroup shape can run this batch");
+  c->tuned[key] = best;
+  if (kpw_out) *kpw_out = best;
+  return MPCPCG_OK;
+}
+
+}  // extern "C"

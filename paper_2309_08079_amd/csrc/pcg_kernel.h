@@ -1,0 +1,748 @@
+// Fused Schur-complement formation + PCG + reconstruction kernel for gfx950.
+//
+// Work decomposition
+//   * One knot (block row b of S) per 16-lane group; lane i owns row i of the block row.
+//   * A workgroup holds KPW consecutive knots ("a part").  A problem of N knots needs
+//     ceil(N / KPW) parts; the parts of one problem form a gang that meets at gang
+//     barriers (global-memory counters) whenever data crosses a part boundary.
+//   * Registers, per lane, for the whole solve: the FP64 row of S (three nx-blocks:
+//     (b,b-1), (b,b), (b,b+1)) and the FP32 row of Phi^-1 (same three blocks), plus the
+//     PCG vectors lambda, r, p and the halo copies of p and r for knots b-1 and b+1.
+//
+// Method (MPCGPU): S, gamma follow Section III-B (theta_k, phi_k, zeta_k; S and gamma
+// negated so S is positive definite), Phi^-1 follows Section IV-A (symmetric stair:
+// D_b^-1 on the diagonal, -D_b^-1 S_{b,b+-1} D_{b+-1}^-1 beside it), the loop follows
+// Algorithm 1 as distributed per block row in Algorithm 2 (two reductions per iteration,
+// halos of neighbouring block rows), and the primal step is dZ = -G^-1 (g - C^T lambda).
+// The stopping rule is sqrt(eta/eta_ref) < eps with eta_ref = gamma^T Phi^-1 gamma.
+//
+// Precision: inputs/outputs FP32; formation, S, the PCG vectors and all reductions in
+// FP64; Phi^-1 stored and applied in FP32 (a preconditioner only changes the Krylov
+// path, not the system being solved).
+#pragma once
+#include "lane_ops.h"
+#include "mpcpcg.h"
+
+namespace mpc {
+
+enum Mode : int { kForm = 0, kForward = 1, kAdjoint = 2 };
+
+struct ProbDesc {
+  int64_t k0;       // first knot row of the problem in the packed arrays
+  int32_t N;        // knots
+  int32_t t0;       // index of the problem's first task (part 0)
+  int32_t nparts;   // ceil(N / KPW)
+  int32_t id;       // problem index b (x0 row, stats slot, control offset k0 - b)
+};
+
+struct Task {
+  int32_t prob;
+  int32_t part;
+};
+
+struct Gang {         // per problem; zero between launches (reset by the last part out)
+  int arrive;
+  int done;
+  int abort;
+  int pad;
+};
+
+template <int NX>
+struct TaskWS {       // per task; read by the neighbouring parts of the same gang
+  double red[2][2];              // [parity][value] partial sums of this part
+  double hv[2][2][2][kGroup];    // [parity][channel][side][lane] double vector halos
+  float hf[2][2][kGroup];        // [parity][side][lane] float vector halos
+  double hm[2][NX][kGroup];      // [side][row][col] matrix halo (one use, in formation)
+};
+
+struct KArgs {
+  // problem data (packed)
+  const float *Q, *R, *A, *B, *q, *r, *x0, *e;
+  // adjoint inputs: saved forward solution and loss gradients
+  const float *lam_in, *dx_in, *du_in, *gl, *gx, *gu;
+  // outputs
+  float *lam, *dx, *du;
+  mpcpcg_stats *stats;
+  float *dQ, *dR, *dA, *dB, *dq, *dr, *dx0, *de, *dgamma;
+  float *S_out, *P_out, *gam_out;
+  // schedule
+  const ProbDesc *probs;
+  const Task *tasks;
+  ProbDesc single;       // used when probs == nullptr (one problem, task = blockIdx.x)
+  int32_t ntasks;
+  int32_t persistent;    // 1: workgroups pop tasks from queue[0]
+  // workspace
+  void *tws;             // TaskWS<NX>[ntasks]
+  Gang *gang;            // [nprobs]
+  int *queue;            // [0] head, [1] workgroups finished
+  double *qinv_ws;       // [knots][NX][NX]   Q_b^-1 rows
+  double *rinv_ws;       // [controls][NU][NU + NX]  R^-1 rows and (R^-1 B^T) rows
+  // options
+  float eps;
+  int32_t max_iter;
+  int32_t warm;
+  int32_t pad;
+};
+
+constexpr long long kSpinLimitTicks = 200000000LL;  // 2 s at the 100 MHz wall clock
+
+// Wave-uniform copies (kept in SGPRs): values every lane of the workgroup shares.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uni(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ int ld_acq(int *p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Register budget: the S row (84 VGPRs) and Phi^-1 row (42) stay resident for the whole
+// solve; 2 waves per SIMD (256 VGPRs) leaves room for the formation's temporaries.
+template <int NX, int NU, int KPW, int MODE>
+__global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_eu(2, 2)))
+    pcg_kernel(const KArgs a) {
+  static_assert(NX == 14 && NU <= NX, "the fused row kernels are written for 14-row blocks");
+  constexpr int NT = KPW * kGroup;
+  constexpr int NW = NT / 64;
+  static_assert(NT % 64 == 0, "whole waves");
+
+  __shared__ double ex_d[2][KPW + 2][kGroup];  // vector exchange, slot s+1 is knot s
+  __shared__ float ex_f[KPW + 2][kGroup];
+  __shared__ double ex_m[KPW + 2][NX][kGroup];  // matrix exchange (formation only)
+  __shared__ double red_w[2][2][NW];           // [phase][value][wave]
+  __shared__ double tot[2];
+  __shared__ int sh_task;
+  __shared__ int sh_abort;
+
+  // Lane indices are re-derived through an opaque copy of threadIdx.x at every phase
+  // boundary (refresh below).  Otherwise the compiler computes every per-lane address of
+  // the formation and epilogue once, up front, and keeps them live through the PCG loop,
+  // which costs the registers the loop needs for S and Phi^-1.
+  int tid = threadIdx.x;
+  int lane = tid & (kGroup - 1);  // row within the knot block
+  int slot = tid >> 4;            // knot slot within the workgroup
+  int wave = tid >> 6;
+  int wl = tid & 63;
+  TaskWS<NX> *tws = reinterpret_cast<TaskWS<NX> *>(a.tws);
+
+  for (int iter_task = 0;; ++iter_task) {
+    // ------------------------------------------------------------- task selection
+    int task;
+    if (a.persistent) {
+      __syncthreads();
+      if (tid == 0) sh_task = atomicAdd(&a.queue[0], 1);
+      __syncthreads();
+      task = uni(sh_task);
+      if (task >= a.ntasks) break;
+    } else {
+      if (iter_task > 0) break;
+      task = blockIdx.x;
+    }
+    const Task tk = a.probs ? a.tasks[task] : Task{0, task};
+    const ProbDesc pd = a.probs ? a.probs[tk.prob] : a.single;
+    const int part = tk.part;
+    const int G = pd.nparts;
+    const bool multi = G > 1;
+    const int N = pd.N;
+    int b;             // knot (block row) of this group
+    bool act, rowv, hasPrev, hasNext;  // knot exists / row < nx / control b-1 / control b
+    int64_t kb, cb;    // packed knot row of knot b, packed control row of control b
+    auto refresh = [&]() {
+      asm volatile("" : "+v"(tid));
+      lane = tid & (kGroup - 1);
+      slot = tid >> 4;
+      wave = tid >> 6;
+      wl = tid & 63;
+      b = part * KPW + slot;
+      act = b < N;
+      rowv = lane < NX;
+      hasPrev = act && b >= 1;
+      hasNext = act && b + 1 < N;
+      kb = pd.k0 + b;
+      cb = pd.k0 - pd.id + b;
+    };
+    refresh();
+    Gang *gang = a.gang + (a.probs ? tk.prob : 0);
+    const int my_t = a.probs ? pd.t0 + part : part;
+    // halo slots 0 and KPW+1 are zero unless a neighbouring part fills them
+    for (int t = tid; t < 2 * kGroup; t += NT) {
+      const int side = t / kGroup, l = t % kGroup;
+      const int s = side ? KPW + 1 : 0;
+      ex_d[0][s][l] = 0.0;
+      ex_d[1][s][l] = 0.0;
+      ex_f[s][l] = 0.0f;
+    }
+    for (int t = tid; t < 2 * NX * kGroup; t += NT) {
+      const int side = t / (NX * kGroup), rem = t % (NX * kGroup);
+      ex_m[side ? KPW + 1 : 0][rem / kGroup][rem % kGroup] = 0.0;
+    }
+    int nsync = 0;   // gang barrier counter (identical sequence in every part)
+    bool aborted = false;
+    if (tid == 0) sh_abort = 0;
+
+    // Synchronisation point shared by every exchange: publishes this part's halos and
+    // partial sums, waits for the gang, fills halo slots 0 / KPW+1 from the neighbours
+    // and leaves totals in tot[].  ND double channels, NF float channel, NM matrix, NR
+    // reduction values (read from red_w[ph]).
+    auto sync_point = [&](int ND, int NF, int NM, int NR, int ph) {
+      __syncthreads();
+      if (multi) {
+        const int par = nsync & 1;
+        if (wave == 0) {
+          if (wl == 0) {
+            double s0 = 0.0, s1 = 0.0;
+            for (int w = 0; w < NW; ++w) {
+              if (NR > 0) s0 += red_w[ph][0][w];
+              if (NR > 1) s1 += red_w[ph][1][w];
+            }
+            __hip_atomic_store(&tws[my_t].red[par][0], s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&tws[my_t].red[par][1], s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_fetch_add(&gang->arrive, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const int target = (nsync + 1) * G;
+            const long long t_start = wall_clock64();
+            int ab = 0;
+            while (ld_acq(&gang->arrive) < target) {
+              if (ld_acq(&gang->abort)) { ab = 1; break; }
+              if (wall_clock64() - t_start > kSpinLimitTicks) {
+                __hip_atomic_store(&gang->abort, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                ab = 1;
+                break;
+              }
+              __builtin_amdgcn_s_sleep(1);
+            }
+            sh_abort = ab;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            // totals: identical summation order in every part
+            double t0 = 0.0, t1 = 0.0;
+            for (int g = 0; g < G; ++g) {
+              t0 += __hip_atomic_load(&tws[pd.t0 + g].red[par][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              t1 += __hip_atomic_load(&tws[pd.t0 + g].red[par][1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            tot[0] = t0;
+            tot[1] = t1;
+          }
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          // halos from the neighbouring parts: lanes 0..15 left, 16..31 right
+          if (wl < 2 * kGroup) {
+            const int side = wl >> 4, l = wl & 15;
+            const int nb = side == 0 ? part - 1 : part + 1;
+            const bool has = nb >= 0 && nb < G;
+            const TaskWS<NX> *src = &tws[my_t + (side == 0 ? -1 : 1)];
+            const int dst = side == 0 ? 0 : KPW + 1;
+            const int srcside = side == 0 ? 1 : 0;  // left neighbour's last knot / right's first
+            for (int c = 0; c < ND; ++c)
+              ex_d[c][dst][l] = has ? __hip_atomic_load(&src->hv[par][c][srcside][l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+            if (NF)
+              ex_f[dst][l] = has ? __hip_atomic_load(&src->hf[par][srcside][l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0f;
+            if (NM)
+              for (int rr = 0; rr < NX; ++rr)
+                ex_m[dst][rr][l] = has ? __hip_atomic_load(&src->hm[srcside][rr][l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+          }
+        }
+        __syncthreads();
+        ++nsync;
+        aborted = uni(sh_abort) != 0;
+      } else {
+        if (tid == 0) {
+          double s0 = 0.0, s1 = 0.0;
+          for (int w = 0; w < NW; ++w) {
+            if (NR > 0) s0 += red_w[ph][0][w];
+            if (NR > 1) s1 += red_w[ph][1][w];
+          }
+          tot[0] = s0;
+          tot[1] = s1;
+        }
+        __syncthreads();
+      }
+    };
+
+    // publish this group's value of a double vector channel (LDS + boundary halo)
+    auto put_d = [&](int c, double v) {
+      ex_d[c][slot + 1][lane] = v;
+      if (multi) {
+        const int par = nsync & 1;
+        if (slot == 0)
+          __hip_atomic_store(&tws[my_t].hv[par][c][0][lane], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (slot == KPW - 1)
+          __hip_atomic_store(&tws[my_t].hv[par][c][1][lane], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    };
+    auto put_f = [&](float v) {
+      ex_f[slot + 1][lane] = v;
+      if (multi) {
+        const int par = nsync & 1;
+        if (slot == 0)
+          __hip_atomic_store(&tws[my_t].hf[par][0][lane], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (slot == KPW - 1)
+          __hip_atomic_store(&tws[my_t].hf[par][1][lane], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    };
+    // per-wave partial of a lane value (deterministic order), written to red_w[ph][v]
+    auto put_red = [&](int ph, int v, double x) {
+      const double g = group_sum_to_last(x);
+      const uint64_t u = __builtin_bit_cast(uint64_t, g);
+      const uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t l2 = __builtin_amdgcn_readlane(lo, 16 * q + 15);
+        const uint32_t h2 = __builtin_amdgcn_readlane(hi, 16 * q + 15);
+        s += __builtin_bit_cast(double, ((uint64_t)h2 << 32) | l2);
+      }
+      if (wl == 0) red_w[ph][v][wave] = s;
+    };
+
+    // ================================================================== formation
+    refresh();
+    // Blocks that do not exist (no previous control at b = 0, no next one at b = N-1,
+    // slots past the end of the horizon) are loaded as zeros, and missing Q blocks as the
+    // identity, so every group runs the same instruction stream.
+
+    double Sm[NX], Sd[NX], Sp[NX];
+    double rhs;  // gamma_b (forward) or the adjoint right-hand side y_b
+    const float *qv = (MODE == kAdjoint) ? a.gx : a.q;
+    const float *rv = (MODE == kAdjoint) ? a.gu : a.r;
+    {
+      // (1) previous-knot terms: T = A_{b-1} Q_{b-1}^-1 -> S_{b,b-1} = -T,
+      //     theta = T A_{b-1}^T + ..., zeta = -T q_{b-1} - ...
+      double Qm[NX], Ar[NX], T[NX];
+#pragma unroll
+      for (int j = 0; j < NX; ++j) { Qm[j] = 0.0; Ar[j] = 0.0; }
+      if (hasPrev && rowv) {
+        const float *pq = a.Q + ((kb - 1) * NX + lane) * NX;
+        const float *pa = a.A + ((cb - 1) * NX + lane) * NX;
+#pragma unroll
+        for (int j = 0; j < NX; ++j) { Qm[j] = (double)pq[j]; Ar[j] = (double)pa[j]; }
+      } else if (rowv) {
+#pragma unroll
+        for (int j = 0; j < NX; ++j) Qm[j] = (j == lane) ? 1.0 : 0.0;
+      }
+      gj_inverse<NX>(Qm, lane);
+      mm_nn<NX, NX>(Ar, Qm, T);
+#pragma unroll
+      for (int j = 0; j < NX; ++j) Sm[j] = -T[j];
+      mm_nt<NX, NX>(T, Ar, Sd);
+      double qprev = 0.0;
+      if (hasPrev && rowv && qv) qprev = (double)qv[(kb - 1) * NX + lane];
+      rhs = -row_dot<NX>(T, qprev);
+    }
+    {
+      // (2) control b-1: R^-1, U = B R^-1, theta += U B^T, zeta -= U r,
+      //     W = R^-1 B^T kept for the primal step
+      double Rr[NX], Br[NX], U[NX], th2[NX], W[NX];
+#pragma unroll
+      for (int j = 0; j < NX; ++j) { Rr[j] = 0.0; Br[j] = 0.0; }
+      if (hasPrev && lane < NU) {
+        const float *pr = a.R + ((cb - 1) * NU + lane) * NU;
+#pragma unroll
+        for (int j = 0; j < NU; ++j) Rr[j] = (double)pr[j];
+      } else if (lane < NU) {
+#pragma unroll
+        for (int j = 0; j < NU; ++j) Rr[j] = (j == lane) ? 1.0 : 0.0;
+      }
+      if (hasPrev && rowv) {
+        const float *pb = a.B + ((cb - 1) * NX + lane) * NU;
+#pragma unroll
+        for (int j = 0; j < NU; ++j) Br[j] = (double)pb[j];
+      }
+      gj_inverse<NU>(Rr, lane);
+      mm_nn<NU, NU>(Br, Rr, U);
+      mm_nt<NU, NX>(U, Br, th2);
+#pragma unroll
+      for (int j = 0; j < NX; ++j) Sd[j] += th2[j];
+      double rprev = 0.0;
+      if (hasPrev && lane < NU && rv) rprev = (double)rv[(cb - 1) * NU + lane];
+      rhs -= row_dot<NU>(U, rprev);
+      mm_nt<NU, NX>(Rr, Br, W);
+      if (MODE != kForm && hasPrev && lane < NU) {
+        double *w = a.rinv_ws + ((cb - 1) * NU + lane) * (NU + NX);
+#pragma unroll
+        for (int j = 0; j < NU; ++j) w[j] = Rr[j];
+#pragma unroll
+        for (int j = 0; j < NX; ++j) w[NU + j] = W[j];
+      }
+    }
+    double Dd[NX];
+    {
+      // (3) own knot: Q_b^-1 enters theta and gamma; (4) S_{b,b+1} = -Q_b^-1 A_b^T
+      double Qi[NX], An[NX], Sx[NX];
+#pragma unroll
+      for (int j = 0; j < NX; ++j) { Qi[j] = 0.0; An[j] = 0.0; }
+      if (act && rowv) {
+        const float *pq = a.Q + (kb * NX + lane) * NX;
+#pragma unroll
+        for (int j = 0; j < NX; ++j) Qi[j] = (double)pq[j];
+      } else if (rowv) {
+#pragma unroll
+        for (int j = 0; j < NX; ++j) Qi[j] = (j == lane) ? 1.0 : 0.0;
+      }
+      // D_0^-1 = Q_0 exactly (the first diagonal block of S is Q_0^-1)
+#pragma unroll
+      for (int j = 0; j < NX; ++j) Dd[j] = Qi[j];
+      gj_inverse<NX>(Qi, lane);
+      if (MODE != kForm && act && rowv) {
+        double *w = a.qinv_ws + (kb * NX + lane) * NX;
+#pragma unroll
+        for (int j = 0; j < NX; ++j) w[j] = Qi[j];
+      }
+#pragma unroll
+      for (int j = 0; j < NX; ++j) Sd[j] += Qi[j];
+      double qb = 0.0, add = 0.0;
+      if (act && rowv) {
+        if (qv) qb = (double)qv[kb * NX + lane];
+        if (MODE == kAdjoint) {
+          add = (double)a.gl[kb * NX + lane];
+        } else if (b == 0) {
+          add = (double)a.x0[(int64_t)pd.id * NX + lane];
+        } else if (a.e) {
+          add = -(double)a.e[(cb - 1) * NX + lane];
+        }
+      }
+      rhs += row_dot<NX>(Qi, qb) + add;
+      if (hasNext && rowv) {
+        const float *pa = a.A + (cb * NX + lane) * NX;
+#pragma unroll
+        for (int j = 0; j < NX; ++j) An[j] = (double)pa[j];
+      }
+      mm_nt<NX, NX>(Qi, An, Sx);
+#pragma unroll
+      for (int j = 0; j < NX; ++j) Sp[j] = -Sx[j];
+    }
+    // (5) D_b^-1 = theta_{b-1}^-1 for b >= 1; D_0^-1 = Q_0 exactly (Dd holds the Q_b row).
+    //     Knot slots past the horizon have S_bb = I, so their D^-1 = I stays finite.
+    {
+      double Dt[NX];
+#pragma unroll
+      for (int j = 0; j < NX; ++j) Dt[j] = Sd[j];
+      gj_inverse<NX>(Dt, lane);
+      const bool keepQ0 = act && b == 0;
+#pragma unroll
+      for (int j = 0; j < NX; ++j) Dd[j] = keepQ0 ? Dd[j] : Dt[j];
+    }
+    // (6) exchange D^-1 rows with the neighbouring knots (the one cross-knot dependency of
+    //     the formation: "only theta_k^-1 needs to be shared")
+    if (rowv) {
+#pragma unroll
+      for (int j = 0; j < NX; ++j) ex_m[slot + 1][lane][j] = Dd[j];
+    }
+    if (multi && rowv) {
+      if (slot == 0)
+        for (int j = 0; j < NX; ++j)
+          __hip_atomic_store(&tws[my_t].hm[0][lane][j], Dd[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (slot == KPW - 1)
+        for (int j = 0; j < NX; ++j)
+          __hip_atomic_store(&tws[my_t].hm[1][lane][j], Dd[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (multi && rowv && (slot == 0 || slot == KPW - 1)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    sync_point(0, 0, 1, 0, 0);
+    // (7) Phi^-1_{b,b-1} = -D_b^-1 S_{b,b-1} D_{b-1}^-1, Phi^-1_{b,b+1} likewise
+    float Pm[NX], Pd[NX], Pp[NX];
+    {
+      double X[NX];
+      mm_nn<NX, NX>(Dd, Sm, X);
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < NX; ++m) s = __builtin_fma(X[m], ex_m[slot][m][j], s);
+        Pm[j] = (float)(-s);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      mm_nn<NX, NX>(Dd, Sp, X);
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < NX; ++m) s = __builtin_fma(X[m], ex_m[slot + 2][m][j], s);
+        Pp[j] = (float)(-s);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int j = 0; j < NX; ++j) Pd[j] = (float)Dd[j];
+    }
+    if (!rowv) {
+#pragma unroll
+      for (int j = 0; j < NX; ++j) { Sm[j] = 0.0; Sd[j] = 0.0; Sp[j] = 0.0; Pm[j] = 0.f; Pd[j] = 0.f; Pp[j] = 0.f; }
+      rhs = 0.0;
+    }
+
+    if constexpr (MODE == kForm) {
+      if (act && rowv) {
+        const int64_t o = kb * 3 * NX * NX + (int64_t)lane * NX;
+        if (a.S_out)
+          for (int j = 0; j < NX; ++j) {
+            a.S_out[o + j] = (float)Sm[j];
+            a.S_out[o + NX * NX + j] = (float)Sd[j];
+            a.S_out[o + 2 * NX * NX + j] = (float)Sp[j];
+          }
+        if (a.P_out)
+          for (int j = 0; j < NX; ++j) {
+            a.P_out[o + j] = Pm[j];
+            a.P_out[o + NX * NX + j] = Pd[j];
+            a.P_out[o + 2 * NX * NX + j] = Pp[j];
+          }
+        if (a.gam_out) a.gam_out[kb * NX + lane] = (float)rhs;
+      }
+    } else {
+      // ================================================================== PCG
+      refresh();
+      const int max_iter = a.max_iter > 0 ? a.max_iter : N * NX;
+      double lam = 0.0, r = rhs, p, pm, pp, rm, rp;
+      // eta_ref = rhs^T Phi^-1 rhs
+      put_d(0, rhs);
+      if (MODE == kForward && a.warm && act && rowv) lam = (double)a.lam[kb * NX + lane];
+      put_d(1, lam);
+      if (multi && (slot == 0 || slot == KPW - 1)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      sync_point(2, 0, 0, 0, 0);
+      const double gm = ex_d[0][slot][lane], gp = ex_d[0][slot + 2][lane];
+      float gt = 0.f;
+      {
+        float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
+        row_fma14_f32(acc0, (float)gm, Pm);
+        row_fma14_f32(acc1, (float)rhs, Pd);
+        row_fma14_f32(acc2, (float)gp, Pp);
+        gt = (acc0 + acc1) + acc2;
+      }
+      const bool warm = (MODE == kForward) && a.warm;
+      rm = gm;
+      rp = gp;
+      if (warm) {
+        // r = gamma - S lambda_0
+        const double lm = ex_d[1][slot][lane], lp = ex_d[1][slot + 2][lane];
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        row_fma14_f64(a0, lm, Sm);
+        row_fma14_f64(a1, lam, Sd);
+        row_fma14_f64(a2, lp, Sp);
+        r = rhs - ((a0 + a1) + a2);
+        put_d(0, r);
+        if (multi && (slot == 0 || slot == KPW - 1)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        sync_point(1, 0, 0, 0, 1);
+        rm = ex_d[0][slot][lane];
+        rp = ex_d[0][slot + 2][lane];
+      }
+      float rt;
+      if (warm) {
+        float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
+        row_fma14_f32(acc0, (float)rm, Pm);
+        row_fma14_f32(acc1, (float)r, Pd);
+        row_fma14_f32(acc2, (float)rp, Pp);
+        rt = (acc0 + acc1) + acc2;
+      } else {
+        rt = gt;
+      }
+      // eta_0 = r^T r~ and eta_ref = rhs^T Phi^-1 rhs; p = r~ (halo via the float channel)
+      put_red(0, 0, r * (double)rt);
+      put_red(0, 1, rhs * (double)gt);
+      put_f(rt);
+      if (multi && (slot == 0 || slot == KPW - 1)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      sync_point(0, 1, 0, 2, 0);
+      double eta = uni(tot[0]);
+      const double eta_ref = uni(tot[1]);
+      const double tau = (double)a.eps * (double)a.eps * eta_ref;
+      p = (double)rt;
+      pm = (double)ex_f[slot][lane];
+      pp = (double)ex_f[slot + 2][lane];
+      int status = MPCPCG_NOT_CONVERGED;
+      int it = 0;
+      double eta_new = eta;
+      if (!(eta == eta) || !(eta_ref == eta_ref) || __builtin_isinf(eta) || __builtin_isinf(eta_ref)) {
+        status = MPCPCG_BREAKDOWN;
+      } else if (eta <= tau) {
+        status = MPCPCG_OK;
+      } else {
+        for (it = 1; it <= max_iter && !aborted; ++it) {
+          // ---- phase A: Y = S p, upsilon = p^T Y
+          double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+          row_fma14_f64(a0, pm, Sm);
+          row_fma14_f64(a1, p, Sd);
+          row_fma14_f64(a2, pp, Sp);
+          const double Y = (a0 + a1) + a2;
+          put_red(0, 0, p * Y);
+          put_d(0, Y);
+          if (multi && (slot == 0 || slot == KPW - 1)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          sync_point(1, 0, 0, 1, 0);
+          const double ups = uni(tot[0]);
+          if (!(ups > 0.0) || __builtin_isinf(ups)) {
+            status = MPCPCG_BREAKDOWN;
+            break;
+          }
+          const double alpha = eta / ups;
+          const double Ym = ex_d[0][slot][lane], Yp = ex_d[0][slot + 2][lane];
+          lam = __builtin_fma(alpha, p, lam);
+          r = __builtin_fma(-alpha, Y, r);
+          rm = __builtin_fma(-alpha, Ym, rm);
+          rp = __builtin_fma(-alpha, Yp, rp);
+          // ---- phase B: r~ = Phi^-1 r, eta' = r^T r~
+          float c0 = 0.f, c1 = 0.f, c2 = 0.f;
+          row_fma14_f32(c0, (float)rm, Pm);
+          row_fma14_f32(c1, (float)r, Pd);
+          row_fma14_f32(c2, (float)rp, Pp);
+          const float rtn = (c0 + c1) + c2;
+          put_red(1, 0, r * (double)rtn);
+          put_f(rtn);
+          if (multi && (slot == 0 || slot == KPW - 1)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+          sync_point(0, 1, 0, 1, 1);
+          eta_new = uni(tot[0]);
+          if (!(eta_new == eta_new) || __builtin_isinf(eta_new)) {
+            status = MPCPCG_BREAKDOWN;
+            break;
+          }
+          if (eta_new < tau) {
+            status = MPCPCG_OK;
+            break;
+          }
+          // ---- phase C: p = r~ + beta p (own knot and both halo copies)
+          const double beta = eta_new / eta;
+          p = __builtin_fma(beta, p, (double)rtn);
+          pm = __builtin_fma(beta, pm, (double)ex_f[slot][lane]);
+          pp = __builtin_fma(beta, pp, (double)ex_f[slot + 2][lane]);
+          eta = eta_new;
+        }
+        if (it > max_iter) it = max_iter;
+      }
+      if (aborted) status = MPCPCG_TIMEOUT;
+      if (!rowv || !act) lam = 0.0;
+
+      // ================================================================== epilogue
+      refresh();
+      // primal step dZ = -G^-1 (g - C^T lambda) (with mu and the loss gradients in the
+      // adjoint): x rows use Q_b^-1 and S_{b,b+1} = -Q_b^-1 A_b^T; u rows of control b-1
+      // use R_{b-1}^-1 and W = R_{b-1}^-1 B_{b-1}^T (both written during formation).
+      put_d(0, lam);
+      if (multi && (slot == 0 || slot == KPW - 1)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      sync_point(1, 0, 0, 0, 0);
+      const double lp = ex_d[0][slot + 2][lane];
+      double qmin = 0.0;   // q_b - lambda_b  (or gx_b - mu_b)
+      if (act && rowv) {
+        const double qb = qv ? (double)qv[kb * NX + lane] : 0.0;
+        qmin = qb - lam;
+      }
+      double Qi[NX];
+#pragma unroll
+      for (int j = 0; j < NX; ++j) Qi[j] = 0.0;
+      if (act && rowv) {
+        const double *w = a.qinv_ws + (kb * NX + lane) * NX;
+#pragma unroll
+        for (int j = 0; j < NX; ++j) Qi[j] = w[j];
+      }
+      const double xrow = -row_dot<NX>(Qi, qmin) + row_dot<NX>(Sp, lp);
+      double Rr[NX], W[NX];
+#pragma unroll
+      for (int j = 0; j < NX; ++j) { Rr[j] = 0.0; W[j] = 0.0; }
+      double rprev = 0.0;
+      if (hasPrev && lane < NU) {
+        const double *w = a.rinv_ws + ((cb - 1) * NU + lane) * (NU + NX);
+#pragma unroll
+        for (int j = 0; j < NU; ++j) Rr[j] = w[j];
+#pragma unroll
+        for (int j = 0; j < NX; ++j) W[j] = w[NU + j];
+        if (rv) rprev = (double)rv[(cb - 1) * NU + lane];
+      }
+      const double urow = -row_dot<NU>(Rr, rprev) - row_dot<NX>(W, lam);
+      if constexpr (MODE == kForward) {
+        if (act && rowv) {
+          a.lam[kb * NX + lane] = (float)lam;
+          a.dx[kb * NX + lane] = (float)xrow;
+        }
+        if (hasPrev && lane < NU) a.du[(cb - 1) * NU + lane] = (float)urow;
+      } else {
+        // adjoint: lam holds mu, xrow = nu1x_b, urow = nu1u_{b-1}
+        const double mu = lam, n1x = xrow, n1u = urow;
+        put_d(0, n1x);
+        if (multi && (slot == 0 || slot == KPW - 1)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        sync_point(1, 0, 0, 0, 1);
+        const double n1xm = ex_d[0][slot][lane];  // nu1x_{b-1}
+        double dxb = 0.0, dxm = 0.0, lb = 0.0, dum = 0.0;
+        if (act && rowv) {
+          dxb = (double)a.dx_in[kb * NX + lane];
+          lb = (double)a.lam_in[kb * NX + lane];
+        }
+        if (hasPrev && rowv) dxm = (double)a.dx_in[(kb - 1) * NX + lane];
+        if (hasPrev && lane < NU) dum = (double)a.du_in[(cb - 1) * NU + lane];
+        // dQ_b = sym(nu1x_b dx_b^T); row i = (nu1x_i dx^T + dx_i nu1x^T) / 2
+        double dQrow[NX], tmp[NX];
+        outer_row<NX>(dQrow, dxb, 0.5 * n1x);
+        outer_row<NX>(tmp, n1x, 0.5 * dxb);
+#pragma unroll
+        for (int j = 0; j < NX; ++j) dQrow[j] += tmp[j];
+        if (act && rowv) {
+          float *dq = a.dQ + (kb * NX + lane) * NX;
+#pragma unroll
+          for (int j = 0; j < NX; ++j) dq[j] = (float)dQrow[j];
+          a.dq[kb * NX + lane] = (float)n1x;
+          if (a.dgamma) a.dgamma[kb * NX + lane] = (float)mu;
+          if (b == 0) a.dx0[(int64_t)pd.id * NX + lane] = (float)mu;
+        }
+        // control b-1 (owned by this group): dA, dB, dR, dr, de
+        double dArow[NX], dBrow[NX], dRrow[NX];
+        outer_row<NX>(dArow, n1xm, lb);
+        outer_row<NX>(tmp, dxm, mu);
+#pragma unroll
+        for (int j = 0; j < NX; ++j) dArow[j] += tmp[j];
+        outer_row<NU>(dBrow, n1u, lb);
+        outer_row<NU>(tmp, dum, mu);
+#pragma unroll
+        for (int j = 0; j < NU; ++j) dBrow[j] += tmp[j];
+        outer_row<NU>(dRrow, dum, 0.5 * n1u);
+        outer_row<NU>(tmp, n1u, 0.5 * dum);
+#pragma unroll
+        for (int j = 0; j < NU; ++j) dRrow[j] += tmp[j];
+        if (hasPrev && rowv) {
+          float *pa = a.dA + ((cb - 1) * NX + lane) * NX;
+#pragma unroll
+          for (int j = 0; j < NX; ++j) pa[j] = (float)dArow[j];
+          float *pb = a.dB + ((cb - 1) * NX + lane) * NU;
+#pragma unroll
+          for (int j = 0; j < NU; ++j) pb[j] = (float)dBrow[j];
+          if (a.de) a.de[(cb - 1) * NX + lane] = (float)(-mu);
+        }
+        if (hasPrev && lane < NU) {
+          float *pr = a.dR + ((cb - 1) * NU + lane) * NU;
+#pragma unroll
+          for (int j = 0; j < NU; ++j) pr[j] = (float)dRrow[j];
+          a.dr[(cb - 1) * NU + lane] = (float)n1u;
+        }
+      }
+      if (tid == 0 && part == 0) {
+        mpcpcg_stats st;
+        st.iters = it;
+        st.status = status;
+        st.final_ratio = eta_ref > 0.0 ? (float)__builtin_sqrt(eta_new > 0.0 ? eta_new / eta_ref : 0.0) : 0.0f;
+        st.reserved = 0;
+        a.stats[pd.id] = st;
+      }
+    }
+
+    // ------------------------------------------------------------- gang teardown
+    if (multi) {
+      __syncthreads();
+      if (tid == 0) {
+        const int d = __hip_atomic_fetch_add(&gang->done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (d == G - 1) {
+          __hip_atomic_store(&gang->arrive, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&gang->abort, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&gang->done, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+    }
+  }
+
+  // ------------------------------------------------------------- queue teardown
+  if (a.persistent) {
+    __syncthreads();
+    if (tid == 0) {
+      const int d = __hip_atomic_fetch_add(&a.queue[1], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (d == (int)gridDim.x - 1) {
+        __hip_atomic_store(&a.queue[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&a.queue[1], 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+}
+
+}  // namespace mpc

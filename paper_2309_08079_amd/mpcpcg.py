@@ -1,0 +1,263 @@
+"""Thin ctypes binding of libmpcpcg (argument marshalling only).
+
+Every entry point of include/mpcpcg.h has a method of the same name on ``Context``.
+Arrays are torch tensors on the current HIP device (float32, contiguous); they are passed
+as raw device pointers together with the current torch stream.  There is no CPU path:
+if the library is missing the import of this module fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+OK, NOT_CONVERGED, BREAKDOWN, TIMEOUT = 0, 1, 2, 3
+EINVAL, EUNSUPPORTED, ENOMEM, EHIP = -1, -2, -3, -4
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmpcpcg.so")
+_lib = None
+
+
+class MPCPCGError(RuntimeError):
+    pass
+
+
+class Problem(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("nu", C.c_int32), ("N", C.c_int32)] + [
+        (k, C.c_void_p) for k in ("Q", "R", "A", "B", "q", "r", "x0", "e")]
+
+
+class Opts(C.Structure):
+    _fields_ = [("eps", C.c_float), ("max_iter", C.c_int32), ("warm_start", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class Schur(C.Structure):
+    _fields_ = [("S", C.c_void_p), ("Pinv", C.c_void_p), ("gamma", C.c_void_p)]
+
+
+STATS_DTYPE = np.dtype([("iters", np.int32), ("status", np.int32), ("final_ratio", np.float32),
+                        ("reserved", np.int32)])
+
+
+def load_library(path: str = _LIB_PATH):
+    """Load libmpcpcg.so (built by ``paper_2309_08079_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise MPCPCGError("libmpcpcg.so not found at %s; build it with "
+                          "`python -m paper_2309_08079_amd.build`" % path)
+    lib = C.CDLL(path)
+    vp, i32, i64p = C.c_void_p, C.c_int32, C.POINTER(C.c_int64)
+    P, O = C.POINTER(Problem), C.POINTER(Opts)
+    lib.mpcpcg_create.argtypes = [C.POINTER(vp), i32, i32, C.c_int64, i32]
+    lib.mpcpcg_destroy.argtypes = [vp]
+    lib.mpcpcg_last_error.argtypes = [vp]
+    lib.mpcpcg_last_error.restype = C.c_char_p
+    lib.mpcpcg_form_schur.argtypes = [vp, P, C.POINTER(Schur), vp]
+    lib.mpcpcg_solve.argtypes = [vp, P, O, vp, vp, vp, vp, vp]
+    lib.mpcpcg_solve_batched.argtypes = [vp, i32, i64p, P, O, vp, vp, vp, vp, vp]
+    lib.mpcpcg_backward.argtypes = [vp, i32, i64p, P, O] + [vp] * 6 + [vp] * 9 + [vp, vp]
+    lib.mpcpcg_set_knots_per_group.argtypes = [vp, i32]
+    lib.mpcpcg_set_graph.argtypes = [vp, i32]
+    lib.mpcpcg_autotune.argtypes = [vp, i32, i64p, P, O, vp, vp, vp, vp, vp, C.POINTER(i32)]
+    for f in ("mpcpcg_create", "mpcpcg_destroy", "mpcpcg_form_schur", "mpcpcg_solve",
+              "mpcpcg_solve_batched", "mpcpcg_backward", "mpcpcg_set_knots_per_group",
+              "mpcpcg_set_graph", "mpcpcg_autotune"):
+        getattr(lib, f).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise MPCPCGError("expected a contiguous float32 device tensor")
+    return t.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _problem(d, nx, nu, N=0):
+    p = Problem()
+    p.nx, p.nu, p.N = nx, nu, N
+    for k in ("Q", "R", "A", "B", "q", "r", "x0", "e"):
+        t = d.get(k)
+        setattr(p, k, None if t is None or t.numel() == 0 else _ptr(t))
+    if p.Q is None or p.q is None or p.x0 is None:
+        raise MPCPCGError("Q, q and x0 are required")
+    return p
+
+
+def _opts(eps, max_iter, warm):
+    o = Opts()
+    o.eps, o.max_iter, o.warm_start, o.reserved = float(eps), int(max_iter), int(bool(warm)), 0
+    return o
+
+
+def stats_to_numpy(t):
+    """View a device stats tensor (int32 [batch, 4]) as a structured numpy array."""
+    return t.cpu().numpy().view(STATS_DTYPE).reshape(-1)
+
+
+class Context:
+    """Owns an mpcpcg_ctx on the current device."""
+
+    def __init__(self, nx=14, nu=7, max_total_knots=1 << 17, max_batch=4096):
+        self.lib = load_library()
+        self.nx, self.nu = nx, nu
+        h = C.c_void_p()
+        st = self.lib.mpcpcg_create(C.byref(h), nx, nu, int(max_total_knots), int(max_batch))
+        if st != OK:
+            raise MPCPCGError("mpcpcg_create failed with %d" % st)
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mpcpcg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st != OK:
+            msg = self.lib.mpcpcg_last_error(self.h).decode()
+            raise MPCPCGError("%s failed (%d): %s" % (what, st, msg))
+
+    # ---- entry points ------------------------------------------------------------------
+    def mpcpcg_form_schur(self, prob):
+        N = prob["q"].shape[0]
+        dev = prob["q"].device
+        S = torch.zeros((N, 3, self.nx, self.nx), device=dev)
+        P = torch.zeros_like(S)
+        g = torch.zeros((N, self.nx), device=dev)
+        out = Schur(S.data_ptr(), P.data_ptr(), g.data_ptr())
+        self._check(self.lib.mpcpcg_form_schur(self.h, C.byref(_problem(prob, self.nx, self.nu, N)),
+                                               C.byref(out), _stream()), "mpcpcg_form_schur")
+        return S, P, g
+
+    def mpcpcg_solve(self, prob, eps=1e-6, max_iter=0, lam0=None, out=None):
+        N = prob["q"].shape[0]
+        dev = prob["q"].device
+        o = out or {}
+        lam = o.get("lam", torch.empty((N, self.nx), device=dev))
+        if lam0 is not None:
+            lam.copy_(lam0)
+        dx = o.get("dx", torch.empty((N, self.nx), device=dev))
+        du = o.get("du", torch.empty((max(N - 1, 0), self.nu), device=dev))
+        stats = o.get("stats", torch.zeros((1, 4), dtype=torch.int32, device=dev))
+        self._check(self.lib.mpcpcg_solve(
+            self.h, C.byref(_problem(prob, self.nx, self.nu, N)), C.byref(_opts(eps, max_iter, lam0 is not None)),
+            _ptr(lam), _ptr(dx), _ptr(du) if du.numel() else None, stats.data_ptr(), _stream()),
+            "mpcpcg_solve")
+        return dict(lam=lam, dx=dx, du=du, stats=stats)
+
+    def mpcpcg_solve_batched(self, packed, knot_off, eps=1e-6, max_iter=0, lam0=None, out=None):
+        off = np.ascontiguousarray(knot_off, dtype=np.int64)
+        B = len(off) - 1
+        K = int(off[-1])
+        dev = packed["q"].device
+        o = out or {}
+        lam = o.get("lam", torch.empty((K, self.nx), device=dev))
+        if lam0 is not None:
+            lam.copy_(lam0)
+        dx = o.get("dx", torch.empty((K, self.nx), device=dev))
+        du = o.get("du", torch.empty((max(K - B, 0), self.nu), device=dev))
+        stats = o.get("stats", torch.zeros((B, 4), dtype=torch.int32, device=dev))
+        self._check(self.lib.mpcpcg_solve_batched(
+            self.h, B, off.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(_problem(packed, self.nx, self.nu)),
+            C.byref(_opts(eps, max_iter, lam0 is not None)), _ptr(lam), _ptr(dx),
+            _ptr(du) if du.numel() else None, stats.data_ptr(), _stream()), "mpcpcg_solve_batched")
+        return dict(lam=lam, dx=dx, du=du, stats=stats)
+
+    def mpcpcg_backward(self, packed, knot_off, fwd, gl, gx=None, gu=None, eps=1e-6, max_iter=0,
+                        out=None):
+        off = np.ascontiguousarray(knot_off, dtype=np.int64)
+        B = len(off) - 1
+        K = int(off[-1])
+        M = K - B
+        dev = packed["q"].device
+        nx, nu = self.nx, self.nu
+        o = out or {}
+        z = lambda key, shape: o.get(key, torch.empty(shape, device=dev))
+        g = dict(dQ=z("dQ", (K, nx, nx)), dR=z("dR", (M, nu, nu)), dA=z("dA", (M, nx, nx)),
+                 dB=z("dB", (M, nx, nu)), dq=z("dq", (K, nx)), dr=z("dr", (M, nu)),
+                 dx0=z("dx0", (B, nx)), de=z("de", (M, nx)), dgamma=z("dgamma", (K, nx)))
+        stats = o.get("stats", torch.zeros((B, 4), dtype=torch.int32, device=dev))
+        opt = lambda t: _ptr(t) if t is not None and t.numel() else None
+        self._check(self.lib.mpcpcg_backward(
+            self.h, B, off.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(_problem(packed, nx, nu)),
+            C.byref(_opts(eps, max_iter, False)), _ptr(fwd["lam"]), _ptr(fwd["dx"]), opt(fwd["du"]),
+            _ptr(gl), opt(gx), opt(gu),
+            *[opt(g[k]) for k in ("dQ", "dR", "dA", "dB", "dq", "dr", "dx0", "de", "dgamma")],
+            stats.data_ptr(), _stream()), "mpcpcg_backward")
+        g["stats"] = stats
+        return g
+
+    def mpcpcg_set_knots_per_group(self, k):
+        self._check(self.lib.mpcpcg_set_knots_per_group(self.h, int(k)), "mpcpcg_set_knots_per_group")
+
+    def mpcpcg_set_graph(self, enable):
+        self._check(self.lib.mpcpcg_set_graph(self.h, int(bool(enable))), "mpcpcg_set_graph")
+
+    def mpcpcg_autotune(self, packed, knot_off, eps=1e-6, max_iter=0):
+        off = np.ascontiguousarray(knot_off, dtype=np.int64)
+        B = len(off) - 1
+        K = int(off[-1])
+        dev = packed["q"].device
+        lam = torch.empty((K, self.nx), device=dev)
+        dx = torch.empty((K, self.nx), device=dev)
+        du = torch.empty((max(K - B, 1), self.nu), device=dev)
+        stats = torch.zeros((B, 4), dtype=torch.int32, device=dev)
+        k = C.c_int32(0)
+        self._check(self.lib.mpcpcg_autotune(
+            self.h, B, off.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(_problem(packed, self.nx, self.nu)),
+            C.byref(_opts(eps, max_iter, False)), _ptr(lam), _ptr(dx), _ptr(du), stats.data_ptr(),
+            _stream(), C.byref(k)), "mpcpcg_autotune")
+        return k.value
+
+
+def to_device(d, device="cuda"):
+    """numpy dict (from synth) -> dict of contiguous float32 device tensors."""
+    return {k: torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32)).to(device) for k, v in d.items()}
+
+
+class MPCPCGFunction(torch.autograd.Function):
+    """lambda, dx, du = MPCPCGFunction.apply(ctx, knot_off, eps, Q, R, A, B, q, r, x0, e).
+
+    Forward: mpcpcg_solve_batched.  Backward: mpcpcg_backward (adjoint PCG with the same
+    stopping rule); returns gradients for Q, R, A, B, q, r, x0, e (symmetric part for Q, R).
+    """
+
+    @staticmethod
+    def forward(fctx, mctx, knot_off, eps, Q, R, A, B, q, r, x0, e):
+        packed = dict(Q=Q.contiguous(), R=R.contiguous(), A=A.contiguous(), B=B.contiguous(),
+                      q=q.contiguous(), r=r.contiguous(), x0=x0.contiguous(),
+                      e=None if e is None else e.contiguous())
+        out = mctx.mpcpcg_solve_batched(packed, knot_off, eps=eps)
+        fctx.mctx, fctx.off, fctx.eps = mctx, np.asarray(knot_off, dtype=np.int64), eps
+        fctx.packed = packed
+        fctx.save_for_backward(out["lam"], out["dx"], out["du"])
+        fctx.has_e = e is not None
+        fctx.stats = out["stats"]
+        return out["lam"], out["dx"], out["du"]
+
+    @staticmethod
+    def backward(fctx, glam, gdx, gdu):
+        lam, dx, du = fctx.saved_tensors
+        zero_like = lambda t, ref: torch.zeros_like(ref) if t is None else t.contiguous()
+        g = fctx.mctx.mpcpcg_backward(fctx.packed, fctx.off, dict(lam=lam, dx=dx, du=du),
+                                      zero_like(glam, lam), None if gdx is None else gdx.contiguous(),
+                                      None if gdu is None else gdu.contiguous(), eps=fctx.eps)
+        return (None, None, None, g["dQ"], g["dR"], g["dA"], g["dB"], g["dq"], g["dr"], g["dx0"],
+                g["de"] if fctx.has_e else None)

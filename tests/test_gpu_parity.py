@@ -1,0 +1,328 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, element by element.
+
+Tolerances (norm-wise relative error per problem, FP32 outputs):
+  * lambda, dx, du vs the oracle's PCG iterate at the same eps (O2): 1e-5 (the bar); the
+    GPU keeps S and the PCG vectors in FP64, so the measured gap is ~1e-9.
+  * lambda vs the exact KKT solution (O1): 1e-5 at eps = 1e-6.
+  * S, gamma (FP32 outputs of FP64 formation) vs the oracle: 2e-7 relative per block row,
+    Phi^-1: 1e-6 relative.
+  * iteration counts equal those of the oracle's PCG within 1 (the last step decides a
+    strict inequality on a value both sides compute to ~1e-12 relative).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import kkt
+from oracle import ref as orc
+from paper_2309_08079_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+EPS = 1e-6
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_08079_amd.mpcpcg import Context
+    c = Context(14, 7, max_total_knots=1 << 17, max_batch=1024)
+    yield c
+    c.close()
+
+
+def dev(p):
+    from paper_2309_08079_amd.mpcpcg import to_device
+    return to_device(p)
+
+
+def stats(t):
+    from paper_2309_08079_amd.mpcpcg import stats_to_numpy
+    return stats_to_numpy(t)
+
+
+@pytest.mark.parametrize("N", [1, 2, 17, 32, 33, 70])
+def test_form_schur_matches_oracle(ctx, N):
+    p = synth.problem(N, seed=1 if N == 32 else 50 + N)
+    S, P, g = ctx.mpcpcg_form_schur(dev(p))
+    torch.cuda.synchronize()
+    So, Po, go = orc.form(p)
+    S, P, g = S.cpu().numpy(), P.cpu().numpy(), g.cpu().numpy()
+    for b in range(N):
+        assert rel(S[b], So[b]) < 2e-7, ("S", b)
+        assert rel(P[b], Po[b]) < 1e-6, ("Phi^-1", b)
+        assert rel(g[b], go[b]) < 2e-7, ("gamma", b)
+
+
+def check_solution(out, p, ref_pcg, tol=1e-5, it_tol=1):
+    lam = out["lam"].cpu().numpy()
+    dx = out["dx"].cpu().numpy()
+    du = out["du"].cpu().numpy()
+    st = stats(out["stats"])[0]
+    assert st["status"] == ref_pcg["status"]
+    assert abs(int(st["iters"]) - ref_pcg["iters"]) <= it_tol
+    assert rel(lam, ref_pcg["lam"]) < tol
+    assert rel(dx, ref_pcg["dx"]) < tol
+    if du.size:
+        assert rel(du, ref_pcg["du"]) < tol
+    return lam, dx, du, st
+
+
+def test_solve_single_problem_matches_kkt_and_oracle_pcg(ctx):
+    # 14-state / 7-control problem, N = 32 knots, seed 1 (the small oracle-sized case)
+    p = synth.problem(32, seed=1)
+    out = ctx.mpcpcg_solve(dev(p), eps=EPS)
+    torch.cuda.synchronize()
+    o2 = orc.solve(p, eps=EPS)
+    lam, dx, du, st = check_solution(out, p, o2)
+    o1 = kkt.kkt_solve(p)
+    assert rel(lam, o1["lam"]) < 1e-5
+    assert rel(np.concatenate([dx.ravel(), du.ravel()]),
+               np.concatenate([o1["dx"].ravel(), o1["du"].ravel()])) < 1e-5
+    assert st["final_ratio"] < EPS
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 15, 16, 17, 31, 33, 64, 100, 128, 256, 512])
+@pytest.mark.parametrize("kpw", [0, 4, 16])
+def test_solve_horizons_and_shapes(ctx, N, kpw):
+    ctx.mpcpcg_set_knots_per_group(kpw)
+    try:
+        p = synth.problem(N, seed=2000 + N)
+        out = ctx.mpcpcg_solve(dev(p), eps=EPS)
+        torch.cuda.synchronize()
+    finally:
+        ctx.mpcpcg_set_knots_per_group(0)
+    check_solution(out, p, orc.solve(p, eps=EPS))
+
+
+def test_solve_with_defects(ctx):
+    p = synth.problem(40, seed=77, defects=True)
+    out = ctx.mpcpcg_solve(dev(p), eps=EPS)
+    torch.cuda.synchronize()
+    check_solution(out, p, orc.solve(p, eps=EPS))
+
+
+def test_warm_start(ctx):
+    p = synth.problem(48, seed=9)
+    ex = kkt.kkt_solve(p)
+    lam0 = torch.from_numpy(ex["lam"].astype(np.float32)).cuda()
+    out = ctx.mpcpcg_solve(dev(p), eps=EPS, lam0=lam0)
+    torch.cuda.synchronize()
+    o2 = orc.solve(p, eps=EPS, lam0=ex["lam"].astype(np.float32).astype(np.float64))
+    st = stats(out["stats"])[0]
+    assert st["iters"] == o2["iters"] and st["status"] == 0
+    assert rel(out["lam"].cpu().numpy(), o2["lam"]) < 1e-5
+    # a perturbed start converges to the same iterate rule
+    lam0 = torch.from_numpy((ex["lam"] + 0.1).astype(np.float32)).cuda()
+    out = ctx.mpcpcg_solve(dev(p), eps=EPS, lam0=lam0)
+    torch.cuda.synchronize()
+    o2 = orc.solve(p, eps=EPS, lam0=(ex["lam"] + 0.1).astype(np.float32).astype(np.float64))
+    check_solution(out, p, o2)
+
+
+def test_status_paths(ctx):
+    p = synth.problem(24, seed=3)
+    out = ctx.mpcpcg_solve(dev(p), eps=EPS, max_iter=1)
+    torch.cuda.synchronize()
+    st = stats(out["stats"])[0]
+    assert st["status"] == 1 and st["iters"] == 1
+    o = orc.solve(p, eps=EPS, max_iter=1)
+    assert rel(out["lam"].cpu().numpy(), o["lam"]) < 1e-5
+    bad = {k: v.copy() for k, v in p.items()}
+    bad["Q"][5] = -bad["Q"][5]
+    out = ctx.mpcpcg_solve(dev(bad), eps=EPS)
+    torch.cuda.synchronize()
+    assert stats(out["stats"])[0]["status"] == 2
+    nan = {k: v.copy() for k, v in p.items()}
+    nan["q"][4, 2] = np.nan
+    out = ctx.mpcpcg_solve(dev(nan), eps=EPS)
+    torch.cuda.synchronize()
+    assert stats(out["stats"])[0]["status"] == 2
+    z = {k: v.copy() for k, v in p.items()}
+    for k in ("q", "r", "x0"):
+        z[k][:] = 0
+    out = ctx.mpcpcg_solve(dev(z), eps=EPS)
+    torch.cuda.synchronize()
+    st = stats(out["stats"])[0]
+    assert st["status"] == 0 and st["iters"] == 0
+    assert not out["lam"].cpu().numpy().any()
+
+
+def test_invalid_arguments_rejected(ctx):
+    from paper_2309_08079_amd.mpcpcg import MPCPCGError
+    p = dev(synth.problem(4, seed=1))
+    with pytest.raises(MPCPCGError):
+        ctx.mpcpcg_solve(p, eps=-1.0)
+    with pytest.raises(MPCPCGError):
+        ctx.mpcpcg_solve_batched(p, np.array([0, 2, 2]), eps=EPS)  # zero-length horizon
+    with pytest.raises(MPCPCGError):
+        ctx.mpcpcg_set_knots_per_group(5)
+
+
+def _batch_case(Ns, seed0, **kw):
+    probs = synth.batch(Ns, seed0=seed0, **kw)
+    packed, off = synth.pack(probs)
+    return probs, packed, off
+
+
+def check_batch(out, packed, off, eps=EPS, tol=1e-5):
+    ref = orc.solve_batch(packed, off, eps=eps, threads=8)
+    lam = out["lam"].cpu().numpy()
+    dx = out["dx"].cpu().numpy()
+    du = out["du"].cpu().numpy()
+    st = stats(out["stats"])
+    for b in range(len(off) - 1):
+        k0, k1 = off[b], off[b + 1]
+        c0, c1 = k0 - b, k1 - b - 1
+        assert st[b]["status"] == ref["status"][b], b
+        assert abs(int(st[b]["iters"]) - int(ref["iters"][b])) <= 1, b
+        assert rel(lam[k0:k1], ref["lam"][k0:k1]) < tol, b
+        assert rel(dx[k0:k1], ref["dx"][k0:k1]) < tol, b
+        if c1 > c0:
+            assert rel(du[c0:c1], ref["du"][c0:c1]) < tol, b
+    return ref
+
+
+@pytest.mark.parametrize("kpw", [4, 8, 16, 32])
+def test_batched_ragged_horizons(ctx, kpw):
+    Ns = [1, 5, 32, 33, 64, 100, 2, 17, 47, 129]
+    probs, packed, off = _batch_case(Ns, 300)
+    ctx.mpcpcg_set_knots_per_group(kpw)
+    try:
+        out = ctx.mpcpcg_solve_batched(dev(packed), off, eps=EPS)
+        torch.cuda.synchronize()
+    finally:
+        ctx.mpcpcg_set_knots_per_group(0)
+    check_batch(out, packed, off)
+
+
+def test_batched_mixed_horizon_workload(ctx):
+    # 256 problems, N uniform over {32, 64, 128, 256, 512}, seeds 3001 + b
+    Ns = synth.horizons_uniform_choice(256, seed=3000)
+    probs, packed, off = _batch_case(Ns, 3001)
+    out = ctx.mpcpcg_solve_batched(dev(packed), off, eps=EPS)
+    torch.cuda.synchronize()
+    check_batch(out, packed, off)
+
+
+def test_batched_graph_replay_is_deterministic(ctx):
+    Ns = [64, 13, 128, 7, 256]
+    probs, packed, off = _batch_case(Ns, 900)
+    d = dev(packed)
+    outs = []
+    for _ in range(3):
+        o = ctx.mpcpcg_solve_batched(d, off, eps=EPS)
+        torch.cuda.synchronize()
+        outs.append({k: v.clone() for k, v in o.items()})
+    ctx.mpcpcg_set_graph(False)
+    try:
+        o = ctx.mpcpcg_solve_batched(d, off, eps=EPS)
+        torch.cuda.synchronize()
+        outs.append({k: v.clone() for k, v in o.items()})
+    finally:
+        ctx.mpcpcg_set_graph(True)
+    for o in outs[1:]:
+        for k in ("lam", "dx", "du", "stats"):
+            assert torch.equal(o[k], outs[0][k]), k
+    check_batch(outs[0], packed, off)
+
+
+def test_batch_of_one_equals_single_solve(ctx):
+    p = synth.problem(96, seed=11)
+    packed, off = synth.pack([p])
+    ctx.mpcpcg_set_knots_per_group(16)
+    try:
+        a = ctx.mpcpcg_solve(dev(p), eps=EPS)
+        b = ctx.mpcpcg_solve_batched(dev(packed), off, eps=EPS)
+        torch.cuda.synchronize()
+    finally:
+        ctx.mpcpcg_set_knots_per_group(0)
+    for k in ("lam", "dx", "du"):
+        assert torch.equal(a[k], b[k]), k
+
+
+GRAD_KEYS = ("dQ", "dR", "dA", "dB", "dq", "dr", "dx0", "de")
+
+
+def check_grads(g, ref, off, tol=1e-4):
+    B = len(off) - 1
+    st = stats(g["stats"])
+    out = {k: g[k].cpu().numpy() for k in GRAD_KEYS}
+    for b in range(B):
+        k0, k1 = off[b], off[b + 1]
+        c0, c1 = k0 - b, k1 - b - 1
+        assert st[b]["status"] == ref["status"][b]
+        assert abs(int(st[b]["iters"]) - int(ref["iters"][b])) <= 1
+        assert rel(out["dQ"][k0:k1], ref["dQ"][k0:k1]) < tol, ("dQ", b)
+        assert rel(out["dq"][k0:k1], ref["dq"][k0:k1]) < tol, ("dq", b)
+        assert rel(out["dx0"][b], ref["dx0"][b]) < tol, ("dx0", b)
+        if c1 > c0:
+            for k in ("dR", "dA", "dB", "dr", "de"):
+                assert rel(out[k][c0:c1], ref[k][c0:c1]) < tol, (k, b)
+
+
+@pytest.mark.parametrize("Ns,seed0", [([8], 4000), ([1, 3, 17, 40], 4100)])
+def test_backward_matches_oracle_adjoint(ctx, Ns, seed0):
+    probs, packed, off = _batch_case(Ns, seed0)
+    d = dev(packed)
+    f = ctx.mpcpcg_solve_batched(d, off, eps=EPS)
+    gl = 2 * f["lam"]
+    g = ctx.mpcpcg_backward(d, off, f, gl, eps=EPS)
+    torch.cuda.synchronize()
+    fwd = {k: f[k].cpu().numpy().astype(np.float64) for k in ("lam", "dx", "du")}
+    ref = orc.backward_batch(packed, off, fwd, gl.cpu().numpy().astype(np.float64), eps=EPS, threads=8)
+    check_grads(g, ref, off)
+    assert rel(g["dgamma"].cpu().numpy(), ref["mu"]) < 1e-4
+
+
+def test_backward_with_primal_gradients(ctx):
+    probs, packed, off = _batch_case([20, 9], 4200)
+    d = dev(packed)
+    f = ctx.mpcpcg_solve_batched(d, off, eps=EPS)
+    rng = np.random.default_rng(5)
+    gl = torch.from_numpy(rng.standard_normal(f["lam"].shape).astype(np.float32)).cuda()
+    gx = torch.from_numpy(rng.standard_normal(f["dx"].shape).astype(np.float32)).cuda()
+    gu = torch.from_numpy(rng.standard_normal(f["du"].shape).astype(np.float32)).cuda()
+    g = ctx.mpcpcg_backward(d, off, f, gl, gx, gu, eps=EPS)
+    torch.cuda.synchronize()
+    fwd = {k: f[k].cpu().numpy().astype(np.float64) for k in ("lam", "dx", "du")}
+    ref = orc.backward_batch(packed, off, fwd, gl.cpu().numpy().astype(np.float64),
+                             gx.cpu().numpy().astype(np.float64), gu.cpu().numpy().astype(np.float64),
+                             eps=EPS, threads=8)
+    check_grads(g, ref, off)
+
+
+def test_backward_batch64_horizon128(ctx):
+    # batch 64, N = 128, L = ||lambda||^2, seeds 4001 + b
+    probs, packed, off = _batch_case([128] * 64, 4001)
+    d = dev(packed)
+    f = ctx.mpcpcg_solve_batched(d, off, eps=EPS)
+    g = ctx.mpcpcg_backward(d, off, f, 2 * f["lam"], eps=EPS)
+    torch.cuda.synchronize()
+    fwd = {k: f[k].cpu().numpy().astype(np.float64) for k in ("lam", "dx", "du")}
+    ref = orc.backward_batch(packed, off, fwd, 2 * fwd["lam"], eps=EPS, threads=8)
+    check_grads(g, ref, off)
+
+
+def test_autograd_function_matches_dense_gradients(ctx):
+    from paper_2309_08079_amd.mpcpcg import MPCPCGFunction
+    p = synth.problem(8, seed=4000)
+    packed, off = synth.pack([p])
+    d = dev(packed)
+    leaves = {k: d[k].clone().requires_grad_(True) for k in ("Q", "R", "A", "B", "q", "r", "x0", "e")}
+    lam, dx, du = MPCPCGFunction.apply(ctx, off, EPS, *[leaves[k] for k in ("Q", "R", "A", "B", "q", "r", "x0", "e")])
+    (lam * lam).sum().backward()
+    ref = kkt.adjoint_dense(p, 2 * kkt.kkt_solve(p)["lam"])
+    for k in ("Q", "R", "A", "B", "q", "r", "x0", "e"):
+        got = leaves[k].grad.cpu().numpy()
+        want = ref["d" + k].reshape(got.shape)
+        assert rel(got, want) < 1e-4, k
