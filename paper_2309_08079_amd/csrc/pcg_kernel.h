@@ -40,11 +40,15 @@ struct Task {
   int32_t part;
 };
 
-struct Gang {         // per problem; zero between launches (reset by the last part out)
-  int arrive;
-  int done;
-  int abort;
-  int pad;
+// Per-problem gang state, zero between launches (reset by the last part out).  Each
+// problem's counter sits on its own 256-byte block: with several gangs polling counters
+// that share a cache line, a barrier costs 10x more.
+struct alignas(256) Gang {
+  int arrive;      // monotonic arrivals: barrier n completes at (n + 1) * nparts
+  int pad0[31];
+  int done;        // parts finished with the problem
+  int abort;       // set when a part gave up waiting
+  int pad1[30];
 };
 
 template <int NX>
@@ -95,9 +99,6 @@ __device__ __forceinline__ double uni(double v) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-__device__ __forceinline__ int ld_acq(int *p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // Register budget: the S row (84 VGPRs) and Phi^-1 row (42) stay resident for the whole
 // solve; 2 waves per SIMD (256 VGPRs) leaves room for the formation's temporaries.
@@ -188,6 +189,12 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
     // and leaves totals in tot[].  ND double channels, NF float channel, NM matrix, NR
     // reduction values (read from red_w[ph]).
     auto sync_point = [&](int ND, int NF, int NM, int NR, int ph) {
+      // Cross-part data (halos, partial sums) moves through agent-scope relaxed atomics,
+      // which bypass the non-coherent cache levels.  Ordering comes from completion
+      // waits: every wave waits for its own stores before the workgroup barrier, and the
+      // arrival is issued only after the partial-sum store has completed; a reader issues
+      // its loads only after it has observed every arrival.
+      if (multi) __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       if (multi) {
         const int par = nsync & 1;
@@ -200,22 +207,23 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
             }
             __hip_atomic_store(&tws[my_t].red[par][0], s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&tws[my_t].red[par][1], s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __hip_atomic_fetch_add(&gang->arrive, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_s_waitcnt(0);
+            __hip_atomic_fetch_add(&gang->arrive, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const int target = (nsync + 1) * G;
             const long long t_start = wall_clock64();
-            int ab = 0;
-            while (ld_acq(&gang->arrive) < target) {
-              if (ld_acq(&gang->abort)) { ab = 1; break; }
-              if (wall_clock64() - t_start > kSpinLimitTicks) {
-                __hip_atomic_store(&gang->abort, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                ab = 1;
-                break;
+            int ab = 0, polls = 0;
+            while (__hip_atomic_load(&gang->arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+              __builtin_amdgcn_s_sleep(2);
+              if ((++polls & 63) == 0) {
+                if (__hip_atomic_load(&gang->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ab = 1; break; }
+                if (wall_clock64() - t_start > kSpinLimitTicks) {
+                  __hip_atomic_store(&gang->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                  ab = 1;
+                  break;
+                }
               }
-              __builtin_amdgcn_s_sleep(1);
             }
             sh_abort = ab;
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             // totals: identical summation order in every part
             double t0 = 0.0, t1 = 0.0;
             for (int g = 0; g < G; ++g) {
@@ -226,7 +234,6 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
             tot[1] = t1;
           }
           __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
           // halos from the neighbouring parts: lanes 0..15 left, 16..31 right
           if (wl < 2 * kGroup) {
             const int side = wl >> 4, l = wl & 15;
@@ -438,7 +445,6 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         for (int j = 0; j < NX; ++j)
           __hip_atomic_store(&tws[my_t].hm[1][lane][j], Dd[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (multi && rowv && (slot == 0 || slot == KPW - 1)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     sync_point(0, 0, 1, 0, 0);
     // (7) Phi^-1_{b,b-1} = -D_b^-1 S_{b,b-1} D_{b-1}^-1, Phi^-1_{b,b+1} likewise
     float Pm[NX], Pd[NX], Pp[NX];
@@ -497,7 +503,6 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       put_d(0, rhs);
       if (MODE == kForward && a.warm && act && rowv) lam = (double)a.lam[kb * NX + lane];
       put_d(1, lam);
-      if (multi && (slot == 0 || slot == KPW - 1)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       sync_point(2, 0, 0, 0, 0);
       const double gm = ex_d[0][slot][lane], gp = ex_d[0][slot + 2][lane];
       float gt = 0.f;
@@ -520,8 +525,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         row_fma14_f64(a2, lp, Sp);
         r = rhs - ((a0 + a1) + a2);
         put_d(0, r);
-        if (multi && (slot == 0 || slot == KPW - 1)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        sync_point(1, 0, 0, 0, 1);
+          sync_point(1, 0, 0, 0, 1);
         rm = ex_d[0][slot][lane];
         rp = ex_d[0][slot + 2][lane];
       }
@@ -539,7 +543,6 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       put_red(0, 0, r * (double)rt);
       put_red(0, 1, rhs * (double)gt);
       put_f(rt);
-      if (multi && (slot == 0 || slot == KPW - 1)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       sync_point(0, 1, 0, 2, 0);
       double eta = uni(tot[0]);
       const double eta_ref = uni(tot[1]);
@@ -564,8 +567,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
           const double Y = (a0 + a1) + a2;
           put_red(0, 0, p * Y);
           put_d(0, Y);
-          if (multi && (slot == 0 || slot == KPW - 1)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-          sync_point(1, 0, 0, 1, 0);
+              sync_point(1, 0, 0, 1, 0);
           const double ups = uni(tot[0]);
           if (!(ups > 0.0) || __builtin_isinf(ups)) {
             status = MPCPCG_BREAKDOWN;
@@ -585,8 +587,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
           const float rtn = (c0 + c1) + c2;
           put_red(1, 0, r * (double)rtn);
           put_f(rtn);
-          if (multi && (slot == 0 || slot == KPW - 1)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-          sync_point(0, 1, 0, 1, 1);
+              sync_point(0, 1, 0, 1, 1);
           eta_new = uni(tot[0]);
           if (!(eta_new == eta_new) || __builtin_isinf(eta_new)) {
             status = MPCPCG_BREAKDOWN;
@@ -614,7 +615,6 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       // adjoint): x rows use Q_b^-1 and S_{b,b+1} = -Q_b^-1 A_b^T; u rows of control b-1
       // use R_{b-1}^-1 and W = R_{b-1}^-1 B_{b-1}^T (both written during formation).
       put_d(0, lam);
-      if (multi && (slot == 0 || slot == KPW - 1)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       sync_point(1, 0, 0, 0, 0);
       const double lp = ex_d[0][slot + 2][lane];
       double qmin = 0.0;   // q_b - lambda_b  (or gx_b - mu_b)
@@ -654,8 +654,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         // adjoint: lam holds mu, xrow = nu1x_b, urow = nu1u_{b-1}
         const double mu = lam, n1x = xrow, n1u = urow;
         put_d(0, n1x);
-        if (multi && (slot == 0 || slot == KPW - 1)) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        sync_point(1, 0, 0, 0, 1);
+          sync_point(1, 0, 0, 0, 1);
         const double n1xm = ex_d[0][slot][lane];  // nu1x_{b-1}
         double dxb = 0.0, dxm = 0.0, lb = 0.0, dum = 0.0;
         if (act && rowv) {
