@@ -41,6 +41,11 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0, help="problems in the CPU sample (0 = auto)")
+    ap.add_argument("--step-only", action="store_true",
+                    help="time the batched step only (no single-launch comparison, no CPU baseline)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="run one plain device-to-device copy of MIB MiB and exit (hardware-counter "
+                         "calibration: bytes a copy of known size reads and writes)")
     return ap.parse_args()
 
 
@@ -85,6 +90,15 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, device=dev)
+        dst = torch.empty(n, device=dev)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 4 * n}))
+        return
     probs = synth.batch([N_KNOTS] * BATCH, NX, NU, seed0=SEED0)
     packed_np, off = synth.pack(probs)
     d = to_device(packed_np, dev)
@@ -144,6 +158,11 @@ def main():
                                      + FLOP_PER_KNOT_GRAD)))
     dom_name, dom_ms, dom_flop = ("adjoint", adj_ms, flop_b) if adj_ms >= fwd_ms else ("forward", fwd_ms, flop_f)
     achieved = dom_flop / (dom_ms * 1e-3) / 1e12
+
+    if args.step_only:
+        print(json.dumps({"ms_per_step": ms_step, "kernel_ms": {"forward": fwd_ms, "adjoint": adj_ms},
+                          "iters_forward_mean": float(it_f.mean()), "iters_adjoint_mean": float(it_b.mean())}))
+        return
 
     # one launch per solve: single problem latency and 256 sequential launches
     single = {"Q": d["Q"][:N_KNOTS], "q": d["q"][:N_KNOTS], "x0": d["x0"][0]}
@@ -206,7 +225,7 @@ def main():
         "iters_forward_mean": float(it_f.mean()),
         "iters_adjoint_mean": float(it_b.mean()),
         "kernel_ms": {"forward": fwd_ms, "adjoint": adj_ms},
-        "roofline": {"bound": "alu", "kernel": "pcg_kernel<14,7,%s> (%s)" % ("16", dom_name),
+        "roofline": {"bound": "alu", "kernel": "pcg_kernel<14,7,32,%s>" % dom_name,
                      "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None},
         "cpu_baseline": cpu,

@@ -58,6 +58,22 @@ __device__ __forceinline__ double group_sum_to_last(double v) {
   return v;
 }
 
+// Sum over the 64 lanes of the wave with a fixed reduction shape (identical rounding in
+// every wave that calls it); the result is returned in every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+  const double g = group_sum_to_last(v);
+  const uint64_t u = __builtin_bit_cast(uint64_t, g);
+  const uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t l2 = __builtin_amdgcn_readlane(lo, 16 * q + 15);
+    const uint32_t h2 = __builtin_amdgcn_readlane(hi, 16 * q + 15);
+    s += __builtin_bit_cast(double, ((uint64_t)h2 << 32) | l2);
+  }
+  return s;
+}
+
 // ---- hot-loop matvec rows with the broadcast fused into the FMA -----------------------
 // acc += sum_{j<NX} m[j] * x(lane j).  One asm block per 14-term row keeps the DPP
 // broadcast folded into v_fmac (the compiler does not fuse row_newbcast by itself).  The

@@ -309,11 +309,11 @@ int mpcpcg_create(mpcpcg_ctx **out, int32_t nx, int32_t nu, int64_t max_total_kn
   const size_t gb = sizeof(Gang) * (size_t)max_batch;
   if (hipMalloc(&c->qinv_ws, qb) != hipSuccess || hipMalloc(&c->rinv_ws, rb) != hipSuccess ||
       hipMalloc(&c->tws, tb) != hipSuccess || hipMalloc(&c->gang, gb) != hipSuccess ||
-      hipMalloc(&c->queue, 2 * sizeof(int)) != hipSuccess) {
+      hipMalloc(&c->queue, 4 * sizeof(int)) != hipSuccess) {
     mpcpcg_destroy(c.release());
     return MPCPCG_ENOMEM;
   }
-  if (hipMemset(c->gang, 0, gb) != hipSuccess || hipMemset(c->queue, 0, 2 * sizeof(int)) != hipSuccess ||
+  if (hipMemset(c->gang, 0, gb) != hipSuccess || hipMemset(c->queue, 0, 4 * sizeof(int)) != hipSuccess ||
       hipMemset(c->tws, 0, tb) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     mpcpcg_destroy(c.release());
     return MPCPCG_EHIP;

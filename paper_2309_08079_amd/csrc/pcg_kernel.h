@@ -40,19 +40,20 @@ struct Task {
   int32_t part;
 };
 
-// Per-problem gang state, zero between launches (reset by the last part out).  Each
-// problem's counter sits on its own 256-byte block: with several gangs polling counters
-// that share a cache line, a barrier costs 10x more.
+// Per-problem gang state, zero between launches (reset by the last part out), on its
+// own 256-byte block so that gangs never share a cache line.
 struct alignas(256) Gang {
-  int arrive;      // monotonic arrivals: barrier n completes at (n + 1) * nparts
-  int pad0[31];
   int done;        // parts finished with the problem
   int abort;       // set when a part gave up waiting
-  int pad1[30];
+  int pad[62];
 };
 
 template <int NX>
-struct TaskWS {       // per task; read by the neighbouring parts of the same gang
+struct TaskWS {       // per task; read by the other parts of the same gang
+  // epoch of the last barrier this part reached: (launch generation << 32) | (n + 1)
+  // for barrier n; written after everything the part publishes for that barrier.
+  uint64_t flag;
+  uint64_t pad[7];
   double red[2][2];              // [parity][value] partial sums of this part
   double hv[2][2][2][kGroup];    // [parity][channel][side][lane] double vector halos
   float hf[2][2][kGroup];        // [parity][side][lane] float vector halos
@@ -78,7 +79,7 @@ struct KArgs {
   // workspace
   void *tws;             // TaskWS<NX>[ntasks]
   Gang *gang;            // [nprobs]
-  int *queue;            // [0] head, [1] workgroups finished
+  int *queue;            // [0] head, [1] workgroups finished, [2] launch generation
   double *qinv_ws;       // [knots][NX][NX]   Q_b^-1 rows
   double *rinv_ws;       // [controls][NU][NU + NX]  R^-1 rows and (R^-1 B^T) rows
   // options
@@ -128,6 +129,9 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
   int wave = tid >> 6;
   int wl = tid & 63;
   TaskWS<NX> *tws = reinterpret_cast<TaskWS<NX> *>(a.tws);
+  // launch generation: advanced by the last workgroup of every launch, so flags written
+  // by earlier launches are always older than any epoch of this one
+  const uint64_t gen = (uint64_t)(uint32_t)uni(__hip_atomic_load(&a.queue[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 
   for (int iter_task = 0;; ++iter_task) {
     // ------------------------------------------------------------- task selection
@@ -189,15 +193,17 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
     // and leaves totals in tot[].  ND double channels, NF float channel, NM matrix, NR
     // reduction values (read from red_w[ph]).
     auto sync_point = [&](int ND, int NF, int NM, int NR, int ph) {
-      // Cross-part data (halos, partial sums) moves through agent-scope relaxed atomics,
-      // which bypass the non-coherent cache levels.  Ordering comes from completion
-      // waits: every wave waits for its own stores before the workgroup barrier, and the
-      // arrival is issued only after the partial-sum store has completed; a reader issues
-      // its loads only after it has observed every arrival.
+      // Cross-part data (halos, partial sums, flags) moves through agent-scope relaxed
+      // atomics, which bypass the non-coherent cache levels.  Ordering comes from
+      // completion waits: every wave waits for its own stores before the workgroup
+      // barrier, the flag is written only after the partial sums have completed, and a
+      // reader loads data only after it has seen the flags of every part.  Lane g of wave
+      // 0 polls part g, so the wait costs one round trip whatever the number of parts.
       if (multi) __builtin_amdgcn_s_waitcnt(0);
       __syncthreads();
       if (multi) {
         const int par = nsync & 1;
+        const uint64_t epoch = (gen << 32) | (uint64_t)(uint32_t)(nsync + 1);
         if (wave == 0) {
           if (wl == 0) {
             double s0 = 0.0, s1 = 0.0;
@@ -208,12 +214,17 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
             __hip_atomic_store(&tws[my_t].red[par][0], s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&tws[my_t].red[par][1], s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __builtin_amdgcn_s_waitcnt(0);
-            __hip_atomic_fetch_add(&gang->arrive, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const int target = (nsync + 1) * G;
-            const long long t_start = wall_clock64();
-            int ab = 0, polls = 0;
-            while (__hip_atomic_load(&gang->arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-              __builtin_amdgcn_s_sleep(2);
+            __hip_atomic_store(&tws[my_t].flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+          const long long t_start = wall_clock64();
+          int ab = 0, polls = 0;
+          for (int g0 = 0; g0 < G && !ab; g0 += 64) {
+            const int g = g0 + wl;
+            while (true) {
+              const bool ok = g >= G || __hip_atomic_load(&tws[pd.t0 + (g < G ? g : 0)].flag, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+              if (__ballot(ok) == ~0ull) break;
+              __builtin_amdgcn_s_sleep(1);
               if ((++polls & 63) == 0) {
                 if (__hip_atomic_load(&gang->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ab = 1; break; }
                 if (wall_clock64() - t_start > kSpinLimitTicks) {
@@ -223,19 +234,10 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
                 }
               }
             }
-            sh_abort = ab;
-            // totals: identical summation order in every part
-            double t0 = 0.0, t1 = 0.0;
-            for (int g = 0; g < G; ++g) {
-              t0 += __hip_atomic_load(&tws[pd.t0 + g].red[par][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              t1 += __hip_atomic_load(&tws[pd.t0 + g].red[par][1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            tot[0] = t0;
-            tot[1] = t1;
           }
-          __builtin_amdgcn_wave_barrier();
-          // halos from the neighbouring parts: lanes 0..15 left, 16..31 right
-          if (wl < 2 * kGroup) {
+          // halos from the neighbouring parts (lanes 0..15 left, 16..31 right) and the
+          // partial sums (lane g: parts g, g+64, ...) are loaded together, one round trip
+          if (wl < 2 * kGroup && !ab) {
             const int side = wl >> 4, l = wl & 15;
             const int nb = side == 0 ? part - 1 : part + 1;
             const bool has = nb >= 0 && nb < G;
@@ -249,6 +251,20 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
             if (NM)
               for (int rr = 0; rr < NX; ++rr)
                 ex_m[dst][rr][l] = has ? __hip_atomic_load(&src->hm[srcside][rr][l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+          }
+          // totals: a fixed-shape reduction, so every part computes bit-identical totals
+          double v0 = 0.0, v1 = 0.0;
+          if (!ab && NR > 0) {
+            for (int g = wl; g < G; g += 64) {
+              v0 += __hip_atomic_load(&tws[pd.t0 + g].red[par][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              v1 += __hip_atomic_load(&tws[pd.t0 + g].red[par][1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+          }
+          const double w0 = wave_sum(v0), w1 = wave_sum(v1);
+          if (wl == 0) {
+            tot[0] = w0;
+            tot[1] = w1;
+            sh_abort = ab;
           }
         }
         __syncthreads();
@@ -723,7 +739,6 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       if (tid == 0) {
         const int d = __hip_atomic_fetch_add(&gang->done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (d == G - 1) {
-          __hip_atomic_store(&gang->arrive, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           __hip_atomic_store(&gang->abort, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           __hip_atomic_store(&gang->done, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -731,15 +746,15 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
     }
   }
 
-  // ------------------------------------------------------------- queue teardown
-  if (a.persistent) {
-    __syncthreads();
-    if (tid == 0) {
-      const int d = __hip_atomic_fetch_add(&a.queue[1], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      if (d == (int)gridDim.x - 1) {
-        __hip_atomic_store(&a.queue[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&a.queue[1], 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      }
+  // ------------------------------------------------------------- launch teardown
+  // The last workgroup out resets the queue and advances the launch generation.
+  __syncthreads();
+  if (tid == 0) {
+    const int d = __hip_atomic_fetch_add(&a.queue[1], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (d == (int)gridDim.x - 1) {
+      __hip_atomic_store(&a.queue[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&a.queue[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&a.queue[1], 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }

@@ -1,0 +1,81 @@
+"""CPU-side checks of the boundary: the built library exports every entry point that
+include/mpcpcg.h declares, the binding fails loudly without it, and the seeded generator
+packs batches in the layout the header documents.  Nothing here calls into the GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2309_08079_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mpcpcg.h")
+LIB = os.path.join(ROOT, "paper_2309_08079_amd", "libmpcpcg.so")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(mpcpcg_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for name in ("mpcpcg_create", "mpcpcg_destroy", "mpcpcg_last_error", "mpcpcg_form_schur",
+                 "mpcpcg_solve", "mpcpcg_solve_batched", "mpcpcg_backward"):
+        assert name in syms
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmpcpcg.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    from paper_2309_08079_amd import mpcpcg
+    saved = mpcpcg._lib
+    mpcpcg._lib = None
+    try:
+        with pytest.raises(mpcpcg.MPCPCGError):
+            mpcpcg.load_library(str(tmp_path / "missing.so"))
+    finally:
+        mpcpcg._lib = saved
+
+
+def test_struct_layouts_match_header():
+    from paper_2309_08079_amd import mpcpcg
+    assert ctypes.sizeof(mpcpcg.Opts) == 16
+    assert ctypes.sizeof(mpcpcg.Problem) == 16 + 8 * 8
+    assert mpcpcg.STATS_DTYPE.itemsize == 16
+
+
+def test_generator_recipe_and_packing():
+    p = synth.problem(5, seed=3)
+    assert p["Q"].shape == (5, 14, 14) and p["R"].shape == (4, 7, 7)
+    assert p["A"].shape == (4, 14, 14) and p["B"].shape == (4, 14, 7)
+    assert all(v.dtype == np.float32 for v in p.values())
+    assert np.allclose(p["Q"], np.transpose(p["Q"], (0, 2, 1)))
+    assert np.all(np.linalg.eigvalsh(p["Q"].astype(np.float64)) > 0)
+    assert np.all(np.diagonal(p["R"], axis1=1, axis2=2) >= 0.1)
+    assert np.allclose(np.diagonal(p["A"], axis1=1, axis2=2), 1.0, atol=0.05)
+    assert not p["e"].any()
+    # same seed, same draw; different seed, different draw
+    assert all(np.array_equal(p[k], synth.problem(5, seed=3)[k]) for k in p)
+    assert not np.array_equal(p["q"], synth.problem(5, seed=4)["q"])
+    probs = synth.batch([3, 1, 4], seed0=10)
+    packed, off = synth.pack(probs)
+    assert off.tolist() == [0, 3, 4, 8]
+    assert packed["Q"].shape[0] == 8 and packed["A"].shape[0] == 8 - 3
+    for b, pb in enumerate(probs):
+        assert np.array_equal(synth.unpack_knots(packed["q"], off)[b], pb["q"])
+        assert np.array_equal(synth.unpack_controls(packed["B"], off)[b], pb["B"])
+        assert np.array_equal(packed["x0"][b], pb["x0"])
+
+
+def test_mixed_horizon_draw():
+    Ns = synth.horizons_uniform_choice(256, seed=3000)
+    assert len(Ns) == 256 and set(Ns) <= {32, 64, 128, 256, 512}
+    assert 40_000 < sum(Ns) < 60_000
