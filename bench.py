@@ -34,6 +34,29 @@ FLOP_PER_KNOT_GRAD = 1960      # dQ, dA (two outer products each), dB, dR
 PEAK_VALU_TFLOPS = 78.6        # FP64 vector FMA issue rate of MI355X (= non-packed FP32)
 
 
+def measured_traffic(mode):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes (calibrated on a plain copy), or None once the kernel sources differ
+    from those the counters were taken on."""
+    import glob
+    import hashlib
+
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", "pcg_kernel_traffic_256xN512.json")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256()
+        for src in rec["kernel_sources"]:
+            h.update(open(os.path.join(root, src), "rb").read())
+        srcs = sorted(glob.glob(os.path.join(root, "paper_2309_08079_amd", "csrc", "*")))
+        if h.hexdigest() != rec["kernel_sources_sha256"] or len(srcs) + 1 != len(rec["kernel_sources"]):
+            return None
+        pl = rec["per_launch"][mode]
+        return pl["fetch_bytes"] + pl["write_bytes"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,7 +250,7 @@ def main():
         "kernel_ms": {"forward": fwd_ms, "adjoint": adj_ms},
         "roofline": {"bound": "alu", "kernel": "pcg_kernel<14,7,32,%s>" % dom_name,
                      "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None},
+                     "frac": achieved / PEAK_VALU_TFLOPS, "traffic": measured_traffic(dom_name)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -150,12 +150,12 @@ class Context:
         N = prob["q"].shape[0]
         dev = prob["q"].device
         o = out or {}
-        lam = o.get("lam", torch.empty((N, self.nx), device=dev))
+        lam = o["lam"] if "lam" in o else torch.empty((N, self.nx), device=dev)
         if lam0 is not None:
             lam.copy_(lam0)
-        dx = o.get("dx", torch.empty((N, self.nx), device=dev))
-        du = o.get("du", torch.empty((max(N - 1, 0), self.nu), device=dev))
-        stats = o.get("stats", torch.zeros((1, 4), dtype=torch.int32, device=dev))
+        dx = o["dx"] if "dx" in o else torch.empty((N, self.nx), device=dev)
+        du = o["du"] if "du" in o else torch.empty((max(N - 1, 0), self.nu), device=dev)
+        stats = o["stats"] if "stats" in o else torch.zeros((1, 4), dtype=torch.int32, device=dev)
         self._check(self.lib.mpcpcg_solve(
             self.h, C.byref(_problem(prob, self.nx, self.nu, N)), C.byref(_opts(eps, max_iter, lam0 is not None)),
             _ptr(lam), _ptr(dx), _ptr(du) if du.numel() else None, stats.data_ptr(), _stream()),
@@ -168,12 +168,12 @@ class Context:
         K = int(off[-1])
         dev = packed["q"].device
         o = out or {}
-        lam = o.get("lam", torch.empty((K, self.nx), device=dev))
+        lam = o["lam"] if "lam" in o else torch.empty((K, self.nx), device=dev)
         if lam0 is not None:
             lam.copy_(lam0)
-        dx = o.get("dx", torch.empty((K, self.nx), device=dev))
-        du = o.get("du", torch.empty((max(K - B, 0), self.nu), device=dev))
-        stats = o.get("stats", torch.zeros((B, 4), dtype=torch.int32, device=dev))
+        dx = o["dx"] if "dx" in o else torch.empty((K, self.nx), device=dev)
+        du = o["du"] if "du" in o else torch.empty((max(K - B, 0), self.nu), device=dev)
+        stats = o["stats"] if "stats" in o else torch.zeros((B, 4), dtype=torch.int32, device=dev)
         self._check(self.lib.mpcpcg_solve_batched(
             self.h, B, off.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(_problem(packed, self.nx, self.nu)),
             C.byref(_opts(eps, max_iter, lam0 is not None)), _ptr(lam), _ptr(dx),
@@ -189,11 +189,11 @@ class Context:
         dev = packed["q"].device
         nx, nu = self.nx, self.nu
         o = out or {}
-        z = lambda key, shape: o.get(key, torch.empty(shape, device=dev))
+        z = lambda key, shape: o[key] if key in o else torch.empty(shape, device=dev)
         g = dict(dQ=z("dQ", (K, nx, nx)), dR=z("dR", (M, nu, nu)), dA=z("dA", (M, nx, nx)),
                  dB=z("dB", (M, nx, nu)), dq=z("dq", (K, nx)), dr=z("dr", (M, nu)),
                  dx0=z("dx0", (B, nx)), de=z("de", (M, nx)), dgamma=z("dgamma", (K, nx)))
-        stats = o.get("stats", torch.zeros((B, 4), dtype=torch.int32, device=dev))
+        stats = o["stats"] if "stats" in o else torch.zeros((B, 4), dtype=torch.int32, device=dev)
         opt = lambda t: _ptr(t) if t is not None and t.numel() else None
         self._check(self.lib.mpcpcg_backward(
             self.h, B, off.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(_problem(packed, nx, nu)),
