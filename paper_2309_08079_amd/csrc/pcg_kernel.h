@@ -27,6 +27,8 @@ namespace mpc {
 
 enum Mode : int { kForm = 0, kForward = 1, kAdjoint = 2 };
 
+constexpr int kMaxWaves = 8;    // waves per workgroup (32 knots x 16 lanes / 64)
+
 struct ProbDesc {
   int64_t k0;       // first knot row of the problem in the packed arrays
   int32_t N;        // knots
@@ -54,7 +56,7 @@ struct TaskWS {       // per task; read by the other parts of the same gang
   // for barrier n; written after everything the part publishes for that barrier.
   uint64_t flag;
   uint64_t pad[7];
-  double red[2][2];              // [parity][value] partial sums of this part
+  double red[2][kMaxWaves][2];   // [parity][wave][value] partial sums of this part's waves
   double hv[2][2][2][kGroup];    // [parity][channel][side][lane] double vector halos
   float hf[2][2][kGroup];        // [parity][side][lane] float vector halos
   double hm[2][NX][kGroup];      // [side][row][col] matrix halo (one use, in formation)
@@ -109,7 +111,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
   static_assert(NX == 14 && NU <= NX, "the fused row kernels are written for 14-row blocks");
   constexpr int NT = KPW * kGroup;
   constexpr int NW = NT / 64;
-  static_assert(NT % 64 == 0, "whole waves");
+  static_assert(NT % 64 == 0 && NW <= kMaxWaves, "whole waves, at most kMaxWaves");
 
   __shared__ double ex_d[2][KPW + 2][kGroup];  // vector exchange, slot s+1 is knot s
   __shared__ float ex_f[KPW + 2][kGroup];
@@ -205,17 +207,9 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         const int par = nsync & 1;
         const uint64_t epoch = (gen << 32) | (uint64_t)(uint32_t)(nsync + 1);
         if (wave == 0) {
-          if (wl == 0) {
-            double s0 = 0.0, s1 = 0.0;
-            for (int w = 0; w < NW; ++w) {
-              if (NR > 0) s0 += red_w[ph][0][w];
-              if (NR > 1) s1 += red_w[ph][1][w];
-            }
-            __hip_atomic_store(&tws[my_t].red[par][0], s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&tws[my_t].red[par][1], s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __builtin_amdgcn_s_waitcnt(0);
+          // every wave's halo and partial-sum stores completed before the barrier above
+          if (wl == 0)
             __hip_atomic_store(&tws[my_t].flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          }
           const long long t_start = wall_clock64();
           int ab = 0, polls = 0;
           for (int g0 = 0; g0 < G && !ab; g0 += 64) {
@@ -252,12 +246,15 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
               for (int rr = 0; rr < NX; ++rr)
                 ex_m[dst][rr][l] = has ? __hip_atomic_load(&src->hm[srcside][rr][l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
           }
-          // totals: a fixed-shape reduction, so every part computes bit-identical totals
+          // totals over (part, wave) in a fixed order and a fixed-shape reduction, so every
+          // part computes bit-identical totals
           double v0 = 0.0, v1 = 0.0;
           if (!ab && NR > 0) {
-            for (int g = wl; g < G; g += 64) {
-              v0 += __hip_atomic_load(&tws[pd.t0 + g].red[par][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              v1 += __hip_atomic_load(&tws[pd.t0 + g].red[par][1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int idx = wl; idx < G * NW; idx += 64) {
+              const int g = idx / NW, w = idx - g * NW;
+              v0 += __hip_atomic_load(&tws[pd.t0 + g].red[par][w][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              if (NR > 1)
+                v1 += __hip_atomic_load(&tws[pd.t0 + g].red[par][w][1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
           }
           const double w0 = wave_sum(v0), w1 = wave_sum(v1);
@@ -317,7 +314,11 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         const uint32_t h2 = __builtin_amdgcn_readlane(hi, 16 * q + 15);
         s += __builtin_bit_cast(double, ((uint64_t)h2 << 32) | l2);
       }
-      if (wl == 0) red_w[ph][v][wave] = s;
+      if (wl == 0) {
+        red_w[ph][v][wave] = s;
+        if (multi)
+          __hip_atomic_store(&tws[my_t].red[nsync & 1][wave][v], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     };
 
     // ================================================================== formation
