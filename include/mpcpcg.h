@@ -24,7 +24,10 @@
  *  - Every call is asynchronous on the given hipStream_t (0 = the null stream).  The
  *    return value reports synchronous errors only (argument validation, a failed
  *    launch).  Per-problem outcomes are written to a device array of mpcpcg_stats.
- *  - Supported (nx, nu): (14, 7).  Others return MPCPCG_EUNSUPPORTED.
+ *  - Supported (nx, nu): (14, 7), on a register-resident fused kernel, and (28, 14), on a
+ *    workspace-staged path (formation, preconditioner and PCG launches; horizons up to
+ *    292 knots).  Others return MPCPCG_EUNSUPPORTED.  Schedule control (knots per group,
+ *    graphs, autotune) applies to the (14, 7) path; on (28, 14) it is accepted and ignored.
  *  - A context is not thread safe; calls that share a context must be serialised by
  *    the caller and must not overlap on different streams.
  *  - Calls never abort or throw across the ABI.  mpcpcg_last_error() describes the

@@ -14,6 +14,7 @@
 
 #include "mpcpcg.h"
 #include "pcg_kernel.h"
+#include "wide_kernels.h"
 
 namespace {
 
@@ -22,7 +23,8 @@ using mpc::KArgs;
 using mpc::ProbDesc;
 using mpc::Task;
 
-constexpr int kNX = 14, kNU = 7;
+constexpr int kNX = 14, kNU = 7;        // register-resident fused path
+constexpr int kWNX = 28, kWNU = 14;     // generic (workspace-staged) path
 constexpr int kKpwChoices[] = {4, 8, 16, 32};
 
 // One schedule per (horizon signature, knots per workgroup): problem descriptors and the
@@ -42,6 +44,12 @@ struct Schedule {
   int grid[3] = {0, 0, 0};
 };
 
+struct WideSchedule {
+  mpc::wide::KnotDesc *d_knots = nullptr;
+  mpc::wide::ProbDescW *d_probs = nullptr;
+  int nknots = 0, nprobs = 0, maxN = 0;
+};
+
 }  // namespace
 
 struct mpcpcg_ctx {
@@ -57,6 +65,11 @@ struct mpcpcg_ctx {
   int *queue = nullptr;
   std::map<std::pair<std::vector<int64_t>, int>, std::unique_ptr<Schedule>> sched;
   std::map<std::vector<int64_t>, int> tuned;  // horizon signature -> knots per workgroup
+  // generic path (nx = 28)
+  bool wide = false;
+  double *w_S = nullptr, *w_Dinv = nullptr, *w_rhs = nullptr, *w_Qinv = nullptr, *w_RW = nullptr;
+  float *w_P = nullptr;
+  std::map<std::vector<int64_t>, std::unique_ptr<WideSchedule>> wsched;
   std::string err;
 };
 
@@ -284,6 +297,78 @@ int launch_batched(mpcpcg_ctx *c, Schedule *s, KArgs &a, int mode, hipStream_t s
   return MPCPCG_OK;
 }
 
+// ---------------------------------------------------------------- generic path (nx = 28)
+constexpr int kWideMaxRows = mpc::wide::kWideThreads * mpc::wide::kWideRows;
+
+size_t wide_lds_bytes(int N, int nx, int nu) {
+  const size_t vd = sizeof(double) * (size_t)(N + 2) * nx;
+  const size_t vf = sizeof(float) * (((size_t)(N + 2) * nx + 1) / 2 * 2);
+  return vd + vf + sizeof(double) * (size_t)N * nu;
+}
+
+int wide_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, WideSchedule **out) {
+  auto it = c->wsched.find(off);
+  if (it != c->wsched.end()) { *out = it->second.get(); return MPCPCG_OK; }
+  const int B = (int)off.size() - 1;
+  std::vector<mpc::wide::KnotDesc> kd;
+  std::vector<mpc::wide::ProbDescW> pd(B);
+  int maxN = 0;
+  for (int b = 0; b < B; ++b) {
+    const int N = (int)(off[b + 1] - off[b]);
+    maxN = std::max(maxN, N);
+    if (N * c->nx > kWideMaxRows || wide_lds_bytes(N, c->nx, c->nu) > 150 * 1024)
+      return fail(c, MPCPCG_EINVAL, "horizon N=%d exceeds the %d-row limit of the nx=%d path", N,
+                  kWideMaxRows, c->nx);
+    pd[b] = mpc::wide::ProbDescW{off[b], N, b};
+    for (int k = 0; k < N; ++k) kd.push_back(mpc::wide::KnotDesc{off[b], N, k, b, 0});
+  }
+  auto w = std::make_unique<WideSchedule>();
+  w->nknots = (int)kd.size();
+  w->nprobs = B;
+  w->maxN = maxN;
+  HIPCHK(c, hipMalloc(&w->d_knots, sizeof(mpc::wide::KnotDesc) * kd.size()));
+  HIPCHK(c, hipMalloc(&w->d_probs, sizeof(mpc::wide::ProbDescW) * B));
+  HIPCHK(c, hipMemcpy(w->d_knots, kd.data(), sizeof(mpc::wide::KnotDesc) * kd.size(), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(w->d_probs, pd.data(), sizeof(mpc::wide::ProbDescW) * B, hipMemcpyHostToDevice));
+  *out = w.get();
+  c->wsched.emplace(off, std::move(w));
+  return MPCPCG_OK;
+}
+
+mpc::wide::WArgs wide_args(mpcpcg_ctx *c, const mpcpcg_problem *p, const mpcpcg_opts *o) {
+  mpc::wide::WArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.Q = p->Q; a.R = p->R; a.A = p->A; a.B = p->B;
+  a.q = p->q; a.r = p->r; a.x0 = p->x0; a.e = p->e;
+  a.S = c->w_S; a.Dinv = c->w_Dinv; a.P = c->w_P; a.rhs = c->w_rhs; a.Qinv = c->w_Qinv; a.RW = c->w_RW;
+  if (o) { a.eps = o->eps; a.max_iter = o->max_iter; a.warm = o->warm_start; }
+  return a;
+}
+
+// formation, preconditioner, then (unless form_only) PCG + epilogue
+int wide_run(mpcpcg_ctx *c, const std::vector<int64_t> &off, mpc::wide::WArgs &a, bool form_only,
+             hipStream_t s) {
+  WideSchedule *w = nullptr;
+  int st = wide_schedule(c, off, &w);
+  if (st) return st;
+  a.knots = w->d_knots;
+  a.probs = w->d_probs;
+  a.nknots = w->nknots;
+  a.nprobs = w->nprobs;
+  hipLaunchKernelGGL((mpc::wide::wide_form<kWNX, kWNU>), dim3(w->nknots), dim3(256), 0, s, a);
+  HIPCHK(c, hipGetLastError());
+  hipLaunchKernelGGL((mpc::wide::wide_precond<kWNX, kWNU>), dim3(w->nknots), dim3(256), 0, s, a);
+  HIPCHK(c, hipGetLastError());
+  if (form_only) return MPCPCG_OK;
+  const size_t lds = wide_lds_bytes(w->maxN, c->nx, c->nu);
+  HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void *>(mpc::wide::wide_pcg<kWNX, kWNU>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL((mpc::wide::wide_pcg<kWNX, kWNU>), dim3(w->nprobs), dim3(mpc::wide::kWideThreads),
+                     lds, s, a);
+  HIPCHK(c, hipGetLastError());
+  return MPCPCG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -291,11 +376,13 @@ extern "C" {
 int mpcpcg_create(mpcpcg_ctx **out, int32_t nx, int32_t nu, int64_t max_total_knots, int32_t max_batch) {
   if (!out) return MPCPCG_EINVAL;
   *out = nullptr;
-  if (nx != kNX || nu != kNU) return MPCPCG_EUNSUPPORTED;
+  const bool wide = (nx == kWNX && nu == kWNU);
+  if (!wide && (nx != kNX || nu != kNU)) return MPCPCG_EUNSUPPORTED;
   if (max_total_knots < 1 || max_batch < 1 || max_batch > max_total_knots) return MPCPCG_EINVAL;
   auto c = std::make_unique<mpcpcg_ctx>();
   c->nx = nx;
   c->nu = nu;
+  c->wide = wide;
   c->max_knots = max_total_knots;
   c->max_batch = max_batch;
   c->max_tasks = max_total_knots / 4 + max_batch;
@@ -303,8 +390,23 @@ int mpcpcg_create(mpcpcg_ctx **out, int32_t nx, int32_t nu, int64_t max_total_kn
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return MPCPCG_EHIP;
   c->cus = prop.multiProcessorCount;
-  const size_t qb = sizeof(double) * (size_t)max_total_knots * nx * nx;
-  const size_t rb = sizeof(double) * (size_t)max_total_knots * nu * (nu + nx);
+  const size_t K = (size_t)max_total_knots;
+  if (wide) {
+    const size_t MM = (size_t)nx * nx;
+    if (hipMalloc(&c->w_S, sizeof(double) * K * 3 * MM) != hipSuccess ||
+        hipMalloc(&c->w_Dinv, sizeof(double) * K * MM) != hipSuccess ||
+        hipMalloc(&c->w_P, sizeof(float) * K * 3 * MM) != hipSuccess ||
+        hipMalloc(&c->w_rhs, sizeof(double) * K * nx) != hipSuccess ||
+        hipMalloc(&c->w_Qinv, sizeof(double) * K * MM) != hipSuccess ||
+        hipMalloc(&c->w_RW, sizeof(double) * K * nu * (nu + nx)) != hipSuccess) {
+      mpcpcg_destroy(c.release());
+      return MPCPCG_ENOMEM;
+    }
+    *out = c.release();
+    return MPCPCG_OK;
+  }
+  const size_t qb = sizeof(double) * K * nx * nx;
+  const size_t rb = sizeof(double) * K * nu * (nu + nx);
   const size_t tb = tws_bytes() * (size_t)c->max_tasks;
   const size_t gb = sizeof(Gang) * (size_t)max_batch;
   if (hipMalloc(&c->qinv_ws, qb) != hipSuccess || hipMalloc(&c->rinv_ws, rb) != hipSuccess ||
@@ -331,6 +433,13 @@ int mpcpcg_destroy(mpcpcg_ctx *c) {
   if (c->tws) (void)hipFree(c->tws);
   if (c->gang) (void)hipFree(c->gang);
   if (c->queue) (void)hipFree(c->queue);
+  for (auto &kv : c->wsched) {
+    if (kv.second->d_knots) (void)hipFree(kv.second->d_knots);
+    if (kv.second->d_probs) (void)hipFree(kv.second->d_probs);
+  }
+  for (void *p : {(void *)c->w_S, (void *)c->w_Dinv, (void *)c->w_P, (void *)c->w_rhs, (void *)c->w_Qinv,
+                  (void *)c->w_RW})
+    if (p) (void)hipFree(p);
   delete c;
   return MPCPCG_OK;
 }
@@ -344,6 +453,13 @@ int mpcpcg_form_schur(mpcpcg_ctx *c, const mpcpcg_problem *p, mpcpcg_schur *out,
   if (p->N > c->max_knots) return fail(c, MPCPCG_EINVAL, "N exceeds the context limit");
   int st = check_problem_ptrs(c, p, p->N > 1);
   if (st) return st;
+  if (c->wide) {
+    if (!out->S || !out->Pinv || !out->gamma)
+      return fail(c, MPCPCG_EINVAL, "the nx=28 path writes S, Pinv and gamma together: none may be NULL");
+    mpc::wide::WArgs w = wide_args(c, p, nullptr);
+    w.S_out = out->S; w.P_out = out->Pinv; w.gam_out = out->gamma;
+    return wide_run(c, std::vector<int64_t>{0, p->N}, w, true, s);
+  }
   KArgs a = base_args(c, p, nullptr);
   a.S_out = out->S;
   a.P_out = out->Pinv;
@@ -362,6 +478,11 @@ int mpcpcg_solve(mpcpcg_ctx *c, const mpcpcg_problem *p, const mpcpcg_opts *o, f
   if ((st = check_opts(c, o))) return st;
   if (!lambda || !dx || !stats || (p->N > 1 && !du))
     return fail(c, MPCPCG_EINVAL, "lambda, dx, du and stats must be non-NULL");
+  if (c->wide) {
+    mpc::wide::WArgs w = wide_args(c, p, o);
+    w.lam = lambda; w.dx = dx; w.du = du; w.stats = stats;
+    return wide_run(c, std::vector<int64_t>{0, p->N}, w, false, s);
+  }
   KArgs a = base_args(c, p, o);
   a.lam = lambda; a.dx = dx; a.du = du; a.stats = stats;
   return launch_single(c, a, p->N, single_kpw(c, p->N), mpc::kForward, s);
@@ -377,6 +498,11 @@ int mpcpcg_solve_batched(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const
   if (!lambda || !dx || !stats || (off[batch] > batch && !du))
     return fail(c, MPCPCG_EINVAL, "lambda, dx, du and stats must be non-NULL");
   std::vector<int64_t> key(off, off + batch + 1);
+  if (c->wide) {
+    mpc::wide::WArgs w = wide_args(c, p, o);
+    w.lam = lambda; w.dx = dx; w.du = du; w.stats = stats;
+    return wide_run(c, key, w, false, s);
+  }
   Schedule *sc = nullptr;
   if ((st = get_schedule(c, key, pick_kpw(c, key), &sc))) return st;
   KArgs a = base_args(c, p, o);
@@ -399,6 +525,16 @@ int mpcpcg_backward(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const mpcp
   if (ctrl && (!du || !dR || !dA || !dB || !dr))
     return fail(c, MPCPCG_EINVAL, "du, dR, dA, dB and dr must be non-NULL when a horizon exceeds one knot");
   std::vector<int64_t> key(off, off + batch + 1);
+  if (c->wide) {
+    mpc::wide::WArgs w = wide_args(c, p, o);
+    w.warm = 0;
+    w.adjoint = 1;
+    w.lam_in = lambda; w.dx_in = dx; w.du_in = du;
+    w.gl = gl; w.gx = gx; w.gu = gu;
+    w.dQ = dQ; w.dR = dR; w.dA = dA; w.dB = dB; w.dq = dq; w.dr = dr; w.dx0 = dx0; w.de = de;
+    w.dgamma = dgamma; w.stats = stats;
+    return wide_run(c, key, w, false, s);
+  }
   Schedule *sc = nullptr;
   if ((st = get_schedule(c, key, pick_kpw(c, key), &sc))) return st;
   KArgs a = base_args(c, p, o);
@@ -431,6 +567,10 @@ int mpcpcg_autotune(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const mpcp
   if (st) return st;
   if ((st = check_opts(c, o))) return st;
   if (o->warm_start) return fail(c, MPCPCG_EINVAL, "autotune runs cold solves (warm_start must be 0)");
+  if (c->wide) {  // one workgroup shape on the nx=28 path
+    if (kpw_out) *kpw_out = 0;
+    return MPCPCG_OK;
+  }
   std::vector<int64_t> key(off, off + batch + 1);
   const int saved = c->kpw_override;
   hipEvent_t e0, e1;
