@@ -24,14 +24,39 @@ _lib = None
 OK, NOT_CONVERGED, BREAKDOWN = 0, 1, 2
 
 
+def compile_source(src: str, out: str) -> str:
+    """gcc -O2 -fopenmp a C oracle source file into a shared library."""
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c99",
+                           "-o", tmp, src, "-lm"])
+    os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (-O2, OpenMP).  Returns the library path."""
     if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c99",
-                               "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+        compile_source(_SRC, _LIB)
     return _LIB
+
+
+def configure(lib):
+    """Declare the argument types of an oracle library handle (returns it)."""
+    d, i, i64 = C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_int64)
+    ci = C.c_int
+    lib.orc_form.argtypes = [ci, ci, ci] + [d] * 8 + [d, d, d]
+    lib.orc_pcg.argtypes = [ci, ci, d, d, d, C.c_double, ci, d, i, d, d]
+    lib.orc_solve.argtypes = [ci, ci, ci] + [d] * 8 + [C.c_double, ci, d, d, d, i, d, d]
+    lib.orc_backward.argtypes = ([ci, ci, ci] + [d] * 8 + [C.c_double, ci] + [d] * 6 +
+                                  [d] * 9 + [i, d])
+    lib.orc_solve_batch.argtypes = ([ci, ci, ci, i64] + [d] * 8 + [C.c_double, ci] +
+                                     [d, d, d, i, d, i, ci])
+    lib.orc_backward_batch.argtypes = ([ci, ci, ci, i64] + [d] * 8 + [C.c_double, ci] +
+                                        [d] * 6 + [d] * 9 + [i, d, i, ci])
+    for f in (lib.orc_form, lib.orc_pcg, lib.orc_solve, lib.orc_backward,
+              lib.orc_solve_batch, lib.orc_backward_batch):
+        f.restype = C.c_int
+    return lib
 
 
 def _load():
@@ -39,21 +64,7 @@ def _load():
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build()
-        _lib = C.CDLL(_LIB)
-        d, i, i64 = C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_int64)
-        ci = C.c_int
-        _lib.orc_form.argtypes = [ci, ci, ci] + [d] * 8 + [d, d, d]
-        _lib.orc_pcg.argtypes = [ci, ci, d, d, d, C.c_double, ci, d, i, d, d]
-        _lib.orc_solve.argtypes = [ci, ci, ci] + [d] * 8 + [C.c_double, ci, d, d, d, i, d, d]
-        _lib.orc_backward.argtypes = ([ci, ci, ci] + [d] * 8 + [C.c_double, ci] + [d] * 6 +
-                                      [d] * 9 + [i, d])
-        _lib.orc_solve_batch.argtypes = ([ci, ci, ci, i64] + [d] * 8 + [C.c_double, ci] +
-                                         [d, d, d, i, d, i, ci])
-        _lib.orc_backward_batch.argtypes = ([ci, ci, ci, i64] + [d] * 8 + [C.c_double, ci] +
-                                            [d] * 6 + [d] * 9 + [i, d, i, ci])
-        for f in (_lib.orc_form, _lib.orc_pcg, _lib.orc_solve, _lib.orc_backward,
-                  _lib.orc_solve_batch, _lib.orc_backward_batch):
-            f.restype = C.c_int
+        _lib = configure(C.CDLL(_LIB))
     return _lib
 
 

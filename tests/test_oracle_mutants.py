@@ -1,0 +1,136 @@
+"""Planted mistakes in the CPU oracle must be caught by its pins.
+
+Each case compiles a copy of oracle/schur_pcg.c with one plausible mistake (a dropped term,
+a wrong sign, a transposed operand, a wrong stopping rule, ...) and runs a battery of the
+checks that pin the oracle: the dense definition of S and gamma, the KKT / Riccati solution,
+the preconditioner identity, the first-crossing stopping rule, exact rational PCG and the
+dense adjoint.  Every mutant must fail at least one of them (and the unmodified source must
+pass all of them).  Everything runs on the CPU.
+"""
+import ctypes
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import exact, kkt
+from oracle import ref as orc
+from paper_2309_08079_amd import synth
+
+SRC = os.path.join(os.path.dirname(orc.__file__), "schur_pcg.c")
+
+MUTANTS = {
+    "phi_sign": ("phi[i * nx + j] = -T[i * nx + j];", "phi[i * nx + j] = T[i * nx + j];"),
+    "theta_drops_Qinv_next": ("theta[t] += V[t] + Qik1[t];", "theta[t] += V[t];"),
+    "theta_A_not_transposed": ("matmul(nx, nx, nx, T, 0, Ak, 1, theta);", "matmul(nx, nx, nx, T, 0, Ak, 0, theta);"),
+    "gamma0_x0_sign": ("for (int i = 0; i < nx; ++i) gam[i] += p->x0[i];", "for (int i = 0; i < nx; ++i) gam[i] -= p->x0[i];"),
+    "gamma_defect_sign": ("g1[i] += v[i] - (p->e ? p->e[(size_t)k * nx + i] : 0.0);", "g1[i] += v[i] + (p->e ? p->e[(size_t)k * nx + i] : 0.0);"),
+    "zeta_drops_control_term": ("for (int i = 0; i < nx; ++i) g1[i] = -v[i] - w[i];", "for (int i = 0; i < nx; ++i) g1[i] = -v[i];"),
+    "precond_offdiag_sign": ("for (size_t t = 0; t < bs; ++t) dst[t] = -V[t];", "for (size_t t = 0; t < bs; ++t) dst[t] = V[t];"),
+    "alpha_scaled": ("const double alpha = eta / pSp;", "const double alpha = 0.9 * eta / pSp;"),
+    "beta_inverted": ("const double beta = eta_new / eta;", "const double beta = eta / eta_new;"),
+    "stop_rule_unsquared": ("const double tau = eps * eps * eta_ref;", "const double tau = eps * eta_ref;"),
+    "recon_lambda_sign": ("for (int i = 0; i < nx; ++i) t[i] = gx[(size_t)k * nx + i] - lam[(size_t)k * nx + i];",
+                          "for (int i = 0; i < nx; ++i) t[i] = gx[(size_t)k * nx + i] + lam[(size_t)k * nx + i];"),
+    "recon_B_not_transposed": ("matvec(nu, nx, p->B + (size_t)k * nx * nu, 1, lam + (size_t)(k + 1) * nx, s);",
+                               "matvec(nu, nx, p->B + (size_t)k * nx * nu, 0, lam + (size_t)(k + 1) * nx, s);"),
+    "adjoint_dA_sign": ("dA[(size_t)k * bs + i * nx + j] = l1[i] * ax[j] + m1[i] * xk[j];",
+                        "dA[(size_t)k * bs + i * nx + j] = l1[i] * ax[j] - m1[i] * xk[j];"),
+    "adjoint_dQ_unsymmetrised": ("dQ[(size_t)k * bs + i * nx + j] = 0.5 * (ax[i] * xk[j] + ax[j] * xk[i]);",
+                                 "dQ[(size_t)k * bs + i * nx + j] = ax[i] * xk[j];"),
+    "adjoint_dx0_sign": ("if (dx0) memcpy(dx0, mu, nx * sizeof(double));",
+                         "if (dx0) for (int i = 0; i < nx; ++i) dx0[i] = -mu[i];"),
+}
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300)
+
+
+def battery():
+    """Pin checks on the library currently loaded in oracle.ref; returns failed check names."""
+    failed = []
+    p = synth.problem(6, seed=91, defects=True)
+    try:
+        S, P, g = orc.form(p)
+        Sd, gd = kkt.schur_dense(p)
+        if np.abs(kkt.blocks_to_dense(S) - Sd).max() > 1e-12 * np.abs(Sd).max() or np.abs(g - gd).max() > 1e-12 * np.abs(gd).max():
+            failed.append("schur_dense")
+        Sdn, Pdn = kkt.blocks_to_dense(S), kkt.blocks_to_dense(P)
+        D = np.zeros_like(Sdn)
+        for b in range(6):
+            D[b * 14:(b + 1) * 14, b * 14:(b + 1) * 14] = S[b, 1]
+        DiE = np.linalg.solve(D, Sdn - D)
+        if np.abs(Pdn @ Sdn - (np.eye(len(Sdn)) - DiE @ DiE)).max() > 1e-10:
+            failed.append("preconditioner_identity")
+    except ValueError:
+        failed.append("form_status")
+    o = orc.solve(p, eps=1e-14, max_iter=500)
+    ex = kkt.kkt_solve(p)
+    if o["status"] != orc.OK or rel(o["lam"], ex["lam"]) > 1e-9 or rel(o["dx"], ex["dx"]) > 1e-9 or rel(o["du"], ex["du"]) > 1e-9:
+        failed.append("kkt_solution")
+    # first-crossing stopping rule against eta_ref from the dense definitions
+    q = synth.problem(20, seed=92)
+    o = orc.solve(q, eps=1e-6, trace=True)
+    Sq, Pq, gq = orc.form(q)
+    eta_ref = float(gq.ravel() @ kkt.blocks_to_dense(Pq) @ gq.ravel())
+    ratios = np.sqrt(np.abs(o["eta"]) / eta_ref)
+    if not (ratios[-1] < 1e-6 and np.all(ratios[:-1] >= 1e-6)):
+        failed.append("stopping_rule")
+    # exact rational PCG trace
+    rng = np.random.default_rng(7)
+    N, nx, nu = 4, 2, 1
+    Q = [[[Fraction(int(v)) for v in row] for row in (np.eye(nx) * 3 + 1)] for _ in range(N)]
+    R = [[[Fraction(2)]] for _ in range(N - 1)]
+    A = [[[Fraction(int(i == j)) + Fraction(int(rng.integers(-2, 3)), 10) for j in range(nx)] for i in range(nx)] for _ in range(N - 1)]
+    B = [[[Fraction(int(rng.integers(-3, 4)), 10)] for _ in range(nx)] for _ in range(N - 1)]
+    qv = [[Fraction(int(v)) for v in rng.integers(-3, 4, nx)] for _ in range(N)]
+    rv = [[Fraction(int(rng.integers(-3, 4)))] for _ in range(N - 1)]
+    x0 = [Fraction(1), Fraction(-2)]
+    Se, Pe, ge = exact.form(Q, R, A, B, qv, rv, x0)
+    lam_e, it_e, etas = exact.pcg(Se, Pe, ge)
+    npf = lambda L: np.array([[float(x) for x in r] for r in L])
+    prob = dict(Q=np.stack([npf(m) for m in Q]), R=np.stack([npf(m) for m in R]), A=np.stack([npf(m) for m in A]),
+                B=np.stack([npf(m) for m in B]), q=npf(qv), r=npf(rv), x0=np.array([float(x) for x in x0]))
+    oe = orc.solve(prob, eps=1e-15, max_iter=it_e + 3, trace=True)
+    n = min(len(oe["eta"]), len(etas)) - 1
+    et = np.array([float(x) for x in etas[:n]])
+    if not np.allclose(oe["eta"][:n], et, rtol=1e-9, atol=1e-12 * et[0]):
+        failed.append("exact_trace")
+    # adjoint against the dense KKT adjoint
+    f = orc.solve(p, eps=1e-14, max_iter=500)
+    gl = 2 * f["lam"]
+    b = orc.backward(p, f, gl, eps=1e-14, max_iter=500)
+    d = kkt.adjoint_dense(p, gl)
+    for k in ("dQ", "dR", "dA", "dB", "dq", "dr", "dx0", "de"):
+        if rel(b[k], d[k]) > 1e-8:
+            failed.append("adjoint_" + k)
+            break
+    return failed
+
+
+def _with_library(path):
+    saved = orc._lib
+    orc._lib = orc.configure(ctypes.CDLL(path))
+    try:
+        return battery()
+    finally:
+        orc._lib = saved
+
+
+def test_unmodified_oracle_passes_battery(tmp_path):
+    out = orc.compile_source(SRC, str(tmp_path / "base.so"))
+    assert _with_library(out) == []
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(tmp_path, name):
+    find, repl = MUTANTS[name]
+    text = open(SRC).read()
+    assert text.count(find) == 1, "mutation site not unique: " + name
+    src = tmp_path / (name + ".c")
+    src.write_text(text.replace(find, repl))
+    out = orc.compile_source(str(src), str(tmp_path / (name + ".so")))
+    failed = _with_library(out)
+    assert failed, "planted mistake %s passed every pin" % name
