@@ -248,7 +248,7 @@ def main():
         "iters_forward_mean": float(it_f.mean()),
         "iters_adjoint_mean": float(it_b.mean()),
         "kernel_ms": {"forward": fwd_ms, "adjoint": adj_ms},
-        "roofline": {"bound": "alu", "kernel": "pcg_kernel<14,7,32,%s>" % dom_name,
+        "roofline": {"bound": "alu", "kernel": "pcg_kernel<14,7,16,%s>" % dom_name,
                      "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_VALU_TFLOPS, "traffic": measured_traffic(dom_name)},
         "cpu_baseline": cpu,

@@ -160,7 +160,7 @@ KArgs base_args(mpcpcg_ctx *c, const mpcpcg_problem *p, const mpcpcg_opts *o) {
 
 int single_kpw(mpcpcg_ctx *c, int N) {
   if (c->kpw_override) return c->kpw_override;
-  return 32;
+  return N <= 32 ? 32 : 16;   // one workgroup when it fits, else the 3-waves/SIMD shape
 }
 
 int launch_single(mpcpcg_ctx *c, KArgs &a, int N, int kpw, int mode, hipStream_t s) {
@@ -199,7 +199,7 @@ int pick_kpw(mpcpcg_ctx *c, const std::vector<int64_t> &off) {
   if (c->kpw_override) return c->kpw_override;
   auto it = c->tuned.find(off);
   if (it != c->tuned.end()) return it->second;
-  return 32;
+  return 16;
 }
 
 int get_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, int kpw, Schedule **out) {

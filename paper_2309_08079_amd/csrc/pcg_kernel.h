@@ -56,7 +56,7 @@ struct TaskWS {       // per task; read by the other parts of the same gang
   // for barrier n; written after everything the part publishes for that barrier.
   uint64_t flag;
   uint64_t pad[7];
-  double red[2][kMaxWaves][2];   // [parity][wave][value] partial sums of this part's waves
+  double red[2][2][kMaxWaves];   // [parity][value][wave] partial sums of this part's waves
   double hv[2][2][2][kGroup];    // [parity][channel][side][lane] double vector halos
   float hf[2][2][kGroup];        // [parity][side][lane] float vector halos
   double hm[2][NX][kGroup];      // [side][row][col] matrix halo (one use, in formation)
@@ -103,10 +103,14 @@ __device__ __forceinline__ double uni(double v) {
 }
 
 
-// Register budget: the S row (84 VGPRs) and Phi^-1 row (42) stay resident for the whole
-// solve; 2 waves per SIMD (256 VGPRs) leaves room for the formation's temporaries.
+// Register budget: the FP64 S row (84 VGPRs) stays resident for the whole solve and the
+// FP32 Phi^-1 row lives in LDS; the occupancy target sets how many knots stay resident.
+// A 32-knot workgroup (8 waves) fits only two waves per SIMD anyway, so it keeps the full
+// 256-VGPR budget; smaller shapes target three.
+template <int KPW>
+constexpr int waves_per_eu() { return KPW >= 32 ? 2 : 3; }
 template <int NX, int NU, int KPW, int MODE>
-__global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_eu(2, 2)))
+__global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_eu(waves_per_eu<KPW>(), waves_per_eu<KPW>())))
     pcg_kernel(const KArgs a) {
   static_assert(NX == 14 && NU <= NX, "the fused row kernels are written for 14-row blocks");
   constexpr int NT = KPW * kGroup;
@@ -115,7 +119,15 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
 
   __shared__ double ex_d[2][KPW + 2][kGroup];  // vector exchange, slot s+1 is knot s
   __shared__ float ex_f[KPW + 2][kGroup];
-  __shared__ double ex_m[KPW + 2][NX][kGroup];  // matrix exchange (formation only)
+  // One LDS region serves two phases: the D^-1 row exchange of the formation, then the
+  // FP32 Phi^-1 rows for the rest of the solve (row r of knot slot s at
+  // pl[(s * 16 + r) * kPRow], blocks (b,b-1), (b,b), (b,b+1) at offsets 0, 14, 28).
+  constexpr int kPRow = 44;
+  constexpr size_t kExBytes = sizeof(double) * (KPW + 2) * NX * kGroup;
+  constexpr size_t kPlBytes = sizeof(float) * KPW * kGroup * kPRow;
+  __shared__ __attribute__((aligned(16))) unsigned char big[kExBytes > kPlBytes ? kExBytes : kPlBytes];
+  auto ex_m = reinterpret_cast<double (*)[NX][kGroup]>(big);
+  float *const pl = reinterpret_cast<float *>(big);
   __shared__ double red_w[2][2][NW];           // [phase][value][wave]
   __shared__ double tot[2];
   __shared__ int sh_task;
@@ -214,10 +226,11 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
           int ab = 0, polls = 0;
           for (int g0 = 0; g0 < G && !ab; g0 += 64) {
             const int g = g0 + wl;
+            bool seen = g >= G;  // a lane stops polling once its part has arrived
             while (true) {
-              const bool ok = g >= G || __hip_atomic_load(&tws[pd.t0 + (g < G ? g : 0)].flag, __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_AGENT) >= epoch;
-              if (__ballot(ok) == ~0ull) break;
+              if (!seen)
+                seen = __hip_atomic_load(&tws[pd.t0 + g].flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+              if (__ballot(seen) == ~0ull) break;
               __builtin_amdgcn_s_sleep(1);
               if ((++polls & 63) == 0) {
                 if (__hip_atomic_load(&gang->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ab = 1; break; }
@@ -250,11 +263,17 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
           // part computes bit-identical totals
           double v0 = 0.0, v1 = 0.0;
           if (!ab && NR > 0) {
-            for (int idx = wl; idx < G * NW; idx += 64) {
-              const int g = idx / NW, w = idx - g * NW;
-              v0 += __hip_atomic_load(&tws[pd.t0 + g].red[par][w][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              if (NR > 1)
-                v1 += __hip_atomic_load(&tws[pd.t0 + g].red[par][w][1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int g = wl; g < G; g += 64) {  // lane g sums part g's waves in order
+              const double *r0 = tws[pd.t0 + g].red[par][0];
+              const double *r1 = tws[pd.t0 + g].red[par][1];
+              double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+              for (int w = 0; w < NW; ++w) {
+                s0 += __hip_atomic_load(&r0[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (NR > 1) s1 += __hip_atomic_load(&r1[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              }
+              v0 += s0;
+              v1 += s1;
             }
           }
           const double w0 = wave_sum(v0), w1 = wave_sum(v1);
@@ -317,7 +336,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       if (wl == 0) {
         red_w[ph][v][wave] = s;
         if (multi)
-          __hip_atomic_store(&tws[my_t].red[nsync & 1][wave][v], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&tws[my_t].red[nsync & 1][v][wave], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     };
 
@@ -512,8 +531,36 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         if (a.gam_out) a.gam_out[kb * NX + lane] = (float)rhs;
       }
     } else {
+      // Phi^-1 rows move to LDS for the solve (the D^-1 exchange above used the same bytes)
+      __syncthreads();
+      {
+        float *row = pl + (slot * kGroup + lane) * kPRow;
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+          row[j] = Pm[j];
+          row[NX + j] = Pd[j];
+          row[2 * NX + j] = Pp[j];
+        }
+      }
       // ================================================================== PCG
       refresh();
+      // r~ row = Phi^-1 row . [x(b-1), x(b), x(b+1)], the row read back from LDS one block
+      // at a time so that only 14 of its values occupy registers
+      auto precond_row = [&](float xm, float x0v, float xp) {
+        const float *row = pl + (slot * kGroup + lane) * kPRow;
+        float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
+        float m[NX];
+#pragma unroll
+        for (int j = 0; j < NX; ++j) m[j] = row[j];
+        row_fma14_f32(acc0, xm, m);
+#pragma unroll
+        for (int j = 0; j < NX; ++j) m[j] = row[NX + j];
+        row_fma14_f32(acc1, x0v, m);
+#pragma unroll
+        for (int j = 0; j < NX; ++j) m[j] = row[2 * NX + j];
+        row_fma14_f32(acc2, xp, m);
+        return (acc0 + acc1) + acc2;
+      };
       const int max_iter = a.max_iter > 0 ? a.max_iter : N * NX;
       double lam = 0.0, r = rhs, p, pm, pp, rm, rp;
       // eta_ref = rhs^T Phi^-1 rhs
@@ -522,14 +569,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       put_d(1, lam);
       sync_point(2, 0, 0, 0, 0);
       const double gm = ex_d[0][slot][lane], gp = ex_d[0][slot + 2][lane];
-      float gt = 0.f;
-      {
-        float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
-        row_fma14_f32(acc0, (float)gm, Pm);
-        row_fma14_f32(acc1, (float)rhs, Pd);
-        row_fma14_f32(acc2, (float)gp, Pp);
-        gt = (acc0 + acc1) + acc2;
-      }
+      const float gt = precond_row((float)gm, (float)rhs, (float)gp);
       const bool warm = (MODE == kForward) && a.warm;
       rm = gm;
       rp = gp;
@@ -546,16 +586,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         rm = ex_d[0][slot][lane];
         rp = ex_d[0][slot + 2][lane];
       }
-      float rt;
-      if (warm) {
-        float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
-        row_fma14_f32(acc0, (float)rm, Pm);
-        row_fma14_f32(acc1, (float)r, Pd);
-        row_fma14_f32(acc2, (float)rp, Pp);
-        rt = (acc0 + acc1) + acc2;
-      } else {
-        rt = gt;
-      }
+      const float rt = warm ? precond_row((float)rm, (float)r, (float)rp) : gt;
       // eta_0 = r^T r~ and eta_ref = rhs^T Phi^-1 rhs; p = r~ (halo via the float channel)
       put_red(0, 0, r * (double)rt);
       put_red(0, 1, rhs * (double)gt);
@@ -597,11 +628,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
           rm = __builtin_fma(-alpha, Ym, rm);
           rp = __builtin_fma(-alpha, Yp, rp);
           // ---- phase B: r~ = Phi^-1 r, eta' = r^T r~
-          float c0 = 0.f, c1 = 0.f, c2 = 0.f;
-          row_fma14_f32(c0, (float)rm, Pm);
-          row_fma14_f32(c1, (float)r, Pd);
-          row_fma14_f32(c2, (float)rp, Pp);
-          const float rtn = (c0 + c1) + c2;
+          const float rtn = precond_row((float)rm, (float)r, (float)rp);
           put_red(1, 0, r * (double)rtn);
           put_f(rtn);
               sync_point(0, 1, 0, 1, 1);
