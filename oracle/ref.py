@@ -6,7 +6,8 @@ returns float64 results.
 
 Follows MPCGPU Section III-B (Schur complement, eq. "schur", "trajoptSchur_1/2"),
 Section IV-A (symmetric stair preconditioner) and Algorithm 1 (PCG), with the stopping
-rule sqrt(eta'/eta_ref) < eps, eta_ref = gamma^T Phi^-1 gamma.
+rule sqrt(eta'/eta_ref) < eps, eta_ref = gamma^T Phi^-1 gamma (stop="relative"), or the
+absolute test eta' < eps printed in Algorithm 1 (stop="absolute").
 """
 from __future__ import annotations
 
@@ -45,13 +46,13 @@ def configure(lib):
     d, i, i64 = C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_int64)
     ci = C.c_int
     lib.orc_form.argtypes = [ci, ci, ci] + [d] * 8 + [d, d, d]
-    lib.orc_pcg.argtypes = [ci, ci, d, d, d, C.c_double, ci, d, i, d, d]
-    lib.orc_solve.argtypes = [ci, ci, ci] + [d] * 8 + [C.c_double, ci, d, d, d, i, d, d]
-    lib.orc_backward.argtypes = ([ci, ci, ci] + [d] * 8 + [C.c_double, ci] + [d] * 6 +
+    lib.orc_pcg.argtypes = [ci, ci, d, d, d, C.c_double, ci, ci, d, i, d, d]
+    lib.orc_solve.argtypes = [ci, ci, ci] + [d] * 8 + [C.c_double, ci, ci, d, d, d, i, d, d]
+    lib.orc_backward.argtypes = ([ci, ci, ci] + [d] * 8 + [C.c_double, ci, ci] + [d] * 6 +
                                   [d] * 9 + [i, d])
-    lib.orc_solve_batch.argtypes = ([ci, ci, ci, i64] + [d] * 8 + [C.c_double, ci] +
+    lib.orc_solve_batch.argtypes = ([ci, ci, ci, i64] + [d] * 8 + [C.c_double, ci, ci] +
                                      [d, d, d, i, d, i, ci])
-    lib.orc_backward_batch.argtypes = ([ci, ci, ci, i64] + [d] * 8 + [C.c_double, ci] +
+    lib.orc_backward_batch.argtypes = ([ci, ci, ci, i64] + [d] * 8 + [C.c_double, ci, ci] +
                                         [d] * 6 + [d] * 9 + [i, d, i, ci])
     for f in (lib.orc_form, lib.orc_pcg, lib.orc_solve, lib.orc_backward,
               lib.orc_solve_batch, lib.orc_backward_batch):
@@ -66,6 +67,12 @@ def _load():
             build()
         _lib = configure(C.CDLL(_LIB))
     return _lib
+
+
+def _stop(stop):
+    if stop not in ("relative", "absolute"):
+        raise ValueError("stop must be 'relative' or 'absolute', not %r" % (stop,))
+    return 1 if stop == "absolute" else 0
 
 
 def _d(a):
@@ -102,7 +109,7 @@ def form(prob):
     return S, P, g
 
 
-def pcg(S, P, gamma, eps=1e-6, max_iter=0, lam0=None, trace=False):
+def pcg(S, P, gamma, eps=1e-6, max_iter=0, lam0=None, trace=False, stop="relative"):
     """Algorithm 1 on given blocks.  Returns dict(lam, iters, ratio, status[, eta])."""
     S, P, gamma = _d(S), _d(P), _d(gamma)
     N, _, nx, _ = S.shape
@@ -110,7 +117,7 @@ def pcg(S, P, gamma, eps=1e-6, max_iter=0, lam0=None, trace=False):
     lam = np.zeros((N, nx)) if lam0 is None else _d(lam0).copy()
     it, ratio = C.c_int(0), C.c_double(0)
     tr = np.full(max_iter + 1, np.nan) if trace else None
-    st = _load().orc_pcg(nx, N, _p(S), _p(P), _p(gamma), eps, max_iter, _p(lam), C.byref(it),
+    st = _load().orc_pcg(nx, N, _p(S), _p(P), _p(gamma), eps, _stop(stop), max_iter, _p(lam), C.byref(it),
                          C.byref(ratio), _p(tr))
     out = dict(lam=lam, iters=it.value, ratio=ratio.value, status=st)
     if trace:
@@ -118,7 +125,7 @@ def pcg(S, P, gamma, eps=1e-6, max_iter=0, lam0=None, trace=False):
     return out
 
 
-def solve(prob, eps=1e-6, max_iter=0, lam0=None, trace=False):
+def solve(prob, eps=1e-6, max_iter=0, lam0=None, trace=False, stop="relative"):
     """Form + PCG + primal step.  Returns dict(lam, dx, du, iters, ratio, status[, eta])."""
     nx, nu, N = _dims(prob)
     a = _args(prob)
@@ -127,7 +134,7 @@ def solve(prob, eps=1e-6, max_iter=0, lam0=None, trace=False):
     dx = np.zeros((N, nx)); du = np.zeros((max(N - 1, 0), nu))
     it, ratio = C.c_int(0), C.c_double(0)
     tr = np.full(mi + 1, np.nan) if trace else None
-    st = _load().orc_solve(nx, nu, N, *[_p(x) for x in a], eps, mi, _p(lam), _p(dx), _p(du),
+    st = _load().orc_solve(nx, nu, N, *[_p(x) for x in a], eps, _stop(stop), mi, _p(lam), _p(dx), _p(du),
                            C.byref(it), C.byref(ratio), _p(tr))
     if st < 0:
         raise ValueError("oracle solve failed (status %d)" % st)
@@ -137,7 +144,7 @@ def solve(prob, eps=1e-6, max_iter=0, lam0=None, trace=False):
     return out
 
 
-def backward(prob, fwd, gl, gx=None, gu=None, eps=1e-6, max_iter=0):
+def backward(prob, fwd, gl, gx=None, gu=None, eps=1e-6, max_iter=0, stop="relative"):
     """Adjoint for L(lambda, dx, du).  Returns dict of gradients (dQ, dR, dA, dB, dq, dr,
     dx0, de, mu) plus iters/ratio/status of the adjoint PCG."""
     nx, nu, N = _dims(prob)
@@ -150,7 +157,7 @@ def backward(prob, fwd, gl, gx=None, gu=None, eps=1e-6, max_iter=0):
     gxd = None if gx is None else _d(gx)
     gud = None if gu is None else _d(gu)
     st = _load().orc_backward(
-        nx, nu, N, *[_p(x) for x in a], eps, max_iter, _p(_d(fwd["lam"])), _p(_d(fwd["dx"])),
+        nx, nu, N, *[_p(x) for x in a], eps, _stop(stop), max_iter, _p(_d(fwd["lam"])), _p(_d(fwd["dx"])),
         _p(_d(fwd["du"])), _p(_d(gl)), _p(gxd), _p(gud),
         *[_p(out[k]) for k in ("dQ", "dR", "dA", "dB", "dq", "dr", "dx0", "de", "mu")],
         C.byref(it), C.byref(ratio))
@@ -160,7 +167,7 @@ def backward(prob, fwd, gl, gx=None, gu=None, eps=1e-6, max_iter=0):
     return out
 
 
-def solve_batch(packed, off, eps=1e-6, max_iter=0, threads=1):
+def solve_batch(packed, off, eps=1e-6, max_iter=0, threads=1, stop="relative"):
     """Batched forward solve on the packed layout; OpenMP over problems."""
     off = np.ascontiguousarray(off, dtype=np.int64)
     B = len(off) - 1
@@ -172,13 +179,14 @@ def solve_batch(packed, off, eps=1e-6, max_iter=0, threads=1):
     lam = np.zeros((K, nx)); dx = np.zeros((K, nx)); du = np.zeros((max(K - B, 0), nu))
     iters = np.zeros(B, dtype=np.int32); ratio = np.zeros(B); status = np.zeros(B, dtype=np.int32)
     _load().orc_solve_batch(nx, nu, B, off.ctypes.data_as(C.POINTER(C.c_int64)),
-                            *[_p(x) for x in a], eps, max_iter, _p(lam), _p(dx), _p(du),
+                            *[_p(x) for x in a], eps, _stop(stop), max_iter, _p(lam), _p(dx), _p(du),
                             iters.ctypes.data_as(C.POINTER(C.c_int)), _p(ratio),
                             status.ctypes.data_as(C.POINTER(C.c_int)), threads)
     return dict(lam=lam, dx=dx, du=du, iters=iters, ratio=ratio, status=status)
 
 
-def backward_batch(packed, off, fwd, gl, gx=None, gu=None, eps=1e-6, max_iter=0, threads=1):
+def backward_batch(packed, off, fwd, gl, gx=None, gu=None, eps=1e-6, max_iter=0, threads=1,
+                   stop="relative"):
     """Batched adjoint on the packed layout; OpenMP over problems."""
     off = np.ascontiguousarray(off, dtype=np.int64)
     B = len(off) - 1
@@ -194,7 +202,7 @@ def backward_batch(packed, off, fwd, gl, gx=None, gu=None, eps=1e-6, max_iter=0,
     gxd = None if gx is None else _d(gx)
     gud = None if gu is None else _d(gu)
     _load().orc_backward_batch(
-        nx, nu, B, off.ctypes.data_as(C.POINTER(C.c_int64)), *[_p(x) for x in a], eps, max_iter,
+        nx, nu, B, off.ctypes.data_as(C.POINTER(C.c_int64)), *[_p(x) for x in a], eps, _stop(stop), max_iter,
         _p(_d(fwd["lam"])), _p(_d(fwd["dx"])), _p(_d(fwd["du"])), _p(_d(gl)), _p(gxd), _p(gud),
         *[_p(out[k]) for k in ("dQ", "dR", "dA", "dB", "dq", "dr", "dx0", "de", "mu")],
         iters.ctypes.data_as(C.POINTER(C.c_int)), _p(ratio),

@@ -26,10 +26,11 @@
  *   Preconditioner (Section IV-A, symmetric stair): Phi^-1 = D^-1 - D^-1 E D^-1 with
  *     D the block diagonal of S and E = S - D, i.e. Phi^-1_bb = D_b^-1 and
  *     Phi^-1_{b,b+-1} = -D_b^-1 S_{b,b+-1} D_{b+-1}^-1.
- *   PCG: Algorithm 1, stopped at the first main-loop iteration with
- *     eta' < eps^2 * eta_ref, eta_ref = gamma^T Phi^-1 gamma (relative preconditioned
- *     residual sqrt(eta'/eta_ref) < eps).  The initial iterate is also tested (this only
- *     matters when the start already satisfies the rule, e.g. r = 0).
+ *   PCG: Algorithm 1, stopped at the first main-loop iteration with eta' < tau, where
+ *     tau = eps^2 * eta_ref, eta_ref = gamma^T Phi^-1 gamma (relative preconditioned
+ *     residual sqrt(eta'/eta_ref) < eps; stop_abs = 0), or tau = eps (the absolute test
+ *     eta' < eps that Algorithm 1 prints; stop_abs = 1).  The initial iterate is also
+ *     tested (this only matters when the start already satisfies the rule, e.g. r = 0).
  *   Primal step (eq. "schur"): dZ = -G^-1 (g - C^T lambda).
  *
  * Storage: row-major, S and Phi^-1 as [N][3][nx][nx] with slot 0 = (b,b-1),
@@ -217,7 +218,8 @@ static int form(const orc_prob *p, const double *Qi, const double *Ri, double *S
  * and the iterate on exit.  eta_trace (optional, length max_iter+1) receives
  * eta after initialisation and after every main-loop iteration. */
 static int pcg(int nx, int N, const double *S, const double *P, const double *gam, double eps,
-               int max_iter, double *lam, int *iters, double *ratio, double *eta_trace) {
+               int stop_abs, int max_iter, double *lam, int *iters, double *ratio,
+               double *eta_trace) {
   const size_t n = (size_t)N * nx;
   double *r = malloc(n * sizeof(double)), *rt = malloc(n * sizeof(double));
   double *p = malloc(n * sizeof(double)), *Sp = malloc(n * sizeof(double));
@@ -227,7 +229,7 @@ static int pcg(int nx, int N, const double *S, const double *P, const double *ga
   /* eta_ref = gamma^T Phi^-1 gamma  (reference for the relative stopping rule) */
   bt_matvec(nx, N, P, gam, rt);
   const double eta_ref = dot((int)n, gam, rt);
-  const double tau = eps * eps * eta_ref;
+  const double tau = stop_abs ? eps : eps * eps * eta_ref;
 
   /* initialisation: r = gamma - S lam; r~ = p = Phi^-1 r; eta = r^T r~ */
   bt_matvec(nx, N, S, lam, Sp);
@@ -318,16 +320,16 @@ int orc_form(int nx, int nu, int N, const double *Q, const double *R, const doub
 
 /* PCG on a given S, Phi^-1, gamma. */
 int orc_pcg(int nx, int N, const double *S, const double *P, const double *gam, double eps,
-            int max_iter, double *lam, int *iters, double *ratio, double *eta_trace) {
+            int stop_abs, int max_iter, double *lam, int *iters, double *ratio, double *eta_trace) {
   if (nx < 1 || N < 1 || max_iter < 0) return ORC_EINVAL;
-  return pcg(nx, N, S, P, gam, eps, max_iter, lam, iters, ratio, eta_trace);
+  return pcg(nx, N, S, P, gam, eps, stop_abs, max_iter, lam, iters, ratio, eta_trace);
 }
 
 /* Forward solve: form, PCG, primal step.  lam: start on entry (zeros for cold). */
 int orc_solve(int nx, int nu, int N, const double *Q, const double *R, const double *A,
               const double *B, const double *q, const double *r, const double *x0, const double *e,
-              double eps, int max_iter, double *lam, double *dx, double *du, int *iters,
-              double *ratio, double *eta_trace) {
+              double eps, int stop_abs, int max_iter, double *lam, double *dx, double *du,
+              int *iters, double *ratio, double *eta_trace) {
   if (nx < 1 || nu < 1 || N < 1) return ORC_EINVAL;
   if (max_iter <= 0) max_iter = N * nx;
   orc_prob p = mkprob(nx, nu, N, Q, R, A, B, q, r, x0, e);
@@ -341,7 +343,7 @@ int orc_solve(int nx, int nu, int N, const double *Q, const double *R, const dou
   if (Qi && Ri && S && P && gam) {
     st = knot_inverses(&p, Qi, Ri) ? ORC_BREAKDOWN : form(&p, Qi, Ri, S, P, gam);
     if (st == ORC_OK) {
-      st = pcg(nx, N, S, P, gam, eps, max_iter, lam, iters, ratio, eta_trace);
+      st = pcg(nx, N, S, P, gam, eps, stop_abs, max_iter, lam, iters, ratio, eta_trace);
       reconstruct(&p, Qi, Ri, q, r, lam, dx, du);
     }
   }
@@ -362,7 +364,8 @@ int orc_solve(int nx, int nu, int N, const double *Q, const double *R, const dou
  *   Outputs may be NULL except mu. */
 int orc_backward(int nx, int nu, int N, const double *Q, const double *R, const double *A,
                  const double *B, const double *q, const double *r, const double *x0,
-                 const double *e, double eps, int max_iter, const double *lam, const double *dx,
+                 const double *e, double eps, int stop_abs, int max_iter, const double *lam,
+                 const double *dx,
                  const double *du, const double *gl, const double *gx, const double *gu,
                  double *dQ, double *dR, double *dA, double *dB, double *dq, double *dr,
                  double *dx0, double *de, double *mu, int *iters, double *ratio) {
@@ -400,7 +403,7 @@ int orc_backward(int nx, int nu, int N, const double *Q, const double *R, const 
     free(w); free(v);
   }
   memset(mu, 0, n * sizeof(double));
-  st = pcg(nx, N, S, P, y, eps, max_iter, mu, iters, ratio, NULL);
+  st = pcg(nx, N, S, P, y, eps, stop_abs, max_iter, mu, iters, ratio, NULL);
   /* nu_1 = -G^-1 (gz - C^T mu) */
   reconstruct(&p, Qi, Ri, zx, zu, mu, n1x, n1u);
   for (int k = 0; k < N; ++k) {
@@ -443,9 +446,9 @@ out:
  * lam must hold the start (zeros for cold).  iters/status/ratio are [batch]. */
 int orc_solve_batch(int nx, int nu, int batch, const int64_t *off, const double *Q,
                     const double *R, const double *A, const double *B, const double *q,
-                    const double *r, const double *x0, const double *e, double eps, int max_iter,
-                    double *lam, double *dx, double *du, int *iters, double *ratio, int *status,
-                    int nthreads) {
+                    const double *r, const double *x0, const double *e, double eps, int stop_abs,
+                    int max_iter, double *lam, double *dx, double *du, int *iters, double *ratio,
+                    int *status, int nthreads) {
   if (nx < 1 || nu < 1 || batch < 0) return ORC_EINVAL;
   const size_t bs = (size_t)nx * nx, bu = (size_t)nu * nu, bb = (size_t)nx * nu;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1)
@@ -454,7 +457,7 @@ int orc_solve_batch(int nx, int nu, int batch, const int64_t *off, const double 
     const int N = (int)(off[b + 1] - off[b]);
     status[b] = orc_solve(nx, nu, N, Q + k0 * bs, R + c0 * bu, A + c0 * bs, B + c0 * bb,
                           q + k0 * nx, r + c0 * nu, x0 + (size_t)b * nx, e ? e + c0 * nx : NULL,
-                          eps, max_iter, lam + k0 * nx, dx + k0 * nx, du + c0 * nu, &iters[b],
+                          eps, stop_abs, max_iter, lam + k0 * nx, dx + k0 * nx, du + c0 * nu, &iters[b],
                           &ratio[b], NULL);
   }
   return ORC_OK;
@@ -464,7 +467,7 @@ int orc_solve_batch(int nx, int nu, int batch, const int64_t *off, const double 
 int orc_backward_batch(int nx, int nu, int batch, const int64_t *off, const double *Q,
                        const double *R, const double *A, const double *B, const double *q,
                        const double *r, const double *x0, const double *e, double eps,
-                       int max_iter, const double *lam, const double *dx, const double *du,
+                       int stop_abs, int max_iter, const double *lam, const double *dx, const double *du,
                        const double *gl, const double *gx, const double *gu, double *dQ,
                        double *dR, double *dA, double *dB, double *dq, double *dr, double *dx0,
                        double *de, double *mu, int *iters, double *ratio, int *status,
@@ -477,7 +480,8 @@ int orc_backward_batch(int nx, int nu, int batch, const int64_t *off, const doub
     const int N = (int)(off[b + 1] - off[b]);
     status[b] = orc_backward(
         nx, nu, N, Q + k0 * bs, R + c0 * bu, A + c0 * bs, B + c0 * bb, q + k0 * nx, r + c0 * nu,
-        x0 + (size_t)b * nx, e ? e + c0 * nx : NULL, eps, max_iter, lam + k0 * nx, dx + k0 * nx,
+        x0 + (size_t)b * nx, e ? e + c0 * nx : NULL, eps, stop_abs, max_iter, lam + k0 * nx,
+        dx + k0 * nx,
         du + c0 * nu, gl + k0 * nx, gx ? gx + k0 * nx : NULL, gu ? gu + c0 * nu : NULL,
         dQ + k0 * bs, dR + c0 * bu, dA + c0 * bs, dB + c0 * bb, dq + k0 * nx, dr + c0 * nu,
         dx0 + (size_t)b * nx, de + c0 * nx, mu + k0 * nx, &iters[b], &ratio[b]);

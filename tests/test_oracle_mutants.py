@@ -30,7 +30,10 @@ MUTANTS = {
     "precond_offdiag_sign": ("for (size_t t = 0; t < bs; ++t) dst[t] = -V[t];", "for (size_t t = 0; t < bs; ++t) dst[t] = V[t];"),
     "alpha_scaled": ("const double alpha = eta / pSp;", "const double alpha = 0.9 * eta / pSp;"),
     "beta_inverted": ("const double beta = eta_new / eta;", "const double beta = eta / eta_new;"),
-    "stop_rule_unsquared": ("const double tau = eps * eps * eta_ref;", "const double tau = eps * eta_ref;"),
+    "stop_rule_unsquared": ("const double tau = stop_abs ? eps : eps * eps * eta_ref;",
+                            "const double tau = stop_abs ? eps : eps * eta_ref;"),
+    "stop_abs_scaled": ("const double tau = stop_abs ? eps : eps * eps * eta_ref;",
+                        "const double tau = stop_abs ? eps * eta_ref : eps * eps * eta_ref;"),
     "recon_lambda_sign": ("for (int i = 0; i < nx; ++i) t[i] = gx[(size_t)k * nx + i] - lam[(size_t)k * nx + i];",
                           "for (int i = 0; i < nx; ++i) t[i] = gx[(size_t)k * nx + i] + lam[(size_t)k * nx + i];"),
     "recon_B_not_transposed": ("matvec(nu, nx, p->B + (size_t)k * nx * nu, 1, lam + (size_t)(k + 1) * nx, s);",
@@ -78,6 +81,9 @@ def battery():
     ratios = np.sqrt(np.abs(o["eta"]) / eta_ref)
     if not (ratios[-1] < 1e-6 and np.all(ratios[:-1] >= 1e-6)):
         failed.append("stopping_rule")
+    oa = orc.solve(q, eps=1e-3, stop="absolute", trace=True)
+    if not (oa["eta"][-1] < 1e-3 and np.all(oa["eta"][:-1] >= 1e-3)):
+        failed.append("stopping_rule_absolute")
     # exact rational PCG trace
     rng = np.random.default_rng(7)
     N, nx, nu = 4, 2, 1

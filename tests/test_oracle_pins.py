@@ -194,6 +194,50 @@ def test_stopping_rule_first_iteration_below_eps():
     assert abs(o["ratio"] - ratios[-1]) < 1e-12
 
 
+@pytest.mark.parametrize("N,nx,nu,seed", [(5, 3, 1, 2), (6, 2, 1, 3)])
+def test_absolute_stopping_rule_against_exact_trace(N, nx, nu, seed):
+    # Algorithm 1 as printed: stop at the first eta' < eps (absolute).  The exact rational
+    # eta sequence fixes which iteration that is; eps sits halfway (geometrically) between
+    # two exact values so rounding cannot move the crossing.
+    Q, R, A, B, q, r, x0 = _rational_problem(N, nx, nu, seed)
+    S, P, g = exact.form(Q, R, A, B, q, r, x0)
+    _, iters, etas = exact.pcg(S, P, g)
+    ef = [float(x) for x in etas]
+    prob = _to_np(Q, R, A, B, q, r, x0)
+    checked = 0
+    for k in range(1, len(ef) - 1):
+        prev = min(ef[:k])
+        if not 0.0 < ef[k] < 0.5 * prev:
+            continue
+        eps = float(np.sqrt(ef[k] * prev))   # first value below eps is eta_k
+        o = orc.solve(prob, eps=eps, stop="absolute", max_iter=iters + 3)
+        assert o["status"] == orc.OK and o["iters"] == k, (k, eps, ef)
+        checked += 1
+    assert checked >= 2
+
+
+def test_absolute_rule_equals_relative_rule_at_scaled_eps():
+    # eta' < eps_rel^2 eta_ref  is the absolute rule with eps_abs = eps_rel^2 eta_ref, with
+    # eta_ref = gamma^T Phi^-1 gamma taken from the dense definitions
+    p = synth.problem(24, seed=5)
+    Sd, gd = kkt.schur_dense(p)
+    gd = gd.ravel()
+    _, P, _ = orc.form(p)
+    eta_ref = float(gd @ kkt.blocks_to_dense(P) @ gd)
+    rel = orc.solve(p, eps=1e-5)
+    ab = orc.solve(p, eps=(1e-5) ** 2 * eta_ref, stop="absolute")
+    assert rel["iters"] == ab["iters"] and np.array_equal(rel["lam"], ab["lam"])
+    # and the absolute rule stops where the dense residual first satisfies it
+    for eps in (1e-2, 1e-4):
+        o = orc.solve(p, eps=eps, stop="absolute", trace=True)
+        assert o["eta"][-1] < eps and np.all(o["eta"][:-1] >= eps)
+        res = gd - Sd @ o["lam"].ravel()
+        eta_dense = float(res @ kkt.blocks_to_dense(P) @ res)
+        assert eta_dense < eps * (1 + 1e-6)
+    with pytest.raises(ValueError):
+        orc.solve(p, stop="sometimes")
+
+
 def test_status_paths():
     p = synth.problem(16, seed=3)
     assert orc.solve(p, max_iter=1)["status"] == orc.NOT_CONVERGED
