@@ -75,6 +75,13 @@ def _stop(stop):
     return 1 if stop == "absolute" else 0
 
 
+def _mode(stop, phi):
+    """Mode word of the solve entry points: bit 0 absolute stop, bit 1 Phi^-1 in FP32."""
+    if phi not in ("fp64", "fp32"):
+        raise ValueError("phi must be 'fp64' or 'fp32', not %r" % (phi,))
+    return _stop(stop) | (2 if phi == "fp32" else 0)
+
+
 def _d(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
@@ -125,8 +132,9 @@ def pcg(S, P, gamma, eps=1e-6, max_iter=0, lam0=None, trace=False, stop="relativ
     return out
 
 
-def solve(prob, eps=1e-6, max_iter=0, lam0=None, trace=False, stop="relative"):
-    """Form + PCG + primal step.  Returns dict(lam, dx, du, iters, ratio, status[, eta])."""
+def solve(prob, eps=1e-6, max_iter=0, lam0=None, trace=False, stop="relative", phi="fp64"):
+    """Form + PCG + primal step.  Returns dict(lam, dx, du, iters, ratio, status[, eta]).
+    phi="fp32" rounds Phi^-1 to single precision before PCG uses it."""
     nx, nu, N = _dims(prob)
     a = _args(prob)
     mi = max_iter if max_iter > 0 else N * nx
@@ -134,7 +142,7 @@ def solve(prob, eps=1e-6, max_iter=0, lam0=None, trace=False, stop="relative"):
     dx = np.zeros((N, nx)); du = np.zeros((max(N - 1, 0), nu))
     it, ratio = C.c_int(0), C.c_double(0)
     tr = np.full(mi + 1, np.nan) if trace else None
-    st = _load().orc_solve(nx, nu, N, *[_p(x) for x in a], eps, _stop(stop), mi, _p(lam), _p(dx), _p(du),
+    st = _load().orc_solve(nx, nu, N, *[_p(x) for x in a], eps, _mode(stop, phi), mi, _p(lam), _p(dx), _p(du),
                            C.byref(it), C.byref(ratio), _p(tr))
     if st < 0:
         raise ValueError("oracle solve failed (status %d)" % st)
@@ -144,7 +152,7 @@ def solve(prob, eps=1e-6, max_iter=0, lam0=None, trace=False, stop="relative"):
     return out
 
 
-def backward(prob, fwd, gl, gx=None, gu=None, eps=1e-6, max_iter=0, stop="relative"):
+def backward(prob, fwd, gl, gx=None, gu=None, eps=1e-6, max_iter=0, stop="relative", phi="fp64"):
     """Adjoint for L(lambda, dx, du).  Returns dict of gradients (dQ, dR, dA, dB, dq, dr,
     dx0, de, mu) plus iters/ratio/status of the adjoint PCG."""
     nx, nu, N = _dims(prob)
@@ -157,7 +165,7 @@ def backward(prob, fwd, gl, gx=None, gu=None, eps=1e-6, max_iter=0, stop="relati
     gxd = None if gx is None else _d(gx)
     gud = None if gu is None else _d(gu)
     st = _load().orc_backward(
-        nx, nu, N, *[_p(x) for x in a], eps, _stop(stop), max_iter, _p(_d(fwd["lam"])), _p(_d(fwd["dx"])),
+        nx, nu, N, *[_p(x) for x in a], eps, _mode(stop, phi), max_iter, _p(_d(fwd["lam"])), _p(_d(fwd["dx"])),
         _p(_d(fwd["du"])), _p(_d(gl)), _p(gxd), _p(gud),
         *[_p(out[k]) for k in ("dQ", "dR", "dA", "dB", "dq", "dr", "dx0", "de", "mu")],
         C.byref(it), C.byref(ratio))
@@ -167,7 +175,7 @@ def backward(prob, fwd, gl, gx=None, gu=None, eps=1e-6, max_iter=0, stop="relati
     return out
 
 
-def solve_batch(packed, off, eps=1e-6, max_iter=0, threads=1, stop="relative"):
+def solve_batch(packed, off, eps=1e-6, max_iter=0, threads=1, stop="relative", phi="fp64"):
     """Batched forward solve on the packed layout; OpenMP over problems."""
     off = np.ascontiguousarray(off, dtype=np.int64)
     B = len(off) - 1
@@ -179,14 +187,14 @@ def solve_batch(packed, off, eps=1e-6, max_iter=0, threads=1, stop="relative"):
     lam = np.zeros((K, nx)); dx = np.zeros((K, nx)); du = np.zeros((max(K - B, 0), nu))
     iters = np.zeros(B, dtype=np.int32); ratio = np.zeros(B); status = np.zeros(B, dtype=np.int32)
     _load().orc_solve_batch(nx, nu, B, off.ctypes.data_as(C.POINTER(C.c_int64)),
-                            *[_p(x) for x in a], eps, _stop(stop), max_iter, _p(lam), _p(dx), _p(du),
+                            *[_p(x) for x in a], eps, _mode(stop, phi), max_iter, _p(lam), _p(dx), _p(du),
                             iters.ctypes.data_as(C.POINTER(C.c_int)), _p(ratio),
                             status.ctypes.data_as(C.POINTER(C.c_int)), threads)
     return dict(lam=lam, dx=dx, du=du, iters=iters, ratio=ratio, status=status)
 
 
 def backward_batch(packed, off, fwd, gl, gx=None, gu=None, eps=1e-6, max_iter=0, threads=1,
-                   stop="relative"):
+                   stop="relative", phi="fp64"):
     """Batched adjoint on the packed layout; OpenMP over problems."""
     off = np.ascontiguousarray(off, dtype=np.int64)
     B = len(off) - 1
@@ -202,7 +210,7 @@ def backward_batch(packed, off, fwd, gl, gx=None, gu=None, eps=1e-6, max_iter=0,
     gxd = None if gx is None else _d(gx)
     gud = None if gu is None else _d(gu)
     _load().orc_backward_batch(
-        nx, nu, B, off.ctypes.data_as(C.POINTER(C.c_int64)), *[_p(x) for x in a], eps, _stop(stop), max_iter,
+        nx, nu, B, off.ctypes.data_as(C.POINTER(C.c_int64)), *[_p(x) for x in a], eps, _mode(stop, phi), max_iter,
         _p(_d(fwd["lam"])), _p(_d(fwd["dx"])), _p(_d(fwd["du"])), _p(_d(gl)), _p(gxd), _p(gud),
         *[_p(out[k]) for k in ("dQ", "dR", "dA", "dB", "dq", "dr", "dx0", "de", "mu")],
         iters.ctypes.data_as(C.POINTER(C.c_int)), _p(ratio),

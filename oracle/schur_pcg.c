@@ -31,6 +31,10 @@
  *     residual sqrt(eta'/eta_ref) < eps; stop_abs = 0), or tau = eps (the absolute test
  *     eta' < eps that Algorithm 1 prints; stop_abs = 1).  The initial iterate is also
  *     tested (this only matters when the start already satisfies the rule, e.g. r = 0).
+ *   The solve entry points take a mode word: bit 0 (ORC_MODE_STOP_ABS) selects the absolute
+ *   rule; bit 1 (ORC_MODE_PHI_FP32) rounds every Phi^-1 entry to the nearest float before
+ *   PCG uses it, for comparing unconverged iterates with a solver that stores Phi^-1 in
+ *   single precision (the preconditioner changes the Krylov path, never the solution).
  *   Primal step (eq. "schur"): dZ = -G^-1 (g - C^T lambda).
  *
  * Storage: row-major, S and Phi^-1 as [N][3][nx][nx] with slot 0 = (b,b-1),
@@ -42,6 +46,12 @@
 #include <string.h>
 
 enum { ORC_OK = 0, ORC_NOT_CONVERGED = 1, ORC_BREAKDOWN = 2, ORC_EINVAL = -1, ORC_ENOMEM = -3 };
+enum { ORC_MODE_STOP_ABS = 1, ORC_MODE_PHI_FP32 = 2 };
+
+/* Phi^-1 entries rounded to single precision (mode bit ORC_MODE_PHI_FP32). */
+static void round_to_float(double *a, size_t n) {
+  for (size_t i = 0; i < n; ++i) a[i] = (double)(float)a[i];
+}
 
 /* ---- small dense helpers (n <= 64) ------------------------------------------------ */
 
@@ -328,7 +338,7 @@ int orc_pcg(int nx, int N, const double *S, const double *P, const double *gam, 
 /* Forward solve: form, PCG, primal step.  lam: start on entry (zeros for cold). */
 int orc_solve(int nx, int nu, int N, const double *Q, const double *R, const double *A,
               const double *B, const double *q, const double *r, const double *x0, const double *e,
-              double eps, int stop_abs, int max_iter, double *lam, double *dx, double *du,
+              double eps, int mode, int max_iter, double *lam, double *dx, double *du,
               int *iters, double *ratio, double *eta_trace) {
   if (nx < 1 || nu < 1 || N < 1) return ORC_EINVAL;
   if (max_iter <= 0) max_iter = N * nx;
@@ -343,7 +353,8 @@ int orc_solve(int nx, int nu, int N, const double *Q, const double *R, const dou
   if (Qi && Ri && S && P && gam) {
     st = knot_inverses(&p, Qi, Ri) ? ORC_BREAKDOWN : form(&p, Qi, Ri, S, P, gam);
     if (st == ORC_OK) {
-      st = pcg(nx, N, S, P, gam, eps, stop_abs, max_iter, lam, iters, ratio, eta_trace);
+      if (mode & ORC_MODE_PHI_FP32) round_to_float(P, (size_t)N * 3 * bs);
+      st = pcg(nx, N, S, P, gam, eps, mode & ORC_MODE_STOP_ABS, max_iter, lam, iters, ratio, eta_trace);
       reconstruct(&p, Qi, Ri, q, r, lam, dx, du);
     }
   }
@@ -364,7 +375,7 @@ int orc_solve(int nx, int nu, int N, const double *Q, const double *R, const dou
  *   Outputs may be NULL except mu. */
 int orc_backward(int nx, int nu, int N, const double *Q, const double *R, const double *A,
                  const double *B, const double *q, const double *r, const double *x0,
-                 const double *e, double eps, int stop_abs, int max_iter, const double *lam,
+                 const double *e, double eps, int mode, int max_iter, const double *lam,
                  const double *dx,
                  const double *du, const double *gl, const double *gx, const double *gu,
                  double *dQ, double *dR, double *dA, double *dB, double *dq, double *dr,
@@ -385,6 +396,7 @@ int orc_backward(int nx, int nu, int N, const double *Q, const double *R, const 
   if (!(Qi && Ri && S && P && gam && y && zx && zu && n1x && n1u && t && s)) goto out;
   st = knot_inverses(&p, Qi, Ri) ? ORC_BREAKDOWN : form(&p, Qi, Ri, S, P, gam);
   if (st != ORC_OK) goto out;
+  if (mode & ORC_MODE_PHI_FP32) round_to_float(P, (size_t)N * 3 * bs);
   if (gx) memcpy(zx, gx, n * sizeof(double));
   if (gu && m) memcpy(zu, gu, m * sizeof(double));
   /* y = gl + C G^-1 gz:  (C G^-1 gz)_0 = Q_0^-1 zx_0,
@@ -403,7 +415,7 @@ int orc_backward(int nx, int nu, int N, const double *Q, const double *R, const 
     free(w); free(v);
   }
   memset(mu, 0, n * sizeof(double));
-  st = pcg(nx, N, S, P, y, eps, stop_abs, max_iter, mu, iters, ratio, NULL);
+  st = pcg(nx, N, S, P, y, eps, mode & ORC_MODE_STOP_ABS, max_iter, mu, iters, ratio, NULL);
   /* nu_1 = -G^-1 (gz - C^T mu) */
   reconstruct(&p, Qi, Ri, zx, zu, mu, n1x, n1u);
   for (int k = 0; k < N; ++k) {
@@ -446,7 +458,7 @@ out:
  * lam must hold the start (zeros for cold).  iters/status/ratio are [batch]. */
 int orc_solve_batch(int nx, int nu, int batch, const int64_t *off, const double *Q,
                     const double *R, const double *A, const double *B, const double *q,
-                    const double *r, const double *x0, const double *e, double eps, int stop_abs,
+                    const double *r, const double *x0, const double *e, double eps, int mode,
                     int max_iter, double *lam, double *dx, double *du, int *iters, double *ratio,
                     int *status, int nthreads) {
   if (nx < 1 || nu < 1 || batch < 0) return ORC_EINVAL;
@@ -457,7 +469,7 @@ int orc_solve_batch(int nx, int nu, int batch, const int64_t *off, const double 
     const int N = (int)(off[b + 1] - off[b]);
     status[b] = orc_solve(nx, nu, N, Q + k0 * bs, R + c0 * bu, A + c0 * bs, B + c0 * bb,
                           q + k0 * nx, r + c0 * nu, x0 + (size_t)b * nx, e ? e + c0 * nx : NULL,
-                          eps, stop_abs, max_iter, lam + k0 * nx, dx + k0 * nx, du + c0 * nu, &iters[b],
+                          eps, mode, max_iter, lam + k0 * nx, dx + k0 * nx, du + c0 * nu, &iters[b],
                           &ratio[b], NULL);
   }
   return ORC_OK;
@@ -467,7 +479,7 @@ int orc_solve_batch(int nx, int nu, int batch, const int64_t *off, const double 
 int orc_backward_batch(int nx, int nu, int batch, const int64_t *off, const double *Q,
                        const double *R, const double *A, const double *B, const double *q,
                        const double *r, const double *x0, const double *e, double eps,
-                       int stop_abs, int max_iter, const double *lam, const double *dx, const double *du,
+                       int mode, int max_iter, const double *lam, const double *dx, const double *du,
                        const double *gl, const double *gx, const double *gu, double *dQ,
                        double *dR, double *dA, double *dB, double *dq, double *dr, double *dx0,
                        double *de, double *mu, int *iters, double *ratio, int *status,
@@ -480,7 +492,7 @@ int orc_backward_batch(int nx, int nu, int batch, const int64_t *off, const doub
     const int N = (int)(off[b + 1] - off[b]);
     status[b] = orc_backward(
         nx, nu, N, Q + k0 * bs, R + c0 * bu, A + c0 * bs, B + c0 * bb, q + k0 * nx, r + c0 * nu,
-        x0 + (size_t)b * nx, e ? e + c0 * nx : NULL, eps, stop_abs, max_iter, lam + k0 * nx,
+        x0 + (size_t)b * nx, e ? e + c0 * nx : NULL, eps, mode, max_iter, lam + k0 * nx,
         dx + k0 * nx,
         du + c0 * nu, gl + k0 * nx, gx ? gx + k0 * nx : NULL, gu ? gu + c0 * nu : NULL,
         dQ + k0 * bs, dR + c0 * bu, dA + c0 * bs, dB + c0 * bb, dq + k0 * nx, dr + c0 * nu,

@@ -38,6 +38,8 @@ MUTANTS = {
                           "for (int i = 0; i < nx; ++i) t[i] = gx[(size_t)k * nx + i] + lam[(size_t)k * nx + i];"),
     "recon_B_not_transposed": ("matvec(nu, nx, p->B + (size_t)k * nx * nu, 1, lam + (size_t)(k + 1) * nx, s);",
                                "matvec(nu, nx, p->B + (size_t)k * nx * nu, 0, lam + (size_t)(k + 1) * nx, s);"),
+    "phi32_not_rounded": ("static void round_to_float(double *a, size_t n) {\n  for (size_t i = 0; i < n; ++i) a[i] = (double)(float)a[i];",
+                          "static void round_to_float(double *a, size_t n) {\n  for (size_t i = 0; i < n; ++i) a[i] = a[i];"),
     "adjoint_dA_sign": ("dA[(size_t)k * bs + i * nx + j] = l1[i] * ax[j] + m1[i] * xk[j];",
                         "dA[(size_t)k * bs + i * nx + j] = l1[i] * ax[j] - m1[i] * xk[j];"),
     "adjoint_dQ_unsymmetrised": ("dQ[(size_t)k * bs + i * nx + j] = 0.5 * (ax[i] * xk[j] + ax[j] * xk[i]);",
@@ -81,6 +83,11 @@ def battery():
     ratios = np.sqrt(np.abs(o["eta"]) / eta_ref)
     if not (ratios[-1] < 1e-6 and np.all(ratios[:-1] >= 1e-6)):
         failed.append("stopping_rule")
+    gq = gq.ravel()
+    P32 = kkt.blocks_to_dense(Pq.astype(np.float32).astype(np.float64))
+    o32 = orc.solve(q, eps=1e-6, trace=True, phi="fp32")
+    if abs(o32["eta"][0] - gq @ P32 @ gq) > 1e-12 * abs(o32["eta"][0]):
+        failed.append("phi_fp32_mode")
     oa = orc.solve(q, eps=1e-3, stop="absolute", trace=True)
     if not (oa["eta"][-1] < 1e-3 and np.all(oa["eta"][:-1] >= 1e-3)):
         failed.append("stopping_rule_absolute")

@@ -238,6 +238,25 @@ def test_absolute_rule_equals_relative_rule_at_scaled_eps():
         orc.solve(p, stop="sometimes")
 
 
+def test_fp32_preconditioner_mode_changes_path_not_solution():
+    # phi="fp32" rounds every Phi^-1 entry to single precision before PCG: eta_0 is then
+    # gamma^T round32(Phi^-1) gamma (dense, from the formed blocks), the trace differs from
+    # the FP64 one, and the converged solution is still the KKT solution
+    p = synth.problem(20, seed=8)
+    S, P, g = orc.form(p)
+    gv = g.ravel()
+    P32 = kkt.blocks_to_dense(P.astype(np.float32).astype(np.float64))
+    o32 = orc.solve(p, eps=1e-6, trace=True, phi="fp32")
+    o64 = orc.solve(p, eps=1e-6, trace=True)
+    assert abs(o32["eta"][0] - gv @ P32 @ gv) <= 1e-12 * abs(o32["eta"][0])
+    assert abs(o64["eta"][0] - gv @ P32 @ gv) > 1e-12 * abs(o64["eta"][0])
+    ex = kkt.kkt_solve(p)
+    c = orc.solve(p, eps=1e-14, max_iter=2000, phi="fp32")
+    assert c["status"] == orc.OK and relerr(c["lam"], ex["lam"]) < 1e-9
+    with pytest.raises(ValueError):
+        orc.solve(p, phi="fp16")
+
+
 def test_status_paths():
     p = synth.problem(16, seed=3)
     assert orc.solve(p, max_iter=1)["status"] == orc.NOT_CONVERGED
