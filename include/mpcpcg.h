@@ -74,17 +74,25 @@ typedef struct {
   const float *Q, *R, *A, *B, *q, *r, *x0, *e;
 } mpcpcg_problem;
 
+/* Stopping rules (mpcpcg_opts.stop_rule), tested after initialisation and after every
+ * main-loop iteration (Algorithm 1, the "eta' < eps" test), eta = r^T Phi^-1 r:
+ *   RELATIVE: sqrt(eta / eta_ref) < eps with eta_ref = gamma^T Phi^-1 gamma, i.e. the
+ *             preconditioned residual relative to that of lambda = 0 (scale free);
+ *   ABSOLUTE: eta < eps, the test exactly as Algorithm 1 prints it (depends on the
+ *             problem's scale; the paper sweeps eps over 1e-4 .. 1e-5). */
+enum { MPCPCG_STOP_RELATIVE = 0, MPCPCG_STOP_ABSOLUTE = 1 };
+
 typedef struct {
-  float eps;          /* stopping tolerance on sqrt(eta/eta_ref); e.g. 1e-6           */
+  float eps;          /* stopping tolerance (see stop_rule); e.g. 1e-6 relative         */
   int32_t max_iter;   /* main-loop iteration cap; 0 means N*nx                         */
   int32_t warm_start; /* non-zero: lambda (in/out) holds the start iterate on entry     */
-  int32_t reserved;   /* must be 0                                                     */
+  int32_t stop_rule;  /* MPCPCG_STOP_RELATIVE (0) or MPCPCG_STOP_ABSOLUTE (1)           */
 } mpcpcg_opts;
 
 typedef struct {
   int32_t iters;      /* main-loop iterations executed (0 if the start already passed) */
   int32_t status;     /* MPCPCG_OK / NOT_CONVERGED / BREAKDOWN / TIMEOUT                */
-  float final_ratio;  /* sqrt(eta/eta_ref) at exit                                      */
+  float final_ratio;  /* sqrt(eta/eta_ref) at exit, whichever stop_rule ran             */
   int32_t reserved;
 } mpcpcg_stats;
 

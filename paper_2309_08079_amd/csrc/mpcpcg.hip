@@ -144,6 +144,8 @@ int check_opts(mpcpcg_ctx *c, const mpcpcg_opts *o) {
   if (!o) return fail(c, MPCPCG_EINVAL, "opts is NULL");
   if (!(o->eps >= 0.0f) || o->max_iter < 0)
     return fail(c, MPCPCG_EINVAL, "eps must be >= 0 and max_iter >= 0");
+  if (o->stop_rule != MPCPCG_STOP_RELATIVE && o->stop_rule != MPCPCG_STOP_ABSOLUTE)
+    return fail(c, MPCPCG_EINVAL, "stop_rule must be MPCPCG_STOP_RELATIVE or MPCPCG_STOP_ABSOLUTE");
   return MPCPCG_OK;
 }
 
@@ -154,7 +156,7 @@ KArgs base_args(mpcpcg_ctx *c, const mpcpcg_problem *p, const mpcpcg_opts *o) {
   a.q = p->q; a.r = p->r; a.x0 = p->x0; a.e = p->e;
   a.tws = c->tws; a.gang = c->gang; a.queue = c->queue;
   a.qinv_ws = c->qinv_ws; a.rinv_ws = c->rinv_ws;
-  if (o) { a.eps = o->eps; a.max_iter = o->max_iter; a.warm = o->warm_start; }
+  if (o) { a.eps = o->eps; a.max_iter = o->max_iter; a.warm = o->warm_start; a.stop_abs = o->stop_rule; }
   return a;
 }
 
@@ -341,7 +343,7 @@ mpc::wide::WArgs wide_args(mpcpcg_ctx *c, const mpcpcg_problem *p, const mpcpcg_
   a.Q = p->Q; a.R = p->R; a.A = p->A; a.B = p->B;
   a.q = p->q; a.r = p->r; a.x0 = p->x0; a.e = p->e;
   a.S = c->w_S; a.Dinv = c->w_Dinv; a.P = c->w_P; a.rhs = c->w_rhs; a.Qinv = c->w_Qinv; a.RW = c->w_RW;
-  if (o) { a.eps = o->eps; a.max_iter = o->max_iter; a.warm = o->warm_start; }
+  if (o) { a.eps = o->eps; a.max_iter = o->max_iter; a.warm = o->warm_start; a.stop_abs = o->stop_rule; }
   return a;
 }
 

@@ -50,17 +50,38 @@ struct alignas(256) Gang {
   int pad[62];
 };
 
+// Tagged words of the loop barriers, per task: (tag << 32) | 32-bit payload with tag =
+// barrier index + 1; a double is two words (low half, high half).  Zero = never written.
+struct TagWS {
+  uint64_t red[2][2][2];              // [parity][value][half] this part's partial sums
+  uint64_t hv[2][2][2][kGroup][2];    // [parity][channel][side][lane][half] double halos
+  uint64_t hf[2][2][kGroup];          // [parity][side][lane] float halos
+};
+
 template <int NX>
 struct TaskWS {       // per task; read by the other parts of the same gang
-  // epoch of the last barrier this part reached: (launch generation << 32) | (n + 1)
-  // for barrier n; written after everything the part publishes for that barrier.
+  TagWS tg;
+  // formation barrier: (launch generation << 32) | 1 once the hm rows below are complete
   uint64_t flag;
   uint64_t pad[7];
-  double red[2][2][kMaxWaves];   // [parity][value][wave] partial sums of this part's waves
-  double hv[2][2][2][kGroup];    // [parity][channel][side][lane] double vector halos
-  float hf[2][2][kGroup];        // [parity][side][lane] float vector halos
-  double hm[2][NX][kGroup];      // [side][row][col] matrix halo (one use, in formation)
+  double hm[2][NX][kGroup];      // [side][row][col] D^-1 rows of the two boundary knots
 };
+
+// Integral constant for the compile-time shape of a barrier.
+template <int V>
+struct IC {
+  static constexpr int value = V;
+};
+
+__device__ __forceinline__ void store_tagged2(uint64_t *w, uint32_t tag, double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint64_t t = (uint64_t)tag << 32;
+  __hip_atomic_store(&w[0], t | (uint32_t)u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&w[1], t | (uint32_t)(u >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double untag2(uint64_t lo, uint64_t hi) {
+  return __builtin_bit_cast(double, (hi << 32) | (uint32_t)lo);
+}
 
 struct KArgs {
   // problem data (packed)
@@ -88,7 +109,7 @@ struct KArgs {
   float eps;
   int32_t max_iter;
   int32_t warm;
-  int32_t pad;
+  int32_t stop_abs;      // 1: eta < eps; 0: sqrt(eta / eta_ref) < eps
 };
 
 constexpr long long kSpinLimitTicks = 200000000LL;  // 2 s at the 100 MHz wall clock
@@ -202,79 +223,98 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
     bool aborted = false;
     if (tid == 0) sh_abort = 0;
 
-    // Synchronisation point shared by every exchange: publishes this part's halos and
-    // partial sums, waits for the gang, fills halo slots 0 / KPW+1 from the neighbours
-    // and leaves totals in tot[].  ND double channels, NF float channel, NM matrix, NR
-    // reduction values (read from red_w[ph]).
-    auto sync_point = [&](int ND, int NF, int NM, int NR, int ph) {
-      // Cross-part data (halos, partial sums, flags) moves through agent-scope relaxed
-      // atomics, which bypass the non-coherent cache levels.  Ordering comes from
-      // completion waits: every wave waits for its own stores before the workgroup
-      // barrier, the flag is written only after the partial sums have completed, and a
-      // reader loads data only after it has seen the flags of every part.  Lane g of wave
-      // 0 polls part g, so the wait costs one round trip whatever the number of parts.
-      if (multi) __builtin_amdgcn_s_waitcnt(0);
+    // Gang barriers.  Every value that crosses a part boundary (halo rows of the vectors,
+    // the part's partial sums) is published as 64-bit words (tag << 32) | payload, where
+    // the tag is the barrier index + 1 and a double takes two words.  A 64-bit store is seen
+    // whole or not at all, so a reader that finds the expected tag in a word also has its
+    // payload: waiting and loading are the same round trip, and a writer never waits for
+    // its stores to complete.  Lane g of wave 0 polls the partial sums of part g, lanes
+    // 0..31 poll the left / right halos.  A part publishes one sum per value (its waves'
+    // partials added in order after the workgroup barrier), which keeps the polled words,
+    // and so the traffic at the coherence point, at 2 * NR per part: per-wave words made
+    // the polling itself the bottleneck once hundreds of workgroups wait at once.  Stale
+    // words from earlier solves never carry a live tag: the last part out of a gang zeroes
+    // the tagged words of every part.
+    auto poll_spin = [&](int &polls, long long t_start) -> int {
+      __builtin_amdgcn_s_sleep(1);
+      if ((++polls & 63) == 0) {
+        if (__hip_atomic_load(&gang->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return 1;
+        if (wall_clock64() - t_start > kSpinLimitTicks) {
+          __hip_atomic_store(&gang->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          return 1;
+        }
+      }
+      return 0;
+    };
+    // Loop barrier: ND double channels and NF float channel of halos, NR partial sums
+    // (read from red_w[ph] when the problem has one part); totals land in tot[].
+    auto sync_point = [&](auto nd_c, auto nf_c, auto nr_c, int ph) {
+      constexpr int ND = decltype(nd_c)::value, NF = decltype(nf_c)::value, NR = decltype(nr_c)::value;
       __syncthreads();
       if (multi) {
-        const int par = nsync & 1;
-        const uint64_t epoch = (gen << 32) | (uint64_t)(uint32_t)(nsync + 1);
         if (wave == 0) {
-          // every wave's halo and partial-sum stores completed before the barrier above
-          if (wl == 0)
-            __hip_atomic_store(&tws[my_t].flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          const long long t_start = wall_clock64();
+          const int par = nsync & 1;
+          const uint32_t tag = (uint32_t)nsync + 1u;
+          if (NR > 0 && wl < NR) {  // this part's sum of value wl, its waves in order
+            double ps = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) ps += red_w[ph][wl][w];
+            store_tagged2(tws[my_t].tg.red[par][wl], tag, ps);
+          }
+          const int side = wl >> 4, l = wl & 15;
+          const int nb = side == 0 ? part - 1 : part + 1;
+          const bool has = wl < 2 * kGroup && nb >= 0 && nb < G;
+          const TagWS *hsrc = &tws[has ? my_t + (side == 0 ? -1 : 1) : my_t].tg;
+          const int srcside = side == 0 ? 1 : 0;  // left neighbour's last knot / right's first
+          uint64_t hd[ND > 0 ? ND : 1][2], hfw = 0;
+          double v0 = 0.0, v1 = 0.0;
           int ab = 0, polls = 0;
+          const long long t_start = wall_clock64();
           for (int g0 = 0; g0 < G && !ab; g0 += 64) {
             const int g = g0 + wl;
-            bool seen = g >= G;  // a lane stops polling once its part has arrived
+            const bool mine = NR > 0 && g < G;
+            const bool halo = g0 == 0 && has;
+            const TagWS *rsrc = &tws[pd.t0 + (mine ? g : 0)].tg;
+            uint64_t rw[NR > 0 ? NR : 1][2];
             while (true) {
-              if (!seen)
-                seen = __hip_atomic_load(&tws[pd.t0 + g].flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
-              if (__ballot(seen) == ~0ull) break;
-              __builtin_amdgcn_s_sleep(1);
-              if ((++polls & 63) == 0) {
-                if (__hip_atomic_load(&gang->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { ab = 1; break; }
-                if (wall_clock64() - t_start > kSpinLimitTicks) {
-                  __hip_atomic_store(&gang->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                  ab = 1;
-                  break;
+              bool ok = true;
+              if (mine) {
+#pragma unroll
+                for (int v = 0; v < NR; ++v)
+#pragma unroll
+                  for (int h = 0; h < 2; ++h) {
+                    rw[v][h] = __hip_atomic_load(&rsrc->red[par][v][h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok &= (uint32_t)(rw[v][h] >> 32) == tag;
+                  }
+              }
+              if (halo) {
+#pragma unroll
+                for (int c = 0; c < ND; ++c)
+#pragma unroll
+                  for (int h = 0; h < 2; ++h) {
+                    hd[c][h] = __hip_atomic_load(&hsrc->hv[par][c][srcside][l][h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok &= (uint32_t)(hd[c][h] >> 32) == tag;
+                  }
+                if (NF) {
+                  hfw = __hip_atomic_load(&hsrc->hf[par][srcside][l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                  ok &= (uint32_t)(hfw >> 32) == tag;
                 }
               }
+              if (__ballot(ok) == ~0ull) break;
+              if ((ab = poll_spin(polls, t_start))) break;
+            }
+            // totals over parts in a fixed order and a fixed-shape reduction, so every part
+            // computes bit-identical totals
+            if (mine && !ab) {
+              v0 += untag2(rw[0][0], rw[0][1]);
+              if (NR > 1) v1 += untag2(rw[NR > 1 ? 1 : 0][0], rw[NR > 1 ? 1 : 0][1]);
             }
           }
-          // halos from the neighbouring parts (lanes 0..15 left, 16..31 right) and the
-          // partial sums (lane g: parts g, g+64, ...) are loaded together, one round trip
           if (wl < 2 * kGroup && !ab) {
-            const int side = wl >> 4, l = wl & 15;
-            const int nb = side == 0 ? part - 1 : part + 1;
-            const bool has = nb >= 0 && nb < G;
-            const TaskWS<NX> *src = &tws[my_t + (side == 0 ? -1 : 1)];
             const int dst = side == 0 ? 0 : KPW + 1;
-            const int srcside = side == 0 ? 1 : 0;  // left neighbour's last knot / right's first
-            for (int c = 0; c < ND; ++c)
-              ex_d[c][dst][l] = has ? __hip_atomic_load(&src->hv[par][c][srcside][l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
-            if (NF)
-              ex_f[dst][l] = has ? __hip_atomic_load(&src->hf[par][srcside][l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0f;
-            if (NM)
-              for (int rr = 0; rr < NX; ++rr)
-                ex_m[dst][rr][l] = has ? __hip_atomic_load(&src->hm[srcside][rr][l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
-          }
-          // totals over (part, wave) in a fixed order and a fixed-shape reduction, so every
-          // part computes bit-identical totals
-          double v0 = 0.0, v1 = 0.0;
-          if (!ab && NR > 0) {
-            for (int g = wl; g < G; g += 64) {  // lane g sums part g's waves in order
-              const double *r0 = tws[pd.t0 + g].red[par][0];
-              const double *r1 = tws[pd.t0 + g].red[par][1];
-              double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-              for (int w = 0; w < NW; ++w) {
-                s0 += __hip_atomic_load(&r0[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (NR > 1) s1 += __hip_atomic_load(&r1[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              }
-              v0 += s0;
-              v1 += s1;
-            }
+            for (int c = 0; c < ND; ++c) ex_d[c][dst][l] = has ? untag2(hd[c][0], hd[c][1]) : 0.0;
+            if (NF) ex_f[dst][l] = has ? __builtin_bit_cast(float, (uint32_t)hfw) : 0.0f;
           }
           const double w0 = wave_sum(v0), w1 = wave_sum(v1);
           if (wl == 0) {
@@ -299,27 +339,59 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         __syncthreads();
       }
     };
+    // Formation barrier (barrier 0): the D^-1 rows of the two boundary knots (NX doubles
+    // per lane) go through plain stores, then a completion wait and a flag
+    // (launch generation << 32) | 1.  It runs once per solve, so it keeps the simpler
+    // protocol and leaves no tagged words behind.
+    auto sync_form = [&]() {
+      if (multi) __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (multi) {
+        const uint64_t epoch = (gen << 32) | 1u;
+        if (wave == 0) {
+          if (wl == 0) __hip_atomic_store(&tws[my_t].flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const long long t_start = wall_clock64();
+          int ab = 0, polls = 0;
+          // only the two neighbours' rows are needed
+          const int nb = wl == 0 ? part - 1 : part + 1;
+          const bool want = wl < 2 && nb >= 0 && nb < G;
+          while (true) {
+            const bool seen = !want || __hip_atomic_load(&tws[pd.t0 + nb].flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+            if (__ballot(seen) == ~0ull) break;
+            if ((ab = poll_spin(polls, t_start))) break;
+          }
+          if (wl < 2 * kGroup && !ab) {
+            const int side = wl >> 4, l = wl & 15;
+            const int nbh = side == 0 ? part - 1 : part + 1;
+            const bool has = nbh >= 0 && nbh < G;
+            const TaskWS<NX> *src = &tws[has ? my_t + (side == 0 ? -1 : 1) : my_t];
+            const int dst = side == 0 ? 0 : KPW + 1;
+            const int srcside = side == 0 ? 1 : 0;
+            for (int rr = 0; rr < NX; ++rr)
+              ex_m[dst][rr][l] = has ? __hip_atomic_load(&src->hm[srcside][rr][l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+          }
+          if (wl == 0) sh_abort = ab;
+        }
+        __syncthreads();
+        ++nsync;
+        aborted = uni(sh_abort) != 0;
+      }
+    };
 
     // publish this group's value of a double vector channel (LDS + boundary halo)
     auto put_d = [&](int c, double v) {
       ex_d[c][slot + 1][lane] = v;
-      if (multi) {
-        const int par = nsync & 1;
-        if (slot == 0)
-          __hip_atomic_store(&tws[my_t].hv[par][c][0][lane], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (slot == KPW - 1)
-          __hip_atomic_store(&tws[my_t].hv[par][c][1][lane], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (multi && (slot == 0 || slot == KPW - 1)) {
+        uint64_t *w = tws[my_t].tg.hv[nsync & 1][c][slot == 0 ? 0 : 1][lane];
+        store_tagged2(w, (uint32_t)nsync + 1u, v);
       }
     };
     auto put_f = [&](float v) {
       ex_f[slot + 1][lane] = v;
-      if (multi) {
-        const int par = nsync & 1;
-        if (slot == 0)
-          __hip_atomic_store(&tws[my_t].hf[par][0][lane], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (slot == KPW - 1)
-          __hip_atomic_store(&tws[my_t].hf[par][1][lane], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
+      if (multi && (slot == 0 || slot == KPW - 1))
+        __hip_atomic_store(&tws[my_t].tg.hf[nsync & 1][slot == 0 ? 0 : 1][lane],
+                           ((uint64_t)((uint32_t)nsync + 1u) << 32) | __builtin_bit_cast(uint32_t, v),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     };
     // per-wave partial of a lane value (deterministic order), written to red_w[ph][v]
     auto put_red = [&](int ph, int v, double x) {
@@ -333,11 +405,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         const uint32_t h2 = __builtin_amdgcn_readlane(hi, 16 * q + 15);
         s += __builtin_bit_cast(double, ((uint64_t)h2 << 32) | l2);
       }
-      if (wl == 0) {
-        red_w[ph][v][wave] = s;
-        if (multi)
-          __hip_atomic_store(&tws[my_t].red[nsync & 1][v][wave], s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
+      if (wl == 0) red_w[ph][v][wave] = s;
     };
 
     // ================================================================== formation
@@ -481,7 +549,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         for (int j = 0; j < NX; ++j)
           __hip_atomic_store(&tws[my_t].hm[1][lane][j], Dd[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    sync_point(0, 0, 1, 0, 0);
+    sync_form();
     // (7) Phi^-1_{b,b-1} = -D_b^-1 S_{b,b-1} D_{b-1}^-1, Phi^-1_{b,b+1} likewise
     float Pm[NX], Pd[NX], Pp[NX];
     {
@@ -561,13 +629,14 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         row_fma14_f32(acc2, xp, m);
         return (acc0 + acc1) + acc2;
       };
-      const int max_iter = a.max_iter > 0 ? a.max_iter : N * NX;
+      // two barriers per iteration; the cap keeps barrier tags far from 32-bit wrap-around
+      const int max_iter = (int)min((int64_t)(a.max_iter > 0 ? a.max_iter : (int64_t)N * NX), (int64_t)1 << 28);
       double lam = 0.0, r = rhs, p, pm, pp, rm, rp;
       // eta_ref = rhs^T Phi^-1 rhs
       put_d(0, rhs);
       if (MODE == kForward && a.warm && act && rowv) lam = (double)a.lam[kb * NX + lane];
       put_d(1, lam);
-      sync_point(2, 0, 0, 0, 0);
+      sync_point(IC<2>{}, IC<0>{}, IC<0>{}, 0);
       const double gm = ex_d[0][slot][lane], gp = ex_d[0][slot + 2][lane];
       const float gt = precond_row((float)gm, (float)rhs, (float)gp);
       const bool warm = (MODE == kForward) && a.warm;
@@ -582,7 +651,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         row_fma14_f64(a2, lp, Sp);
         r = rhs - ((a0 + a1) + a2);
         put_d(0, r);
-          sync_point(1, 0, 0, 0, 1);
+          sync_point(IC<1>{}, IC<0>{}, IC<0>{}, 1);
         rm = ex_d[0][slot][lane];
         rp = ex_d[0][slot + 2][lane];
       }
@@ -591,10 +660,10 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       put_red(0, 0, r * (double)rt);
       put_red(0, 1, rhs * (double)gt);
       put_f(rt);
-      sync_point(0, 1, 0, 2, 0);
+      sync_point(IC<0>{}, IC<1>{}, IC<2>{}, 0);
       double eta = uni(tot[0]);
       const double eta_ref = uni(tot[1]);
-      const double tau = (double)a.eps * (double)a.eps * eta_ref;
+      const double tau = a.stop_abs ? (double)a.eps : (double)a.eps * (double)a.eps * eta_ref;
       p = (double)rt;
       pm = (double)ex_f[slot][lane];
       pp = (double)ex_f[slot + 2][lane];
@@ -615,7 +684,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
           const double Y = (a0 + a1) + a2;
           put_red(0, 0, p * Y);
           put_d(0, Y);
-              sync_point(1, 0, 0, 1, 0);
+              sync_point(IC<1>{}, IC<0>{}, IC<1>{}, 0);
           const double ups = uni(tot[0]);
           if (!(ups > 0.0) || __builtin_isinf(ups)) {
             status = MPCPCG_BREAKDOWN;
@@ -631,7 +700,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
           const float rtn = precond_row((float)rm, (float)r, (float)rp);
           put_red(1, 0, r * (double)rtn);
           put_f(rtn);
-              sync_point(0, 1, 0, 1, 1);
+              sync_point(IC<0>{}, IC<1>{}, IC<1>{}, 1);
           eta_new = uni(tot[0]);
           if (!(eta_new == eta_new) || __builtin_isinf(eta_new)) {
             status = MPCPCG_BREAKDOWN;
@@ -659,7 +728,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       // adjoint): x rows use Q_b^-1 and S_{b,b+1} = -Q_b^-1 A_b^T; u rows of control b-1
       // use R_{b-1}^-1 and W = R_{b-1}^-1 B_{b-1}^T (both written during formation).
       put_d(0, lam);
-      sync_point(1, 0, 0, 0, 0);
+      sync_point(IC<1>{}, IC<0>{}, IC<0>{}, 0);
       const double lp = ex_d[0][slot + 2][lane];
       double qmin = 0.0;   // q_b - lambda_b  (or gx_b - mu_b)
       if (act && rowv) {
@@ -698,7 +767,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         // adjoint: lam holds mu, xrow = nu1x_b, urow = nu1u_{b-1}
         const double mu = lam, n1x = xrow, n1u = urow;
         put_d(0, n1x);
-          sync_point(1, 0, 0, 0, 1);
+          sync_point(IC<1>{}, IC<0>{}, IC<0>{}, 1);
         const double n1xm = ex_d[0][slot][lane];  // nu1x_{b-1}
         double dxb = 0.0, dxm = 0.0, lb = 0.0, dum = 0.0;
         if (act && rowv) {
@@ -762,11 +831,23 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
     }
 
     // ------------------------------------------------------------- gang teardown
+    // Every part has read all it needs once all G have arrived here, so the last one out
+    // zeroes the gang's tagged words (no stale tag survives into a later solve) and resets
+    // the gang state.
     if (multi) {
       __syncthreads();
       if (tid == 0) {
         const int d = __hip_atomic_fetch_add(&gang->done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (d == G - 1) {
+        sh_task = d == G - 1;
+      }
+      __syncthreads();
+      if (uni(sh_task)) {
+        constexpr int kWords = sizeof(TagWS) / sizeof(uint64_t);
+        for (int i = tid; i < G * kWords; i += NT) {
+          uint64_t *w = reinterpret_cast<uint64_t *>(&tws[pd.t0 + i / kWords].tg) + i % kWords;
+          __hip_atomic_store(w, (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (tid == 0) {
           __hip_atomic_store(&gang->abort, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           __hip_atomic_store(&gang->done, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }

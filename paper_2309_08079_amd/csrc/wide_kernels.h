@@ -58,6 +58,8 @@ struct WArgs {
   int32_t max_iter;
   int32_t warm;
   int32_t adjoint;
+  int32_t stop_abs;   // 1: eta < eps; 0: sqrt(eta / eta_ref) < eps
+  int32_t pad;
 };
 
 // ---------------------------------------------------------------- LDS dense helpers
@@ -366,7 +368,7 @@ __global__ void __launch_bounds__(kWideThreads) wide_pcg(const WArgs a) {
   }
   double eta = block_sum(pr, red);
   const double eta_ref = block_sum(pe, red);
-  const double tau = (double)a.eps * (double)a.eps * eta_ref;
+  const double tau = a.stop_abs ? (double)a.eps : (double)a.eps * (double)a.eps * eta_ref;
   const int max_iter = a.max_iter > 0 ? a.max_iter : N * NX;
   int status = MPCPCG_NOT_CONVERGED, it = 0;
   double eta_new = eta;

@@ -14,6 +14,7 @@ import numpy as np
 import torch
 
 OK, NOT_CONVERGED, BREAKDOWN, TIMEOUT = 0, 1, 2, 3
+STOP_RULES = {"relative": 0, "absolute": 1}   # MPCPCG_STOP_RELATIVE / MPCPCG_STOP_ABSOLUTE
 EINVAL, EUNSUPPORTED, ENOMEM, EHIP = -1, -2, -3, -4
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmpcpcg.so")
@@ -31,7 +32,7 @@ class Problem(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("eps", C.c_float), ("max_iter", C.c_int32), ("warm_start", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("stop_rule", C.c_int32)]
 
 
 class Schur(C.Structure):
@@ -95,9 +96,11 @@ def _problem(d, nx, nu, N=0):
     return p
 
 
-def _opts(eps, max_iter, warm):
+def _opts(eps, max_iter, warm, stop="relative"):
+    if stop not in STOP_RULES:
+        raise MPCPCGError("stop must be 'relative' or 'absolute', not %r" % (stop,))
     o = Opts()
-    o.eps, o.max_iter, o.warm_start, o.reserved = float(eps), int(max_iter), int(bool(warm)), 0
+    o.eps, o.max_iter, o.warm_start, o.stop_rule = float(eps), int(max_iter), int(bool(warm)), STOP_RULES[stop]
     return o
 
 
@@ -135,18 +138,21 @@ class Context:
             raise MPCPCGError("%s failed (%d): %s" % (what, st, msg))
 
     # ---- entry points ------------------------------------------------------------------
-    def mpcpcg_form_schur(self, prob):
+    def mpcpcg_form_schur(self, prob, out=None):
         N = prob["q"].shape[0]
         dev = prob["q"].device
-        S = torch.zeros((N, 3, self.nx, self.nx), device=dev)
-        P = torch.zeros_like(S)
-        g = torch.zeros((N, self.nx), device=dev)
+        if out is not None:
+            S, P, g = out
+        else:
+            S = torch.zeros((N, 3, self.nx, self.nx), device=dev)
+            P = torch.zeros_like(S)
+            g = torch.zeros((N, self.nx), device=dev)
         out = Schur(S.data_ptr(), P.data_ptr(), g.data_ptr())
         self._check(self.lib.mpcpcg_form_schur(self.h, C.byref(_problem(prob, self.nx, self.nu, N)),
                                                C.byref(out), _stream()), "mpcpcg_form_schur")
         return S, P, g
 
-    def mpcpcg_solve(self, prob, eps=1e-6, max_iter=0, lam0=None, out=None):
+    def mpcpcg_solve(self, prob, eps=1e-6, max_iter=0, lam0=None, out=None, stop="relative"):
         N = prob["q"].shape[0]
         dev = prob["q"].device
         o = out or {}
@@ -157,12 +163,13 @@ class Context:
         du = o["du"] if "du" in o else torch.empty((max(N - 1, 0), self.nu), device=dev)
         stats = o["stats"] if "stats" in o else torch.zeros((1, 4), dtype=torch.int32, device=dev)
         self._check(self.lib.mpcpcg_solve(
-            self.h, C.byref(_problem(prob, self.nx, self.nu, N)), C.byref(_opts(eps, max_iter, lam0 is not None)),
+            self.h, C.byref(_problem(prob, self.nx, self.nu, N)), C.byref(_opts(eps, max_iter, lam0 is not None, stop)),
             _ptr(lam), _ptr(dx), _ptr(du) if du.numel() else None, stats.data_ptr(), _stream()),
             "mpcpcg_solve")
         return dict(lam=lam, dx=dx, du=du, stats=stats)
 
-    def mpcpcg_solve_batched(self, packed, knot_off, eps=1e-6, max_iter=0, lam0=None, out=None):
+    def mpcpcg_solve_batched(self, packed, knot_off, eps=1e-6, max_iter=0, lam0=None, out=None,
+                             stop="relative"):
         off = np.ascontiguousarray(knot_off, dtype=np.int64)
         B = len(off) - 1
         K = int(off[-1])
@@ -176,12 +183,12 @@ class Context:
         stats = o["stats"] if "stats" in o else torch.zeros((B, 4), dtype=torch.int32, device=dev)
         self._check(self.lib.mpcpcg_solve_batched(
             self.h, B, off.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(_problem(packed, self.nx, self.nu)),
-            C.byref(_opts(eps, max_iter, lam0 is not None)), _ptr(lam), _ptr(dx),
+            C.byref(_opts(eps, max_iter, lam0 is not None, stop)), _ptr(lam), _ptr(dx),
             _ptr(du) if du.numel() else None, stats.data_ptr(), _stream()), "mpcpcg_solve_batched")
         return dict(lam=lam, dx=dx, du=du, stats=stats)
 
     def mpcpcg_backward(self, packed, knot_off, fwd, gl, gx=None, gu=None, eps=1e-6, max_iter=0,
-                        out=None):
+                        out=None, stop="relative"):
         off = np.ascontiguousarray(knot_off, dtype=np.int64)
         B = len(off) - 1
         K = int(off[-1])
@@ -197,7 +204,7 @@ class Context:
         opt = lambda t: _ptr(t) if t is not None and t.numel() else None
         self._check(self.lib.mpcpcg_backward(
             self.h, B, off.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(_problem(packed, nx, nu)),
-            C.byref(_opts(eps, max_iter, False)), _ptr(fwd["lam"]), _ptr(fwd["dx"]), opt(fwd["du"]),
+            C.byref(_opts(eps, max_iter, False, stop)), _ptr(fwd["lam"]), _ptr(fwd["dx"]), opt(fwd["du"]),
             _ptr(gl), opt(gx), opt(gu),
             *[opt(g[k]) for k in ("dQ", "dR", "dA", "dB", "dq", "dr", "dx0", "de", "dgamma")],
             stats.data_ptr(), _stream()), "mpcpcg_backward")
@@ -210,7 +217,7 @@ class Context:
     def mpcpcg_set_graph(self, enable):
         self._check(self.lib.mpcpcg_set_graph(self.h, int(bool(enable))), "mpcpcg_set_graph")
 
-    def mpcpcg_autotune(self, packed, knot_off, eps=1e-6, max_iter=0):
+    def mpcpcg_autotune(self, packed, knot_off, eps=1e-6, max_iter=0, stop="relative"):
         off = np.ascontiguousarray(knot_off, dtype=np.int64)
         B = len(off) - 1
         K = int(off[-1])
@@ -222,7 +229,7 @@ class Context:
         k = C.c_int32(0)
         self._check(self.lib.mpcpcg_autotune(
             self.h, B, off.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(_problem(packed, self.nx, self.nu)),
-            C.byref(_opts(eps, max_iter, False)), _ptr(lam), _ptr(dx), _ptr(du), stats.data_ptr(),
+            C.byref(_opts(eps, max_iter, False, stop)), _ptr(lam), _ptr(dx), _ptr(du), stats.data_ptr(),
             _stream(), C.byref(k)), "mpcpcg_autotune")
         return k.value
 
