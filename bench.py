@@ -15,6 +15,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -34,7 +35,7 @@ FLOP_PER_KNOT_GRAD = 1960      # dQ, dA (two outer products each), dB, dR
 PEAK_VALU_TFLOPS = 78.6        # FP64 vector FMA issue rate of MI355X (= non-packed FP32)
 
 
-def measured_traffic(mode):
+def measured_traffic(mode, kpw):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE passes (calibrated on a plain copy), or None once the kernel sources differ
     from those the counters were taken on."""
@@ -49,12 +50,74 @@ def measured_traffic(mode):
         for src in rec["kernel_sources"]:
             h.update(open(os.path.join(root, src), "rb").read())
         srcs = sorted(glob.glob(os.path.join(root, "paper_2309_08079_amd", "csrc", "*")))
-        if h.hexdigest() != rec["kernel_sources_sha256"] or len(srcs) + 1 != len(rec["kernel_sources"]):
+        if h.hexdigest() != rec["kernel_sources_sha256"] or len(srcs) + 1 != len(rec["kernel_sources"]) \
+                or rec["per_launch"][mode]["knots_per_group"] != kpw:
             return None
         pl = rec["per_launch"][mode]
         return pl["fetch_bytes"] + pl["write_bytes"]
     except (OSError, KeyError, ValueError):
         return None
+
+
+KERNEL_SOURCES = ["paper_2309_08079_amd/csrc/dpp_asm.h", "paper_2309_08079_amd/csrc/lane_ops.h",
+                  "paper_2309_08079_amd/csrc/mpcpcg.hip", "paper_2309_08079_amd/csrc/pcg_kernel.h",
+                  "paper_2309_08079_amd/csrc/wide_kernels.h", "include/mpcpcg.h"]
+MODE_OF_TEMPLATE = {"1": "forward", "2": "adjoint"}
+
+
+def ingest_counters(prof_dir):
+    """Turn four rocprofv3 --pmc passes (FETCH_SIZE and WRITE_SIZE of the --step-only run, the
+    same two of the --copy-probe run) into the per-launch HBM bytes measured_traffic() reads.
+    Host only: parses <prof_dir>/{fetch,write,cfetch,cwrite}/<name>_counter_collection.csv."""
+    import csv
+    import hashlib
+
+    root = os.path.dirname(os.path.abspath(__file__))
+
+    def rows(name):
+        with open(os.path.join(prof_dir, name, name + "_counter_collection.csv")) as f:
+            return list(csv.DictReader(f))
+
+    def copy_kib(name):
+        vals = [float(r["Counter_Value"]) for r in rows(name) if "copyBuffer" in r["Kernel_Name"]]
+        if not vals:
+            raise SystemExit("no copy kernel in the %s pass" % name)
+        return max(vals)
+
+    copy_bytes = 256 << 20
+    fetch_factor = copy_bytes / 1024.0 / copy_kib("cfetch")
+    write_factor = copy_bytes / 1024.0 / copy_kib("cwrite")
+    per_launch = {}
+    for name, key, factor in (("fetch", "fetch", fetch_factor), ("write", "write", write_factor)):
+        acc = {}
+        for r in rows(name):
+            m = re.match(r"void mpc::pcg_kernel<14, 7, (\d+), (\d)>", r["Kernel_Name"])
+            if not m or m.group(2) not in MODE_OF_TEMPLATE:
+                continue
+            acc.setdefault((MODE_OF_TEMPLATE[m.group(2)], m.group(1)), []).append(float(r["Counter_Value"]))
+        for (mode, kpw), v in acc.items():
+            d = per_launch.setdefault(mode, {"knots_per_group": int(kpw)})
+            d[key + "_kib_raw"] = float(np.mean(v))
+            d["dispatches"] = len(v)
+            d[key + "_bytes"] = float(np.mean(v)) * 1024.0 * factor
+    h = hashlib.sha256()
+    for src in KERNEL_SOURCES:
+        h.update(open(os.path.join(root, src), "rb").read())
+    rec = {"workload": "batched %d x N=%d, nx=%d, nu=%d, eps=%g, seeds %d+b (bench.py --step-only)"
+                       % (BATCH, N_KNOTS, NX, NU, EPS, SEED0),
+           "kernel_sources_sha256": h.hexdigest(), "kernel_sources": KERNEL_SOURCES,
+           "calibration": {"copy_bytes": copy_bytes, "fetch_counter_kib": copy_kib("cfetch"),
+                           "write_counter_kib": copy_kib("cwrite"), "fetch_factor": fetch_factor,
+                           "write_factor": write_factor},
+           "per_launch": per_launch}
+    out = os.path.join(root, "profiles", "pcg_kernel_traffic_256xN512.json")
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+    for mode, d in sorted(per_launch.items()):
+        print("| %s (%d knots/group) | %.0f | %.0f | %.3f GB | %.3f GB | %.3f GB |" % (
+            mode, d["knots_per_group"], d["fetch_kib_raw"], d["write_kib_raw"], d["fetch_bytes"] / 1e9,
+            d["write_bytes"] / 1e9, (d["fetch_bytes"] + d["write_bytes"]) / 1e9))
+    print("wrote", out)
 
 
 def parse():
@@ -64,8 +127,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0, help="problems in the CPU sample (0 = auto)")
+    ap.add_argument("--kpw", type=int, default=16,
+                    help="knots per workgroup of the batched kernels (0 = autotune before timing)")
     ap.add_argument("--step-only", action="store_true",
                     help="time the batched step only (no single-launch comparison, no CPU baseline)")
+    ap.add_argument("--ingest-counters", default="", metavar="DIR",
+                    help="host only: turn the rocprofv3 FETCH_SIZE / WRITE_SIZE passes under DIR into "
+                         "profiles/pcg_kernel_traffic_256xN512.json and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="run one plain device-to-device copy of MIB MiB and exit (hardware-counter "
                          "calibration: bytes a copy of known size reads and writes)")
@@ -99,8 +167,153 @@ def cpu_baseline(packed_np, off, n_sample):
                        "OpenMP over problems; %.1f s wall, %.1f s CPU" % (n_sample, BATCH, N_KNOTS, wall, cpu))
 
 
+def _time_ms(fn, stream, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def single_sweep(ctx, dev, stream, reps=10):
+    """One launch per solve over horizons (seeds 2000 + N): latency, iterations, latency per
+    iteration, and the formation alone (mpcpcg_form_schur)."""
+    import torch
+    from paper_2309_08079_amd import synth
+    from paper_2309_08079_amd.mpcpcg import stats_to_numpy, to_device
+
+    rows = []
+    for N in (16, 32, 64, 128, 256, 512):
+        p = to_device(synth.problem(N, NX, NU, seed=2000 + N), dev)
+        o = dict(lam=torch.empty((N, NX), device=dev), dx=torch.empty((N, NX), device=dev),
+                 du=torch.empty((N - 1, NU), device=dev), stats=torch.zeros((1, 4), dtype=torch.int32, device=dev))
+        ms = _time_ms(lambda: ctx.mpcpcg_solve(p, eps=EPS, out=o), stream, reps)
+        it = int(stats_to_numpy(o["stats"])["iters"][0])
+        so = (torch.empty((N, 3, NX, NX), device=dev), torch.empty((N, 3, NX, NX), device=dev),
+              torch.empty((N, NX), device=dev))
+        fms = _time_ms(lambda: ctx.mpcpcg_form_schur(p, out=so), stream, reps)
+        rows.append({"N": N, "us": round(ms * 1e3, 2), "iters": it,
+                     "us_per_iter": round((ms - fms) * 1e3 / max(it, 1), 3),
+                     "formation_us": round(fms * 1e3, 2)})
+    return rows
+
+
+def mixed_batch(ctx, dev, stream, reps=5):
+    """256 problems with horizons drawn from {32, 64, 128, 256, 512} (seed 3000, problem
+    seeds 3001 + b): one batched launch against 256 one-launch-per-solve calls."""
+    import torch
+    from paper_2309_08079_amd import synth
+    from paper_2309_08079_amd.mpcpcg import stats_to_numpy, to_device
+
+    Ns = synth.horizons_uniform_choice(BATCH, seed=3000)
+    packed_np, off = synth.pack(synth.batch(Ns, NX, NU, seed0=3001))
+    d = to_device(packed_np, dev)
+    K = int(off[-1])
+    fo = dict(lam=torch.empty((K, NX), device=dev), dx=torch.empty((K, NX), device=dev),
+              du=torch.empty((K - BATCH, NU), device=dev), stats=torch.zeros((BATCH, 4), dtype=torch.int32, device=dev))
+    bms = _time_ms(lambda: ctx.mpcpcg_solve_batched(d, off, eps=EPS, out=fo), stream, reps)
+    iters = stats_to_numpy(fo["stats"])["iters"]
+    views = []
+    for b in range(BATCH):
+        k0, k1 = int(off[b]), int(off[b + 1])
+        views.append({"Q": d["Q"][k0:k1], "q": d["q"][k0:k1], "R": d["R"][k0 - b:k1 - b - 1],
+                      "A": d["A"][k0 - b:k1 - b - 1], "B": d["B"][k0 - b:k1 - b - 1],
+                      "r": d["r"][k0 - b:k1 - b - 1], "x0": d["x0"][b], "e": d["e"][k0 - b:k1 - b - 1]})
+    outs = [dict(lam=fo["lam"][int(off[b]):int(off[b + 1])], dx=fo["dx"][int(off[b]):int(off[b + 1])],
+                 du=fo["du"][int(off[b]) - b:int(off[b + 1]) - b - 1], stats=fo["stats"][b:b + 1])
+            for b in range(BATCH)]
+
+    def seq():
+        for b in range(BATCH):
+            ctx.mpcpcg_solve(views[b], eps=EPS, out=outs[b])
+    sms = _time_ms(seq, stream, 1)
+    return {"horizons": "uniform choice of {32,64,128,256,512}, seed 3000", "knots": K,
+            "iters_mean": float(iters.mean()), "batched_ms": round(bms, 3),
+            "batched_solves_per_s": BATCH / (bms * 1e-3), "sequential_ms": round(sms, 3),
+            "speedup": sms / bms}
+
+
+def warm_sequences(ctx, dev, stream, T=100, N=128):
+    """The paper's solve-time study: a receding-horizon sequence of T problems of N knots,
+    absolute stopping rule eta' < eps for eps in {1e-4, 5e-5, 1e-5}, each step solved in
+    one launch, warm-started from the previous lambda shifted by one knot or cold.  Reports
+    iterations and the distribution of per-solve device time."""
+    import torch
+    from paper_2309_08079_amd import synth
+    from paper_2309_08079_amd.mpcpcg import stats_to_numpy, to_device
+
+    steps = [to_device(p, dev) for p in synth.sequence(T, N, NX, NU, seed=8000)]
+    out = dict(lam=torch.zeros((N, NX), device=dev), dx=torch.empty((N, NX), device=dev),
+               du=torch.empty((N - 1, NU), device=dev), stats=torch.zeros((T, 4), dtype=torch.int32, device=dev))
+    lam0 = torch.zeros((N, NX), device=dev)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(T)]
+    res = {"horizon": N, "steps": T, "stop": "absolute", "seed": 8000}
+    for eps in (1e-4, 5e-5, 1e-5):
+        row = {}
+        for mode in ("cold", "warm"):
+            out["lam"].zero_()
+            for t in range(T):
+                o = dict(out, stats=out["stats"][t:t + 1])
+                warm = mode == "warm" and t > 0
+                if warm:
+                    # start from the previous multipliers shifted by one knot, staged in the
+                    # in/out buffer before the timed region
+                    lam0[:-1].copy_(out["lam"][1:])
+                    lam0[-1].copy_(out["lam"][-1])
+                    out["lam"].copy_(lam0)
+                ev[t][0].record(stream)
+                ctx.mpcpcg_solve(steps[t], eps=eps, out=o, stop="absolute",
+                                 lam0=out["lam"] if warm else None)
+                ev[t][1].record(stream)
+            torch.cuda.synchronize()
+            us = np.array([a.elapsed_time(b) * 1e3 for a, b in ev])
+            st = stats_to_numpy(out["stats"])
+            row[mode] = {"iters_mean": float(st["iters"].mean()), "iters_max": int(st["iters"].max()),
+                         "all_ok": bool((st["status"] == 0).all()),
+                         "us_p10": float(np.percentile(us, 10)), "us_p50": float(np.percentile(us, 50)),
+                         "us_p90": float(np.percentile(us, 90)), "us_max": float(us.max())}
+        res["eps_%g" % eps] = row
+    return res
+
+
+def two_arm_batch(dev, stream, reps=3):
+    """The 28-state / 14-control workload: 32 problems, horizons uniform on [64, 256]
+    (seed 5000, problem 0 forced to 256), Q diagonal on U[1e-2, 1e2], problem seeds
+    5001 + b; batched forward and adjoint (L = ||lambda||^2) times."""
+    import torch
+    from paper_2309_08079_amd import synth
+    from paper_2309_08079_amd.mpcpcg import Context, stats_to_numpy, to_device
+
+    Ns = synth.horizons_uniform_int(32, 64, 256, seed=5000, first=256)
+    packed_np, off = synth.pack(synth.batch(Ns, 28, 14, seed0=5001, q_lo=1e-2, q_hi=1e2))
+    d = to_device(packed_np, dev)
+    K = int(off[-1])
+    ctx = Context(28, 14, max_total_knots=K, max_batch=32)
+    try:
+        fo = ctx.mpcpcg_solve_batched(d, off, eps=EPS)
+        fms = _time_ms(lambda: ctx.mpcpcg_solve_batched(d, off, eps=EPS, out=fo), stream, reps)
+        gl = 2 * fo["lam"]
+        bo = ctx.mpcpcg_backward(d, off, fo, gl, eps=EPS)
+        bms = _time_ms(lambda: ctx.mpcpcg_backward(d, off, fo, gl, eps=EPS, out=bo), stream, reps)
+        fst, bst = stats_to_numpy(fo["stats"]), stats_to_numpy(bo["stats"])
+        return {"problems": 32, "knots": K, "nx": 28, "nu": 14, "forward_ms": round(fms, 3),
+                "adjoint_ms": round(bms, 3), "solves_per_s_fwd_adj": 32 / ((fms + bms) * 1e-3),
+                "iters_forward_mean": float(fst["iters"].mean()), "iters_adjoint_mean": float(bst["iters"].mean()),
+                "all_ok": bool((fst["status"] == 0).all() and (bst["status"] == 0).all())}
+    finally:
+        ctx.close()
+
+
 def main():
     args = parse()
+    if args.ingest_counters:
+        ingest_counters(args.ingest_counters)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (--gpus %d requested); batched problems "
               "are independent and would shard by problem across GPUs, see DESIGN.md" % args.gpus,
@@ -141,6 +354,13 @@ def main():
                 dx0=torch.empty((BATCH, NX), device=dev), de=torch.empty((M, NX), device=dev),
                 dgamma=torch.empty((K, NX), device=dev),
                 stats=torch.zeros((BATCH, 4), dtype=torch.int32, device=dev))
+
+    if args.kpw:
+        ctx.mpcpcg_set_knots_per_group(args.kpw)
+        kpw = args.kpw
+    else:
+        kpw = ctx.mpcpcg_autotune(d, off, eps=EPS)
+        ctx.mpcpcg_set_knots_per_group(kpw)
 
     def step(evs=None):
         if evs is not None:
@@ -183,7 +403,7 @@ def main():
     achieved = dom_flop / (dom_ms * 1e-3) / 1e12
 
     if args.step_only:
-        print(json.dumps({"ms_per_step": ms_step, "kernel_ms": {"forward": fwd_ms, "adjoint": adj_ms},
+        print(json.dumps({"ms_per_step": ms_step, "knots_per_group": kpw, "kernel_ms": {"forward": fwd_ms, "adjoint": adj_ms},
                           "iters_forward_mean": float(it_f.mean()), "iters_adjoint_mean": float(it_b.mean())}))
         return
 
@@ -219,9 +439,14 @@ def main():
     seq_ms = e0.elapsed_time(e1)
     batched_fwd_sps = BATCH / (fwd_ms * 1e-3)
 
+    sweep = single_sweep(ctx, dev, stream)
+    mixed = mixed_batch(ctx, dev, stream)
+    seqs = warm_sequences(ctx, dev, stream)
+    wide = two_arm_batch(dev, stream)
+
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(packed_np, off, args.cpu_sample or 32)
+        cpu = cpu_baseline(packed_np, off, args.cpu_sample or BATCH)
 
     line = {
         "metric": "µs/solve and PCG solves/s, Kuka nx=14 N=512; batched vs single; fwd+adjoint",
@@ -248,9 +473,13 @@ def main():
         "iters_forward_mean": float(it_f.mean()),
         "iters_adjoint_mean": float(it_b.mean()),
         "kernel_ms": {"forward": fwd_ms, "adjoint": adj_ms},
-        "roofline": {"bound": "alu", "kernel": "pcg_kernel<14,7,16,%s>" % dom_name,
+        "single_solve_sweep": sweep,
+        "mixed_batch_256": mixed,
+        "warm_sequence": seqs,
+        "two_arm_batch_32": wide,
+        "roofline": {"bound": "alu", "kernel": "pcg_kernel<14,7,%d,%s>" % (kpw, dom_name),
                      "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_VALU_TFLOPS, "traffic": measured_traffic(dom_name)},
+                     "frac": achieved / PEAK_VALU_TFLOPS, "traffic": measured_traffic(dom_name, kpw)},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -75,6 +75,32 @@ def batch(Ns, nx: int = 14, nu: int = 7, seed0: int = 0, q_lo: float = 1.0, q_hi
     return [problem(int(n), nx, nu, seed0 + b, q_lo, q_hi, defects) for b, n in enumerate(Ns)]
 
 
+def sequence(T: int, N: int, nx: int = 14, nu: int = 7, seed: int = 8000, q_lo: float = 1.0,
+             q_hi: float = 10.0, drift: float = 0.05):
+    """T consecutive receding-horizon subproblems of one synthetic trajectory.
+
+    One problem of N + T - 1 knots is drawn with ``problem(seed)``; step t takes its knots
+    t .. t+N-1 and controls t .. t+N-2, so consecutive steps share N - 1 knots shifted by
+    one, as when a controller re-solves after advancing one knot.  The initial state of
+    step t follows a drifting plant, x_{t+1} = A_t x_t + drift * w_t with
+    w_t ~ N(0,1)^nx drawn from ``seed + 1``; it never depends on a solver's output.
+    """
+    if T < 1 or N < 1:
+        raise ValueError("T and N must be >= 1")
+    base = problem(N + T - 1, nx, nu, seed, q_lo, q_hi)
+    g = np.random.default_rng(seed + 1)
+    x = base["x0"].astype(np.float64)
+    steps = []
+    for t in range(T):
+        p = {k: base[k][t:t + N] for k in ("Q", "q")}
+        p.update({k: base[k][t:t + N - 1] for k in ("R", "A", "B", "r", "e")})
+        p["x0"] = x.astype(np.float32)
+        steps.append({k: np.ascontiguousarray(v, dtype=np.float32) for k, v in p.items()})
+        if t + 1 < T:
+            x = base["A"][t].astype(np.float64) @ x + drift * g.standard_normal(nx)
+    return steps
+
+
 def pack(probs):
     """Concatenate problems into the packed layout of the batched entry points.
 
