@@ -4,17 +4,18 @@
 //   * One knot (block row b of S) per 16-lane group; lane i owns row i of the block row.
 //   * A workgroup holds KPW consecutive knots ("a part").  A problem of N knots needs
 //     ceil(N / KPW) parts; the parts of one problem form a gang that meets at gang
-//     barriers (global-memory counters) whenever data crosses a part boundary.
-//   * Registers, per lane, for the whole solve: the FP64 row of S (three nx-blocks:
-//     (b,b-1), (b,b), (b,b+1)) and the FP32 row of Phi^-1 (same three blocks), plus the
-//     PCG vectors lambda, r, p and the halo copies of p and r for knots b-1 and b+1.
+//     barriers (tagged words in global memory) whenever data crosses a part boundary.
+//   * For the whole solve each lane keeps the FP64 row of S (three nx-blocks: (b,b-1),
+//     (b,b), (b,b+1)) in registers and its FP32 row of Phi^-1 (same three blocks) in LDS,
+//     plus the PCG vectors lambda, r, p, s = S p and copies of r and s for knots b-1, b+1.
 //
 // Method (MPCGPU): S, gamma follow Section III-B (theta_k, phi_k, zeta_k; S and gamma
 // negated so S is positive definite), Phi^-1 follows Section IV-A (symmetric stair:
-// D_b^-1 on the diagonal, -D_b^-1 S_{b,b+-1} D_{b+-1}^-1 beside it), the loop follows
-// Algorithm 1 as distributed per block row in Algorithm 2 (two reductions per iteration,
-// halos of neighbouring block rows), and the primal step is dZ = -G^-1 (g - C^T lambda).
-// The stopping rule is sqrt(eta/eta_ref) < eps with eta_ref = gamma^T Phi^-1 gamma.
+// D_b^-1 on the diagonal, -D_b^-1 S_{b,b+-1} D_{b+-1}^-1 beside it), the loop computes
+// the iterates of Algorithm 1 per block row as Algorithm 2 distributes it, with its two
+// inner products gathered at one barrier per iteration, and the primal step is
+// dZ = -G^-1 (g - C^T lambda).  Stopping rule: sqrt(eta/eta_ref) < eps with
+// eta_ref = gamma^T Phi^-1 gamma, or eta < eps as Algorithm 1 prints it.
 //
 // Precision: inputs/outputs FP32; formation, S, the PCG vectors and all reductions in
 // FP64; Phi^-1 stored and applied in FP32 (a preconditioner only changes the Krylov
@@ -55,7 +56,6 @@ struct alignas(256) Gang {
 struct TagWS {
   uint64_t red[2][2][2];              // [parity][value][half] this part's partial sums
   uint64_t hv[2][2][2][kGroup][2];    // [parity][channel][side][lane][half] double halos
-  uint64_t hf[2][2][kGroup];          // [parity][side][lane] float halos
 };
 
 template <int NX>
@@ -65,6 +65,10 @@ struct TaskWS {       // per task; read by the other parts of the same gang
   uint64_t flag;
   uint64_t pad[7];
   double hm[2][NX][kGroup];      // [side][row][col] D^-1 rows of the two boundary knots
+  // setup exchange (flag stage 2, once Phi^-1 exists): the boundary knots' Phi^-1 rows and
+  // two halo channels (gamma at depths 1 and 2, or gamma and lambda_0 at depth 1)
+  float hp[2][NX][3 * NX];       // [side][row][col]
+  double hs[2][2][kGroup];       // [side][channel][lane]
 };
 
 // Integral constant for the compile-time shape of a barrier.
@@ -73,14 +77,25 @@ struct IC {
   static constexpr int value = V;
 };
 
-__device__ __forceinline__ void store_tagged2(uint64_t *w, uint32_t tag, double v) {
-  const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const uint64_t t = (uint64_t)tag << 32;
-  __hip_atomic_store(&w[0], t | (uint32_t)u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(&w[1], t | (uint32_t)(u >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// The two tagged words of a double move as one 16-byte device-scope (sc1) buffer access:
+// one memory request instead of two.  Each aligned 8-byte word inside it is still read and
+// written whole, so the per-word tags keep validating every word.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kDeviceScope = 16;  // cache-policy bit sc1
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t ws_rsrc(void *base) {
+  return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, 0x7fffffff, 0x00020000);
 }
-__device__ __forceinline__ double untag2(uint64_t lo, uint64_t hi) {
-  return __builtin_bit_cast(double, (hi << 32) | (uint32_t)lo);
+__device__ __forceinline__ void store_pair(__amdgpu_buffer_rsrc_t rs, uint32_t off, uint32_t tag, double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const u32x4 d = {(uint32_t)u, tag, (uint32_t)(u >> 32), tag};
+  __builtin_amdgcn_raw_buffer_store_b128(d, rs, off, 0, kDeviceScope);
+}
+__device__ __forceinline__ u32x4 load_pair(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kDeviceScope);
+}
+__device__ __forceinline__ bool pair_has(u32x4 w, uint32_t tag) { return w.y == tag && w.w == tag; }
+__device__ __forceinline__ double pair_value(u32x4 w) {
+  return __builtin_bit_cast(double, ((uint64_t)w.z << 32) | w.x);
 }
 
 struct KArgs {
@@ -142,15 +157,18 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
   __shared__ float ex_f[KPW + 2][kGroup];
   // One LDS region serves two phases: the D^-1 row exchange of the formation, then the
   // FP32 Phi^-1 rows for the rest of the solve (row r of knot slot s at
-  // pl[(s * 16 + r) * kPRow], blocks (b,b-1), (b,b), (b,b+1) at offsets 0, 14, 28).
+  // pl[(s * NX + r) * kPRow], blocks (b,b-1), (b,b), (b,b+1) at offsets 0, 14, 28; slots
+  // KPW and KPW + 1 hold the rows of the neighbouring parts' boundary knots b0 - 1 and
+  // b_last + 1, the "ghost" knots whose preconditioned residual this part recomputes).
   constexpr int kPRow = 44;
   constexpr size_t kExBytes = sizeof(double) * (KPW + 2) * NX * kGroup;
-  constexpr size_t kPlBytes = sizeof(float) * KPW * kGroup * kPRow;
+  constexpr size_t kPlBytes = sizeof(float) * (KPW + 2) * NX * kPRow;
   __shared__ __attribute__((aligned(16))) unsigned char big[kExBytes > kPlBytes ? kExBytes : kPlBytes];
   auto ex_m = reinterpret_cast<double (*)[NX][kGroup]>(big);
   float *const pl = reinterpret_cast<float *>(big);
   __shared__ double red_w[2][2][NW];           // [phase][value][wave]
   __shared__ double tot[2];
+  __shared__ double d2[2][2][kGroup];  // [side][r, s][lane] two knots beyond each end
   __shared__ int sh_task;
   __shared__ int sh_abort;
 
@@ -164,6 +182,8 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
   int wave = tid >> 6;
   int wl = tid & 63;
   TaskWS<NX> *tws = reinterpret_cast<TaskWS<NX> *>(a.tws);
+  const __amdgpu_buffer_rsrc_t wsr = ws_rsrc(a.tws);
+  auto ws_off = [&](const void *p) { return (uint32_t)((const char *)p - (const char *)a.tws); };
   // launch generation: advanced by the last workgroup of every launch, so flags written
   // by earlier launches are always older than any epoch of this one
   const uint64_t gen = (uint64_t)(uint32_t)uni(__hip_atomic_load(&a.queue[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
@@ -246,10 +266,10 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       }
       return 0;
     };
-    // Loop barrier: ND double channels and NF float channel of halos, NR partial sums
+    // Loop barrier: ND double channels of halos, NR partial sums
     // (read from red_w[ph] when the problem has one part); totals land in tot[].
-    auto sync_point = [&](auto nd_c, auto nf_c, auto nr_c, int ph) {
-      constexpr int ND = decltype(nd_c)::value, NF = decltype(nf_c)::value, NR = decltype(nr_c)::value;
+    auto sync_point = [&](auto nd_c, auto nr_c, int ph) {
+      constexpr int ND = decltype(nd_c)::value, NR = decltype(nr_c)::value;
       __syncthreads();
       if (multi) {
         if (wave == 0) {
@@ -259,14 +279,14 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
             double ps = 0.0;
 #pragma unroll
             for (int w = 0; w < NW; ++w) ps += red_w[ph][wl][w];
-            store_tagged2(tws[my_t].tg.red[par][wl], tag, ps);
+            store_pair(wsr, ws_off(tws[my_t].tg.red[par][wl]), tag, ps);
           }
           const int side = wl >> 4, l = wl & 15;
           const int nb = side == 0 ? part - 1 : part + 1;
           const bool has = wl < 2 * kGroup && nb >= 0 && nb < G;
           const TagWS *hsrc = &tws[has ? my_t + (side == 0 ? -1 : 1) : my_t].tg;
           const int srcside = side == 0 ? 1 : 0;  // left neighbour's last knot / right's first
-          uint64_t hd[ND > 0 ? ND : 1][2], hfw = 0;
+          u32x4 hq[ND > 0 ? ND : 1];
           double v0 = 0.0, v1 = 0.0;
           int ab = 0, polls = 0;
           const long long t_start = wall_clock64();
@@ -275,29 +295,21 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
             const bool mine = NR > 0 && g < G;
             const bool halo = g0 == 0 && has;
             const TagWS *rsrc = &tws[pd.t0 + (mine ? g : 0)].tg;
-            uint64_t rw[NR > 0 ? NR : 1][2];
+            u32x4 rw[NR > 0 ? NR : 1];
             while (true) {
               bool ok = true;
               if (mine) {
 #pragma unroll
-                for (int v = 0; v < NR; ++v)
-#pragma unroll
-                  for (int h = 0; h < 2; ++h) {
-                    rw[v][h] = __hip_atomic_load(&rsrc->red[par][v][h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok &= (uint32_t)(rw[v][h] >> 32) == tag;
-                  }
+                for (int v = 0; v < NR; ++v) {
+                  rw[v] = load_pair(wsr, ws_off(rsrc->red[par][v]));
+                  ok &= pair_has(rw[v], tag);
+                }
               }
               if (halo) {
 #pragma unroll
-                for (int c = 0; c < ND; ++c)
-#pragma unroll
-                  for (int h = 0; h < 2; ++h) {
-                    hd[c][h] = __hip_atomic_load(&hsrc->hv[par][c][srcside][l][h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok &= (uint32_t)(hd[c][h] >> 32) == tag;
-                  }
-                if (NF) {
-                  hfw = __hip_atomic_load(&hsrc->hf[par][srcside][l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                  ok &= (uint32_t)(hfw >> 32) == tag;
+                for (int c = 0; c < ND; ++c) {
+                  hq[c] = load_pair(wsr, ws_off(hsrc->hv[par][c][srcside][l]));
+                  ok &= pair_has(hq[c], tag);
                 }
               }
               if (__ballot(ok) == ~0ull) break;
@@ -306,15 +318,14 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
             // totals over parts in a fixed order and a fixed-shape reduction, so every part
             // computes bit-identical totals
             if (mine && !ab) {
-              v0 += untag2(rw[0][0], rw[0][1]);
-              if (NR > 1) v1 += untag2(rw[NR > 1 ? 1 : 0][0], rw[NR > 1 ? 1 : 0][1]);
+              v0 += pair_value(rw[0]);
+              if (NR > 1) v1 += pair_value(rw[NR > 1 ? 1 : 0]);
             }
           }
           if (wl < 2 * kGroup && !ab) {
             const int dst = side == 0 ? 0 : KPW + 1;
 #pragma unroll
-            for (int c = 0; c < ND; ++c) ex_d[c][dst][l] = has ? untag2(hd[c][0], hd[c][1]) : 0.0;
-            if (NF) ex_f[dst][l] = has ? __builtin_bit_cast(float, (uint32_t)hfw) : 0.0f;
+            for (int c = 0; c < ND; ++c) ex_d[c][dst][l] = has ? pair_value(hq[c]) : 0.0;
           }
           const double w0 = wave_sum(v0), w1 = wave_sum(v1);
           if (wl == 0) {
@@ -378,20 +389,72 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       }
     };
 
+    // Setup barrier (barrier 1, flag stage 2): the neighbours' boundary Phi^-1 rows go to the
+    // ghost slots of pl, and two double halo channels to the halo slots of ex_d.
+    auto sync_setup = [&]() {
+      if (multi) __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (!multi) {
+        for (int t = tid; t < 2 * NX * kPRow; t += NT) pl[KPW * NX * kPRow + t] = 0.0f;
+        __syncthreads();
+        return;
+      }
+      const uint64_t epoch = (gen << 32) | 2u;
+      if (wave == 0) {
+        if (wl == 0) __hip_atomic_store(&tws[my_t].flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const long long t_start = wall_clock64();
+        int ab = 0, polls = 0;
+        const int nb = wl == 0 ? part - 1 : part + 1;
+        const bool want = wl < 2 && nb >= 0 && nb < G;
+        while (true) {
+          const bool seen = !want || __hip_atomic_load(&tws[pd.t0 + nb].flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+          if (__ballot(seen) == ~0ull) break;
+          if ((ab = poll_spin(polls, t_start))) break;
+        }
+        if (!ab) {
+          constexpr int kRowsF = NX * 3 * NX;
+          for (int t = wl; t < 2 * kRowsF; t += 64) {
+            const int side = t / kRowsF, rem = t % kRowsF, rr = rem / (3 * NX), cc = rem % (3 * NX);
+            const int nbh = side == 0 ? part - 1 : part + 1;
+            const bool has = nbh >= 0 && nbh < G;
+            const TaskWS<NX> *src = &tws[has ? my_t + (side == 0 ? -1 : 1) : my_t];
+            pl[((KPW + side) * NX + rr) * kPRow + cc] =
+                has ? __hip_atomic_load(&src->hp[side == 0 ? 1 : 0][rr][cc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0f;
+          }
+          if (wl < 2 * kGroup) {
+            const int side = wl >> 4, l = wl & 15;
+            const int nbh = side == 0 ? part - 1 : part + 1;
+            const bool has = nbh >= 0 && nbh < G;
+            const TaskWS<NX> *src = &tws[has ? my_t + (side == 0 ? -1 : 1) : my_t];
+            const int dst = side == 0 ? 0 : KPW + 1;
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+              ex_d[c][dst][l] = has ? __hip_atomic_load(&src->hs[side == 0 ? 1 : 0][c][l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+          }
+        }
+        if (wl == 0) sh_abort = ab;
+      }
+      __syncthreads();
+      ++nsync;
+      aborted = uni(sh_abort) != 0;
+    };
+
     // publish this group's value of a double vector channel (LDS + boundary halo)
     auto put_d = [&](int c, double v) {
       ex_d[c][slot + 1][lane] = v;
       if (multi && (slot == 0 || slot == KPW - 1)) {
-        uint64_t *w = tws[my_t].tg.hv[nsync & 1][c][slot == 0 ? 0 : 1][lane];
-        store_tagged2(w, (uint32_t)nsync + 1u, v);
+        store_pair(wsr, ws_off(tws[my_t].tg.hv[nsync & 1][c][slot == 0 ? 0 : 1][lane]), (uint32_t)nsync + 1u, v);
       }
     };
-    auto put_f = [&](float v) {
-      ex_f[slot + 1][lane] = v;
-      if (multi && (slot == 0 || slot == KPW - 1))
-        __hip_atomic_store(&tws[my_t].tg.hf[nsync & 1][slot == 0 ? 0 : 1][lane],
-                           ((uint64_t)((uint32_t)nsync + 1u) << 32) | __builtin_bit_cast(uint32_t, v),
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // publish a double vector whose neighbours need two knots deep: LDS channel 0, and to the
+    // gang channel 0 (boundary knots) / channel 1 (second knots in from each end)
+    auto put_d2 = [&](double v) {
+      ex_d[0][slot + 1][lane] = v;
+      if (multi && (slot <= 1 || slot >= KPW - 2)) {
+        const int side = slot <= 1 ? 0 : 1;
+        const int c = (slot == 0 || slot == KPW - 1) ? 0 : 1;
+        store_pair(wsr, ws_off(tws[my_t].tg.hv[nsync & 1][c][side][lane]), (uint32_t)nsync + 1u, v);
+      }
     };
     // per-wave partial of a lane value (deterministic order), written to red_w[ph][v]
     auto put_red = [&](int ph, int v, double x) {
@@ -601,8 +664,8 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
     } else {
       // Phi^-1 rows move to LDS for the solve (the D^-1 exchange above used the same bytes)
       __syncthreads();
-      {
-        float *row = pl + (slot * kGroup + lane) * kPRow;
+      if (rowv) {
+        float *row = pl + (slot * NX + lane) * kPRow;
 #pragma unroll
         for (int j = 0; j < NX; ++j) {
           row[j] = Pm[j];
@@ -612,10 +675,11 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       }
       // ================================================================== PCG
       refresh();
-      // r~ row = Phi^-1 row . [x(b-1), x(b), x(b+1)], the row read back from LDS one block
-      // at a time so that only 14 of its values occupy registers
-      auto precond_row = [&](float xm, float x0v, float xp) {
-        const float *row = pl + (slot * kGroup + lane) * kPRow;
+      // r~ row = Phi^-1 row . [x(b-1), x(b), x(b+1)] for the rows of knot slot ps (a ghost
+      // slot for the recomputed neighbour knots), read back one block at a time so that
+      // only 14 of its values occupy registers
+      auto precond_row = [&](int ps, float xm, float x0v, float xp) {
+        const float *row = pl + (ps * NX + (rowv ? lane : 0)) * kPRow;
         float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
         float m[NX];
 #pragma unroll
@@ -627,98 +691,146 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
 #pragma unroll
         for (int j = 0; j < NX; ++j) m[j] = row[2 * NX + j];
         row_fma14_f32(acc2, xp, m);
-        return (acc0 + acc1) + acc2;
+        return rowv ? (acc0 + acc1) + acc2 : 0.0f;
       };
-      // two barriers per iteration; the cap keeps barrier tags far from 32-bit wrap-around
-      const int max_iter = (int)min((int64_t)(a.max_iter > 0 ? a.max_iter : (int64_t)N * NX), (int64_t)1 << 28);
-      double lam = 0.0, r = rhs, p, pm, pp, rm, rp;
-      // eta_ref = rhs^T Phi^-1 rhs
-      put_d(0, rhs);
-      if (MODE == kForward && a.warm && act && rowv) lam = (double)a.lam[kb * NX + lane];
-      put_d(1, lam);
-      sync_point(IC<2>{}, IC<0>{}, IC<0>{}, 0);
-      const double gm = ex_d[0][slot][lane], gp = ex_d[0][slot + 2][lane];
-      const float gt = precond_row((float)gm, (float)rhs, (float)gp);
+      // one barrier per iteration; the cap keeps barrier tags far from 32-bit wrap-around
+      const int max_iter = (int)min((int64_t)(a.max_iter > 0 ? a.max_iter : (int64_t)N * NX), (int64_t)1 << 29);
       const bool warm = (MODE == kForward) && a.warm;
-      rm = gm;
-      rp = gp;
+      double lam = 0.0;
+      if (warm && act && rowv) lam = (double)a.lam[kb * NX + lane];
+      // setup exchange: boundary Phi^-1 rows; gamma at depths 1 and 2 (cold) or gamma and
+      // lambda_0 at depth 1 (warm); device-scope stores, completed before the stage flag
+      if (multi && (slot <= 1 || slot >= KPW - 2)) {
+        TaskWS<NX> &w = tws[my_t];
+        const int side = slot <= 1 ? 0 : 1;
+        if (slot == 0 || slot == KPW - 1) {
+          if (rowv) {
+#pragma unroll
+            for (int j = 0; j < NX; ++j) {
+              __hip_atomic_store(&w.hp[side][lane][j], Pm[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              __hip_atomic_store(&w.hp[side][lane][NX + j], Pd[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              __hip_atomic_store(&w.hp[side][lane][2 * NX + j], Pp[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+          }
+          __hip_atomic_store(&w.hs[side][0][lane], rhs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (warm) __hip_atomic_store(&w.hs[side][1][lane], lam, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else if (!warm) {
+          __hip_atomic_store(&w.hs[side][1][lane], rhs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      ex_d[0][slot + 1][lane] = rhs;
+      ex_d[1][slot + 1][lane] = warm ? lam : 0.0;
+      sync_setup();
+      double r = rhs, rm = ex_d[0][slot][lane], rp = ex_d[0][slot + 2][lane];
+      // r and s of the knots two beyond each end live in d2, touched only by the edge slots
+      if (slot == 0) { d2[0][0][lane] = ex_d[1][0][lane]; d2[0][1][lane] = 0.0; }
+      if (slot == KPW - 1) { d2[1][0][lane] = ex_d[1][KPW + 1][lane]; d2[1][1][lane] = 0.0; }
+      double eta_ref = 0.0;
       if (warm) {
-        // r = gamma - S lambda_0
+        // r = gamma - S lambda_0; eta_ref = gamma^T Phi^-1 gamma; then r's halos two deep
         const double lm = ex_d[1][slot][lane], lp = ex_d[1][slot + 2][lane];
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
         row_fma14_f64(a0, lm, Sm);
         row_fma14_f64(a1, lam, Sd);
         row_fma14_f64(a2, lp, Sp);
         r = rhs - ((a0 + a1) + a2);
-        put_d(0, r);
-          sync_point(IC<1>{}, IC<0>{}, IC<0>{}, 1);
+        const float gt = precond_row(slot, (float)rm, (float)rhs, (float)rp);
+        put_red(0, 0, rhs * (double)gt);
+        __syncthreads();  // every halo read of the setup channels is done
+        put_d2(r);
+        sync_point(IC<2>{}, IC<1>{}, 0);
+        eta_ref = uni(tot[0]);
         rm = ex_d[0][slot][lane];
         rp = ex_d[0][slot + 2][lane];
+        if (slot == 0) d2[0][0][lane] = ex_d[1][0][lane];
+        if (slot == KPW - 1) d2[1][0][lane] = ex_d[1][KPW + 1][lane];
       }
-      const float rt = warm ? precond_row((float)rm, (float)r, (float)rp) : gt;
-      // eta_0 = r^T r~ and eta_ref = rhs^T Phi^-1 rhs; p = r~ (halo via the float channel)
-      put_red(0, 0, r * (double)rt);
-      put_red(0, 1, rhs * (double)gt);
-      put_f(rt);
-      sync_point(IC<0>{}, IC<1>{}, IC<2>{}, 0);
-      double eta = uni(tot[0]);
-      const double eta_ref = uni(tot[1]);
-      const double tau = a.stop_abs ? (double)a.eps : (double)a.eps * (double)a.eps * eta_ref;
-      p = (double)rt;
-      pm = (double)ex_f[slot][lane];
-      pp = (double)ex_f[slot + 2][lane];
+      // Algorithm 1 with its two inner products gathered at one barrier per iteration
+      // (Chronopoulos-Gear form): u = Phi^-1 r and w = S u, then gam = r^T u (= eta') and
+      // delta = w^T u meet at the barrier; p^T S p = delta - beta gam / alpha_prev, and the
+      // recurrences p = u + beta p, s = w + beta s (s = S p), lambda += alpha p,
+      // r -= alpha s give the iterates of Algorithm 1.  Each part keeps r and s of the
+      // two knots beyond each of its ends (bit-identical copies, updated from the
+      // neighbours' w), and recomputes u of the adjacent knot itself from a copy of that
+      // knot's Phi^-1 row, so no second exchange is needed inside an iteration.
+      double p = 0.0, sv = 0.0, sm = 0.0, sp = 0.0;
+      double gam_prev = 1.0, alpha_prev = 1.0, tau = 0.0, eta_new = 0.0;
       int status = MPCPCG_NOT_CONVERGED;
       int it = 0;
-      double eta_new = eta;
-      if (!(eta == eta) || !(eta_ref == eta_ref) || __builtin_isinf(eta) || __builtin_isinf(eta_ref)) {
-        status = MPCPCG_BREAKDOWN;
-      } else if (eta <= tau) {
-        status = MPCPCG_OK;
-      } else {
-        for (it = 1; it <= max_iter && !aborted; ++it) {
-          // ---- phase A: Y = S p, upsilon = p^T Y
-          double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-          row_fma14_f64(a0, pm, Sm);
-          row_fma14_f64(a1, p, Sd);
-          row_fma14_f64(a2, pp, Sp);
-          const double Y = (a0 + a1) + a2;
-          put_red(0, 0, p * Y);
-          put_d(0, Y);
-              sync_point(IC<1>{}, IC<0>{}, IC<1>{}, 0);
-          const double ups = uni(tot[0]);
-          if (!(ups > 0.0) || __builtin_isinf(ups)) {
-            status = MPCPCG_BREAKDOWN;
-            break;
-          }
-          const double alpha = eta / ups;
-          const double Ym = ex_d[0][slot][lane], Yp = ex_d[0][slot + 2][lane];
-          lam = __builtin_fma(alpha, p, lam);
-          r = __builtin_fma(-alpha, Y, r);
-          rm = __builtin_fma(-alpha, Ym, rm);
-          rp = __builtin_fma(-alpha, Yp, rp);
-          // ---- phase B: r~ = Phi^-1 r, eta' = r^T r~
-          const float rtn = precond_row((float)rm, (float)r, (float)rp);
-          put_red(1, 0, r * (double)rtn);
-          put_f(rtn);
-              sync_point(IC<0>{}, IC<1>{}, IC<1>{}, 1);
-          eta_new = uni(tot[0]);
-          if (!(eta_new == eta_new) || __builtin_isinf(eta_new)) {
-            status = MPCPCG_BREAKDOWN;
-            break;
-          }
-          if (eta_new < tau) {
-            status = MPCPCG_OK;
-            break;
-          }
-          // ---- phase C: p = r~ + beta p (own knot and both halo copies)
-          const double beta = eta_new / eta;
-          p = __builtin_fma(beta, p, (double)rtn);
-          pm = __builtin_fma(beta, pm, (double)ex_f[slot][lane]);
-          pp = __builtin_fma(beta, pp, (double)ex_f[slot + 2][lane]);
-          eta = eta_new;
+      const bool edge_wave = multi && (wave == 0 || wave == NW - 1);
+      for (it = 0;; ++it) {
+        if (aborted) break;
+        // (1) u = Phi^-1 r on this knot, and on the ghost knot beyond each end
+        const float u = precond_row(slot, (float)rm, (float)r, (float)rp);
+        ex_f[slot + 1][lane] = u;
+        if (edge_wave) {
+          const bool left = slot == 0;
+          const double r2 = d2[left ? 0 : 1][0][lane];
+          const float ug = precond_row(left ? KPW : KPW + 1, (float)(left ? r2 : r), (float)(left ? rm : rp),
+                                       (float)(left ? r : r2));
+          if (slot == 0) ex_f[0][lane] = ug;
+          if (slot == KPW - 1) ex_f[KPW + 1][lane] = ug;
         }
-        if (it > max_iter) it = max_iter;
+        __syncthreads();
+        // (2) w = S u
+        const double um = (double)ex_f[slot][lane], up = (double)ex_f[slot + 2][lane];
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        row_fma14_f64(a0, um, Sm);
+        row_fma14_f64(a1, (double)u, Sd);
+        row_fma14_f64(a2, up, Sp);
+        const double w = (a0 + a1) + a2;
+        // (3) gam = r^T u, delta = w^T u; w two knots deep to the neighbours
+        put_red(0, 0, r * (double)u);
+        put_red(0, 1, w * (double)u);
+        put_d2(w);
+        sync_point(IC<2>{}, IC<2>{}, 0);
+        const double gam = uni(tot[0]), del = uni(tot[1]);
+        eta_new = gam;
+        if (it == 0) {
+          if (!warm) eta_ref = gam;  // lambda_0 = 0: r = gamma, so gam = gamma^T Phi^-1 gamma
+          tau = a.stop_abs ? (double)a.eps : (double)a.eps * (double)a.eps * eta_ref;
+          if (!(eta_ref == eta_ref) || __builtin_isinf(eta_ref)) {
+            status = MPCPCG_BREAKDOWN;
+            break;
+          }
+        }
+        if (!(gam == gam) || __builtin_isinf(gam)) {
+          status = MPCPCG_BREAKDOWN;
+          break;
+        }
+        if (it == 0 ? gam <= tau : gam < tau) {
+          status = MPCPCG_OK;
+          break;
+        }
+        if (it >= max_iter) break;
+        const double beta = it == 0 ? 0.0 : gam / gam_prev;
+        const double pSp = it == 0 ? del : del - beta * gam / alpha_prev;
+        if (!(pSp > 0.0) || __builtin_isinf(pSp)) {
+          status = MPCPCG_BREAKDOWN;
+          break;
+        }
+        const double alpha = gam / pSp;
+        // (4) recurrences on this knot and on the halo copies (depth 1 everywhere, depth 2
+        //     at the part's ends)
+        const double wm = ex_d[0][slot][lane], wp = ex_d[0][slot + 2][lane];
+        p = __builtin_fma(beta, p, (double)u);
+        sv = __builtin_fma(beta, sv, w);
+        sm = __builtin_fma(beta, sm, wm);
+        sp = __builtin_fma(beta, sp, wp);
+        lam = __builtin_fma(alpha, p, lam);
+        r = __builtin_fma(-alpha, sv, r);
+        rm = __builtin_fma(-alpha, sm, rm);
+        rp = __builtin_fma(-alpha, sp, rp);
+        if (multi && (slot == 0 || slot == KPW - 1)) {
+          const int side = slot == 0 ? 0 : 1;
+          const double s2 = __builtin_fma(beta, d2[side][1][lane], ex_d[1][side ? KPW + 1 : 0][lane]);
+          d2[side][1][lane] = s2;
+          d2[side][0][lane] = __builtin_fma(-alpha, s2, d2[side][0][lane]);
+        }
+        gam_prev = gam;
+        alpha_prev = alpha;
       }
+      if (it > max_iter) it = max_iter;
       if (aborted) status = MPCPCG_TIMEOUT;
       if (!rowv || !act) lam = 0.0;
 
@@ -728,7 +840,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       // adjoint): x rows use Q_b^-1 and S_{b,b+1} = -Q_b^-1 A_b^T; u rows of control b-1
       // use R_{b-1}^-1 and W = R_{b-1}^-1 B_{b-1}^T (both written during formation).
       put_d(0, lam);
-      sync_point(IC<1>{}, IC<0>{}, IC<0>{}, 0);
+      sync_point(IC<1>{}, IC<0>{}, 0);
       const double lp = ex_d[0][slot + 2][lane];
       double qmin = 0.0;   // q_b - lambda_b  (or gx_b - mu_b)
       if (act && rowv) {
@@ -767,7 +879,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         // adjoint: lam holds mu, xrow = nu1x_b, urow = nu1u_{b-1}
         const double mu = lam, n1x = xrow, n1u = urow;
         put_d(0, n1x);
-          sync_point(IC<1>{}, IC<0>{}, IC<0>{}, 1);
+          sync_point(IC<1>{}, IC<0>{}, 1);
         const double n1xm = ex_d[0][slot][lane];  // nu1x_{b-1}
         double dxb = 0.0, dxm = 0.0, lb = 0.0, dum = 0.0;
         if (act && rowv) {
