@@ -309,6 +309,39 @@ def two_arm_batch(dev, stream, reps=3):
         ctx.close()
 
 
+def factor_path(dev, stream, reps=3):
+    """The factorisation path (block LDL^T of S, MPCPCG_METHOD_FACTOR) on the headline batch
+    and on one N = 512 problem: batched forward and adjoint, single-solve latency."""
+    import torch
+    from paper_2309_08079_amd import synth
+    from paper_2309_08079_amd.mpcpcg import Context, stats_to_numpy, to_device
+
+    probs = synth.batch([N_KNOTS] * BATCH, NX, NU, seed0=SEED0)
+    packed_np, off = synth.pack(probs)
+    d = to_device(packed_np, dev)
+    K = int(off[-1])
+    ctx = Context(NX, NU, max_total_knots=K, max_batch=BATCH)
+    try:
+        ctx.mpcpcg_set_method("factor")
+        fo = ctx.mpcpcg_solve_batched(d, off, eps=EPS)
+        fms = _time_ms(lambda: ctx.mpcpcg_solve_batched(d, off, eps=EPS, out=fo), stream, reps)
+        gl = 2 * fo["lam"]
+        bo = ctx.mpcpcg_backward(d, off, fo, gl, eps=EPS)
+        bms = _time_ms(lambda: ctx.mpcpcg_backward(d, off, fo, gl, eps=EPS, out=bo), stream, reps)
+        ok = bool((stats_to_numpy(fo["stats"])["status"] == 0).all() and (stats_to_numpy(bo["stats"])["status"] == 0).all())
+        single = {k: v[:N_KNOTS] for k, v in d.items() if k in ("Q", "q")}
+        for k in ("R", "A", "B", "r", "e"):
+            single[k] = d[k][:N_KNOTS - 1]
+        single["x0"] = d["x0"][0]
+        so = ctx.mpcpcg_solve(single, eps=EPS)
+        sms = _time_ms(lambda: ctx.mpcpcg_solve(single, eps=EPS, out=so), stream, 10)
+        return {"batch": BATCH, "knots": N_KNOTS, "forward_ms": round(fms, 3), "adjoint_ms": round(bms, 3),
+                "solves_per_s_fwd_adj": BATCH / ((fms + bms) * 1e-3), "single_solve_us_N512": round(sms * 1e3, 2),
+                "all_ok": ok}
+    finally:
+        ctx.close()
+
+
 def main():
     args = parse()
     if args.ingest_counters:
@@ -443,6 +476,7 @@ def main():
     mixed = mixed_batch(ctx, dev, stream)
     seqs = warm_sequences(ctx, dev, stream)
     wide = two_arm_batch(dev, stream)
+    fac = factor_path(dev, stream)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -477,6 +511,7 @@ def main():
         "mixed_batch_256": mixed,
         "warm_sequence": seqs,
         "two_arm_batch_32": wide,
+        "factorisation_path": fac,
         "roofline": {"bound": "alu", "kernel": "pcg_kernel<14,7,%d,%s>" % (kpw, dom_name),
                      "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_VALU_TFLOPS, "traffic": measured_traffic(dom_name, kpw)},

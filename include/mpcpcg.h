@@ -168,6 +168,23 @@ int mpcpcg_autotune(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
 /* Enable (1, default) or disable (0) hipGraph capture/replay in mpcpcg_solve_batched. */
 int mpcpcg_set_graph(mpcpcg_ctx *ctx, int32_t enable);
 
+/* Solution method of mpcpcg_solve, mpcpcg_solve_batched and mpcpcg_backward.
+ *   MPCPCG_METHOD_PCG (default): PCG as above (Algorithm 1).
+ *   MPCPCG_METHOD_FACTOR: direct solve of the same Schur system by block LDL^T
+ *     factorisation of the block-tridiagonal S (D_0 = S_00, D_k = S_kk - S_{k,k-1}
+ *     D_{k-1}^-1 S_{k-1,k}, forward and back substitution), the alternative to the
+ *     iterative solve that the paper names as future work (Section VI).  FP64 throughout,
+ *     exact up to rounding; eps, max_iter, warm_start and stop_rule are ignored;
+ *     stats report iters = 0, status OK or BREAKDOWN (non-finite result), final_ratio = 0.
+ *     Each problem is swept sequentially by one 16-lane group, so a call costs ~N steps
+ *     whatever the batch: it wins when many problems are solved at once.  Needs
+ *     ~6.5 KB of extra device workspace per knot of max_total_knots, allocated on first use.
+ *     (nx, nu) = (14, 7) only; MPCPCG_EUNSUPPORTED otherwise.
+ *   MPCPCG_METHOD_AUTO: per call, the factorisation when the batch would need several
+ *     rounds of resident PCG workgroups (by a cost model of both), else PCG. */
+enum { MPCPCG_METHOD_PCG = 0, MPCPCG_METHOD_FACTOR = 1, MPCPCG_METHOD_AUTO = 2 };
+int mpcpcg_set_method(mpcpcg_ctx *ctx, int32_t method);
+
 #ifdef __cplusplus
 }
 #endif

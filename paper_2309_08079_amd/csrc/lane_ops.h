@@ -172,11 +172,15 @@ __device__ __forceinline__ void outer_row(double (&C)[LC], double s, double x) {
 // scaled by d = 1/a_kk, every other row i loses (a_ik d) times the pivot row, and column
 // k becomes (d for the pivot row, -a_ik d otherwise).  Written as t = s*a + c*bc_k(a)
 // with (s, c) = (0, d) on the pivot lane and (1, -a_ik d) elsewhere.
+// `positive` (optional) ends false when a pivot is not > 0, i.e. when the matrix is not
+// positive definite (every pivot of an SPD matrix is positive).
 template <int n, int L>
-__device__ __forceinline__ void gj_inverse(double (&a)[L], int lane) {
+__device__ __forceinline__ void gj_inverse(double (&a)[L], int lane, bool *positive = nullptr) {
   static_for<0, n>([&](auto kk) {
     constexpr int k = decltype(kk)::value;
-    const double d = 1.0 / bc<k>(a[k]);
+    const double piv = bc<k>(a[k]);
+    if (positive) *positive = *positive && (piv > 0.0);
+    const double d = 1.0 / piv;
     const bool me = (lane == k);
     const double f = a[k] * d;
     const double sc = me ? 0.0 : 1.0;

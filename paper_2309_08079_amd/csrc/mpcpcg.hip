@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -14,6 +15,7 @@
 
 #include "mpcpcg.h"
 #include "pcg_kernel.h"
+#include "tri_kernel.h"
 #include "wide_kernels.h"
 
 namespace {
@@ -36,6 +38,7 @@ struct Schedule {
   int ntasks = 0;
   int nprobs = 0;
   ProbDesc *d_probs = nullptr;
+  ProbDesc *d_sorted = nullptr;  // the same descriptors, longest first (factorisation sweep)
   Task *d_tasks = nullptr;
   hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
   hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
@@ -59,6 +62,9 @@ struct mpcpcg_ctx {
   int64_t max_tasks = 0;
   int kpw_override = 0;
   int use_graph = 1;
+  int method = MPCPCG_METHOD_PCG;
+  // factorisation path workspace (allocated on first use): S rows, rhs / y, D^-1, lambda
+  double *f_s = nullptr, *f_rhs = nullptr, *f_dinv = nullptr, *f_lam = nullptr;
   double *qinv_ws = nullptr, *rinv_ws = nullptr;
   void *tws = nullptr;
   Gang *gang = nullptr;
@@ -101,6 +107,14 @@ KernelFn kernel_for(int mode) {
     case mpc::kForward: return mpc::pcg_kernel<kNX, kNU, KPW, mpc::kForward>;
     default: return mpc::pcg_kernel<kNX, kNU, KPW, mpc::kAdjoint>;
   }
+}
+
+// formation-only (phase 1) and epilogue-only (phase 2) kernels of the factorisation path,
+// built for 16 knots per workgroup
+KernelFn phase_kernel(int mode, int phase) {
+  if (mode == mpc::kForward)
+    return phase == 1 ? mpc::pcg_kernel<kNX, kNU, 16, mpc::kForward, 1> : mpc::pcg_kernel<kNX, kNU, 16, mpc::kForward, 2>;
+  return phase == 1 ? mpc::pcg_kernel<kNX, kNU, 16, mpc::kAdjoint, 1> : mpc::pcg_kernel<kNX, kNU, 16, mpc::kAdjoint, 2>;
 }
 
 KernelFn kernel_for(int kpw, int mode) {
@@ -217,7 +231,7 @@ int get_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, int kpw, Schedu
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
     return off[x + 1] - off[x] > off[y + 1] - off[y];
   });
-  std::vector<ProbDesc> probs(B);
+  std::vector<ProbDesc> probs(B), sorted;
   std::vector<Task> tasks;
   for (int b : order) {
     ProbDesc d;
@@ -227,6 +241,7 @@ int get_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, int kpw, Schedu
     d.t0 = (int32_t)tasks.size();
     d.id = b;
     probs[b] = d;
+    sorted.push_back(d);
     for (int j = 0; j < d.nparts; ++j) tasks.push_back(Task{b, j});
   }
   if ((int64_t)tasks.size() > c->max_tasks)
@@ -247,8 +262,10 @@ int get_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, int kpw, Schedu
   s->ntasks = (int)tasks.size();
   s->nprobs = B;
   HIPCHK(c, hipMalloc(&s->d_probs, sizeof(ProbDesc) * B));
+  HIPCHK(c, hipMalloc(&s->d_sorted, sizeof(ProbDesc) * B));
   HIPCHK(c, hipMalloc(&s->d_tasks, sizeof(Task) * tasks.size()));
   HIPCHK(c, hipMemcpy(s->d_probs, probs.data(), sizeof(ProbDesc) * B, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(s->d_sorted, sorted.data(), sizeof(ProbDesc) * B, hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(s->d_tasks, tasks.data(), sizeof(Task) * tasks.size(), hipMemcpyHostToDevice));
   for (int m = 0; m < 3; ++m) s->grid[m] = std::min(s->ntasks, cap);
   *out = s.get();
@@ -262,7 +279,92 @@ void free_schedule(Schedule *s) {
     if (s->graph[m]) (void)hipGraphDestroy(s->graph[m]);
   }
   if (s->d_probs) (void)hipFree(s->d_probs);
+  if (s->d_sorted) (void)hipFree(s->d_sorted);
   if (s->d_tasks) (void)hipFree(s->d_tasks);
+}
+
+int ensure_factor_ws(mpcpcg_ctx *c) {
+  if (c->f_s) return MPCPCG_OK;
+  const size_t K = (size_t)c->max_knots;
+  if (hipMalloc(&c->f_s, K * kNX * 3 * kNX * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->f_rhs, K * kNX * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->f_dinv, K * kNX * kNX * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->f_lam, K * kNX * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    for (double **q : {&c->f_s, &c->f_rhs, &c->f_dinv, &c->f_lam})
+      if (*q) { (void)hipFree(*q); *q = nullptr; }
+    return fail(c, MPCPCG_ENOMEM, "cannot allocate the factorisation workspace (%zu knots)", K);
+  }
+  return MPCPCG_OK;
+}
+
+// Whether a call takes the factorisation path: always for MPCPCG_METHOD_FACTOR; for
+// MPCPCG_METHOD_AUTO by a cost model measured on MI355X (N = 512, nx = 14):
+//   PCG: ~600 us per round of resident problems (768 workgroups of 16 knots, ~100
+//        iterations at ~6 us), rounds = ceil(knots / 12288);
+//   factorisation: ~4.1 us per knot of the longest horizon (the sequential sweep, all
+//        problems at once) plus ~260 us per round for its two parallel phases.
+bool use_factor(mpcpcg_ctx *c, const std::vector<int64_t> &off) {
+  if (c->wide || c->method == MPCPCG_METHOD_PCG) return false;
+  if (c->method == MPCPCG_METHOD_FACTOR) return true;
+  int64_t knots = off.back(), nmax = 0;
+  for (size_t b = 0; b + 1 < off.size(); ++b) nmax = std::max(nmax, off[b + 1] - off[b]);
+  const double rounds = std::ceil((double)knots / 12288.0);
+  const double t_pcg = rounds * 600.0;
+  const double t_fac = 4.1 * (double)nmax + 260.0 * rounds + 60.0;
+  return t_fac < t_pcg;
+}
+
+int launch_phase(mpcpcg_ctx *c, KArgs a, int mode, int phase, Schedule *s, int N, hipStream_t stream) {
+  constexpr int kpw = 16;
+  KernelFn fn = phase_kernel(mode, phase);
+  int nb = 0;
+  HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(fn), kpw * mpc::kGroup, 0));
+  const int cap = nb * c->cus;
+  int grid;
+  if (s) {
+    a.probs = s->d_probs; a.tasks = s->d_tasks; a.ntasks = s->ntasks; a.persistent = 1;
+    grid = std::min(s->ntasks, cap);
+    int need = 0;
+    for (int64_t b = 0; b + 1 < (int64_t)s->off.size(); ++b)
+      need = std::max<int>(need, (int)((s->off[b + 1] - s->off[b] + kpw - 1) / kpw));
+    if (need > cap) return fail(c, MPCPCG_EINVAL, "a horizon needs %d co-resident workgroups; the device holds %d", need, cap);
+  } else {
+    grid = (N + kpw - 1) / kpw;
+    if (grid > cap) return fail(c, MPCPCG_EINVAL, "horizon N=%d needs %d co-resident workgroups; the device holds %d", N, grid, cap);
+    a.single.k0 = 0; a.single.N = N; a.single.t0 = 0; a.single.nparts = grid; a.single.id = 0;
+    a.probs = nullptr; a.tasks = nullptr; a.ntasks = grid; a.persistent = 0;
+  }
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(kpw * mpc::kGroup), 0, stream, a);
+  HIPCHK(c, hipGetLastError());
+  return MPCPCG_OK;
+}
+
+// Factorisation path: formation to the workspace (phase 1), the block LDL^T sweep of every
+// problem, then the epilogue from the swept lambda (phase 2).  s == nullptr: one problem
+// of N knots.
+int run_factor(mpcpcg_ctx *c, KArgs a, int mode, Schedule *s, int N, hipStream_t stream) {
+  int st = ensure_factor_ws(c);
+  if (st) return st;
+  const int64_t knots = s ? s->off.back() : N;
+  if (!s && (N + 15) / 16 > c->max_tasks) return fail(c, MPCPCG_EINVAL, "N=%d exceeds the context's task workspace", N);
+  if (knots > c->max_knots) return fail(c, MPCPCG_EINVAL, "knots exceed the context limit");
+  a.s_ws = c->f_s; a.rhs_ws = c->f_rhs; a.lam_ws = c->f_lam;
+  if ((st = launch_phase(c, a, mode, 1, s, N, stream))) return st;
+  mpc::TriArgs t;
+  std::memset(&t, 0, sizeof t);
+  t.s_ws = c->f_s; t.rhs_ws = c->f_rhs; t.dinv_ws = c->f_dinv; t.lam_ws = c->f_lam;
+  t.stats = a.stats;
+  if (s) {
+    t.probs = s->d_sorted; t.nprobs = s->nprobs;
+  } else {
+    t.probs = nullptr; t.nprobs = 1;
+    t.single.k0 = 0; t.single.N = N; t.single.t0 = 0; t.single.nparts = 1; t.single.id = 0;
+  }
+  const int per = mpc::kTriThreads / mpc::kGroup;
+  hipLaunchKernelGGL(mpc::tri_sweep<kNX>, dim3((t.nprobs + per - 1) / per), dim3(mpc::kTriThreads), 0, stream, t);
+  HIPCHK(c, hipGetLastError());
+  return launch_phase(c, a, mode, 2, s, N, stream);
 }
 
 int launch_batched(mpcpcg_ctx *c, Schedule *s, KArgs &a, int mode, hipStream_t stream) {
@@ -430,6 +532,8 @@ int mpcpcg_destroy(mpcpcg_ctx *c) {
   if (!c) return MPCPCG_OK;
   (void)hipDeviceSynchronize();
   for (auto &kv : c->sched) free_schedule(kv.second.get());
+  for (double *q : {c->f_s, c->f_rhs, c->f_dinv, c->f_lam})
+    if (q) (void)hipFree(q);
   if (c->qinv_ws) (void)hipFree(c->qinv_ws);
   if (c->rinv_ws) (void)hipFree(c->rinv_ws);
   if (c->tws) (void)hipFree(c->tws);
@@ -487,6 +591,7 @@ int mpcpcg_solve(mpcpcg_ctx *c, const mpcpcg_problem *p, const mpcpcg_opts *o, f
   }
   KArgs a = base_args(c, p, o);
   a.lam = lambda; a.dx = dx; a.du = du; a.stats = stats;
+  if (use_factor(c, std::vector<int64_t>{0, p->N})) return run_factor(c, a, mpc::kForward, nullptr, p->N, s);
   return launch_single(c, a, p->N, single_kpw(c, p->N), mpc::kForward, s);
 }
 
@@ -505,10 +610,12 @@ int mpcpcg_solve_batched(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const
     w.lam = lambda; w.dx = dx; w.du = du; w.stats = stats;
     return wide_run(c, key, w, false, s);
   }
+  const bool fac = use_factor(c, key);
   Schedule *sc = nullptr;
-  if ((st = get_schedule(c, key, pick_kpw(c, key), &sc))) return st;
+  if ((st = get_schedule(c, key, fac ? 16 : pick_kpw(c, key), &sc))) return st;
   KArgs a = base_args(c, p, o);
   a.lam = lambda; a.dx = dx; a.du = du; a.stats = stats;
+  if (fac) return run_factor(c, a, mpc::kForward, sc, 0, s);
   return launch_batched(c, sc, a, mpc::kForward, s);
 }
 
@@ -537,14 +644,16 @@ int mpcpcg_backward(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const mpcp
     w.dgamma = dgamma; w.stats = stats;
     return wide_run(c, key, w, false, s);
   }
+  const bool fac = use_factor(c, key);
   Schedule *sc = nullptr;
-  if ((st = get_schedule(c, key, pick_kpw(c, key), &sc))) return st;
+  if ((st = get_schedule(c, key, fac ? 16 : pick_kpw(c, key), &sc))) return st;
   KArgs a = base_args(c, p, o);
   a.warm = 0;
   a.lam_in = lambda; a.dx_in = dx; a.du_in = du;
   a.gl = gl; a.gx = gx; a.gu = gu;
   a.dQ = dQ; a.dR = dR; a.dA = dA; a.dB = dB; a.dq = dq; a.dr = dr; a.dx0 = dx0; a.de = de;
   a.dgamma = dgamma; a.stats = stats;
+  if (fac) return run_factor(c, a, mpc::kAdjoint, sc, 0, s);
   return launch_batched(c, sc, a, mpc::kAdjoint, s);
 }
 
@@ -552,6 +661,16 @@ int mpcpcg_set_knots_per_group(mpcpcg_ctx *c, int32_t k) {
   if (!c) return MPCPCG_EINVAL;
   if (k != 0 && !valid_kpw(k)) return fail(c, MPCPCG_EINVAL, "knots per group must be 0, 4, 8, 16 or 32");
   c->kpw_override = k;
+  return MPCPCG_OK;
+}
+
+int mpcpcg_set_method(mpcpcg_ctx *c, int32_t method) {
+  if (!c) return MPCPCG_EINVAL;
+  if (method != MPCPCG_METHOD_PCG && method != MPCPCG_METHOD_FACTOR && method != MPCPCG_METHOD_AUTO)
+    return fail(c, MPCPCG_EINVAL, "method must be MPCPCG_METHOD_PCG, _FACTOR or _AUTO");
+  if (c->wide && method == MPCPCG_METHOD_FACTOR)
+    return fail(c, MPCPCG_EUNSUPPORTED, "the factorisation path is built for (nx, nu) = (14, 7)");
+  c->method = method;
   return MPCPCG_OK;
 }
 

@@ -120,6 +120,9 @@ struct KArgs {
   int *queue;            // [0] head, [1] workgroups finished, [2] launch generation
   double *qinv_ws;       // [knots][NX][NX]   Q_b^-1 rows
   double *rinv_ws;       // [controls][NU][NU + NX]  R^-1 rows and (R^-1 B^T) rows
+  // factorisation path: S rows [knots][NX][3 NX] and rhs [knots][NX] written by phase 1,
+  // lambda [knots][NX] read by phase 2
+  double *s_ws, *rhs_ws, *lam_ws;
   // options
   float eps;
   int32_t max_iter;
@@ -145,7 +148,10 @@ __device__ __forceinline__ double uni(double v) {
 // 256-VGPR budget; smaller shapes target three.
 template <int KPW>
 constexpr int waves_per_eu() { return KPW >= 32 ? 2 : 3; }
-template <int NX, int NU, int KPW, int MODE>
+// PHASE 0: formation, PCG and epilogue fused.  PHASE 1 (factorisation path): formation only,
+// S rows and the right-hand side written to s_ws / rhs_ws.  PHASE 2: formation, lambda
+// read from lam_ws (the block-tridiagonal solve), then the epilogue.
+template <int NX, int NU, int KPW, int MODE, int PHASE = 0>
 __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_eu(waves_per_eu<KPW>(), waves_per_eu<KPW>())))
     pcg_kernel(const KArgs a) {
   static_assert(NX == 14 && NU <= NX, "the fused row kernels are written for 14-row blocks");
@@ -235,9 +241,11 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       ex_d[1][s][l] = 0.0;
       ex_f[s][l] = 0.0f;
     }
-    for (int t = tid; t < 2 * NX * kGroup; t += NT) {
-      const int side = t / (NX * kGroup), rem = t % (NX * kGroup);
-      ex_m[side ? KPW + 1 : 0][rem / kGroup][rem % kGroup] = 0.0;
+    if constexpr (PHASE == 0) {
+      for (int t = tid; t < 2 * NX * kGroup; t += NT) {
+        const int side = t / (NX * kGroup), rem = t % (NX * kGroup);
+        ex_m[side ? KPW + 1 : 0][rem / kGroup][rem % kGroup] = 0.0;
+      }
     }
     int nsync = 0;   // gang barrier counter (identical sequence in every part)
     bool aborted = false;
@@ -481,6 +489,14 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
     double rhs;  // gamma_b (forward) or the adjoint right-hand side y_b
     const float *qv = (MODE == kAdjoint) ? a.gx : a.q;
     const float *rv = (MODE == kAdjoint) ? a.gu : a.r;
+    double Dd[NX];
+    if constexpr (PHASE == 2) {
+      // the epilogue needs only S_{b,b+1} (the rest of its inputs are in the workspace)
+      const double *srow = a.s_ws + (kb * NX + (rowv ? lane : 0)) * (3 * NX);
+#pragma unroll
+      for (int j = 0; j < NX; ++j) { Sm[j] = 0.0; Sd[j] = 0.0; Dd[j] = 0.0; Sp[j] = (act && rowv) ? srow[2 * NX + j] : 0.0; }
+      rhs = 0.0;
+    } else {
     {
       // (1) previous-knot terms: T = A_{b-1} Q_{b-1}^-1 -> S_{b,b-1} = -T,
       //     theta = T A_{b-1}^T + ..., zeta = -T q_{b-1} - ...
@@ -541,7 +557,6 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         for (int j = 0; j < NX; ++j) w[NU + j] = W[j];
       }
     }
-    double Dd[NX];
     {
       // (3) own knot: Q_b^-1 enters theta and gamma; (4) S_{b,b+1} = -Q_b^-1 A_b^T
       double Qi[NX], An[NX], Sx[NX];
@@ -598,6 +613,9 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
 #pragma unroll
       for (int j = 0; j < NX; ++j) Dd[j] = keepQ0 ? Dd[j] : Dt[j];
     }
+    }  // PHASE != 2 (formation)
+    float Pm[NX], Pd[NX], Pp[NX];
+    if constexpr (PHASE == 0) {
     // (6) exchange D^-1 rows with the neighbouring knots (the one cross-knot dependency of
     //     the formation: "only theta_k^-1 needs to be shared")
     if (rowv) {
@@ -614,7 +632,6 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
     }
     sync_form();
     // (7) Phi^-1_{b,b-1} = -D_b^-1 S_{b,b-1} D_{b-1}^-1, Phi^-1_{b,b+1} likewise
-    float Pm[NX], Pd[NX], Pp[NX];
     {
       double X[NX];
       mm_nn<NX, NX>(Dd, Sm, X);
@@ -638,10 +655,25 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
 #pragma unroll
       for (int j = 0; j < NX; ++j) Pd[j] = (float)Dd[j];
     }
+    }  // PHASE == 0
     if (!rowv) {
 #pragma unroll
       for (int j = 0; j < NX; ++j) { Sm[j] = 0.0; Sd[j] = 0.0; Sp[j] = 0.0; Pm[j] = 0.f; Pd[j] = 0.f; Pp[j] = 0.f; }
       rhs = 0.0;
+    }
+    if constexpr (PHASE == 1) {
+      if (act) {
+        double *srow = a.s_ws + (kb * NX + (rowv ? lane : 0)) * (3 * NX);
+        if (rowv) {
+#pragma unroll
+          for (int j = 0; j < NX; ++j) {
+            srow[j] = Sm[j];
+            srow[NX + j] = Sd[j];
+            srow[2 * NX + j] = Sp[j];
+          }
+          a.rhs_ws[kb * NX + lane] = rhs;
+        }
+      }
     }
 
     if constexpr (MODE == kForm) {
@@ -661,7 +693,13 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
           }
         if (a.gam_out) a.gam_out[kb * NX + lane] = (float)rhs;
       }
-    } else {
+    } else if constexpr (PHASE != 1) {
+      double lam = 0.0, eta_ref = 0.0, eta_new = 0.0;
+      int status = MPCPCG_NOT_CONVERGED, it = 0;
+      if constexpr (PHASE == 2) {
+        if (act && rowv) lam = a.lam_ws[kb * NX + lane];
+        status = MPCPCG_OK;
+      } else {
       // Phi^-1 rows move to LDS for the solve (the D^-1 exchange above used the same bytes)
       __syncthreads();
       if (rowv) {
@@ -696,7 +734,6 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       // one barrier per iteration; the cap keeps barrier tags far from 32-bit wrap-around
       const int max_iter = (int)min((int64_t)(a.max_iter > 0 ? a.max_iter : (int64_t)N * NX), (int64_t)1 << 29);
       const bool warm = (MODE == kForward) && a.warm;
-      double lam = 0.0;
       if (warm && act && rowv) lam = (double)a.lam[kb * NX + lane];
       // setup exchange: boundary Phi^-1 rows; gamma at depths 1 and 2 (cold) or gamma and
       // lambda_0 at depth 1 (warm); device-scope stores, completed before the stage flag
@@ -725,7 +762,6 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       // r and s of the knots two beyond each end live in d2, touched only by the edge slots
       if (slot == 0) { d2[0][0][lane] = ex_d[1][0][lane]; d2[0][1][lane] = 0.0; }
       if (slot == KPW - 1) { d2[1][0][lane] = ex_d[1][KPW + 1][lane]; d2[1][1][lane] = 0.0; }
-      double eta_ref = 0.0;
       if (warm) {
         // r = gamma - S lambda_0; eta_ref = gamma^T Phi^-1 gamma; then r's halos two deep
         const double lm = ex_d[1][slot][lane], lp = ex_d[1][slot + 2][lane];
@@ -754,9 +790,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       // neighbours' w), and recomputes u of the adjacent knot itself from a copy of that
       // knot's Phi^-1 row, so no second exchange is needed inside an iteration.
       double p = 0.0, sv = 0.0, sm = 0.0, sp = 0.0;
-      double gam_prev = 1.0, alpha_prev = 1.0, tau = 0.0, eta_new = 0.0;
-      int status = MPCPCG_NOT_CONVERGED;
-      int it = 0;
+      double gam_prev = 1.0, alpha_prev = 1.0, tau = 0.0;
       const bool edge_wave = multi && (wave == 0 || wave == NW - 1);
       for (it = 0;; ++it) {
         if (aborted) break;
@@ -831,6 +865,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         alpha_prev = alpha;
       }
       if (it > max_iter) it = max_iter;
+      }  // PHASE == 0 (PCG)
       if (aborted) status = MPCPCG_TIMEOUT;
       if (!rowv || !act) lam = 0.0;
 
@@ -932,7 +967,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
           a.dr[(cb - 1) * NU + lane] = (float)n1u;
         }
       }
-      if (tid == 0 && part == 0) {
+      if (PHASE == 0 && tid == 0 && part == 0) {
         mpcpcg_stats st;
         st.iters = it;
         st.status = status;

@@ -15,6 +15,7 @@ import torch
 
 OK, NOT_CONVERGED, BREAKDOWN, TIMEOUT = 0, 1, 2, 3
 STOP_RULES = {"relative": 0, "absolute": 1}   # MPCPCG_STOP_RELATIVE / MPCPCG_STOP_ABSOLUTE
+METHODS = {"pcg": 0, "factor": 1, "auto": 2}   # MPCPCG_METHOD_PCG / _FACTOR / _AUTO
 EINVAL, EUNSUPPORTED, ENOMEM, EHIP = -1, -2, -3, -4
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmpcpcg.so")
@@ -63,11 +64,12 @@ def load_library(path: str = _LIB_PATH):
     lib.mpcpcg_solve_batched.argtypes = [vp, i32, i64p, P, O, vp, vp, vp, vp, vp]
     lib.mpcpcg_backward.argtypes = [vp, i32, i64p, P, O] + [vp] * 6 + [vp] * 9 + [vp, vp]
     lib.mpcpcg_set_knots_per_group.argtypes = [vp, i32]
+    lib.mpcpcg_set_method.argtypes = [vp, i32]
     lib.mpcpcg_set_graph.argtypes = [vp, i32]
     lib.mpcpcg_autotune.argtypes = [vp, i32, i64p, P, O, vp, vp, vp, vp, vp, C.POINTER(i32)]
     for f in ("mpcpcg_create", "mpcpcg_destroy", "mpcpcg_form_schur", "mpcpcg_solve",
               "mpcpcg_solve_batched", "mpcpcg_backward", "mpcpcg_set_knots_per_group",
-              "mpcpcg_set_graph", "mpcpcg_autotune"):
+              "mpcpcg_set_graph", "mpcpcg_autotune", "mpcpcg_set_method"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -213,6 +215,12 @@ class Context:
 
     def mpcpcg_set_knots_per_group(self, k):
         self._check(self.lib.mpcpcg_set_knots_per_group(self.h, int(k)), "mpcpcg_set_knots_per_group")
+
+    def mpcpcg_set_method(self, method):
+        """'pcg' (default), 'factor' (block LDL^T of S) or 'auto' (cost model per call)."""
+        if method not in METHODS:
+            raise MPCPCGError("method must be one of %s, not %r" % (sorted(METHODS), method))
+        self._check(self.lib.mpcpcg_set_method(self.h, METHODS[method]), "mpcpcg_set_method")
 
     def mpcpcg_set_graph(self, enable):
         self._check(self.lib.mpcpcg_set_graph(self.h, int(bool(enable))), "mpcpcg_set_graph")

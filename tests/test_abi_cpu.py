@@ -79,3 +79,23 @@ def test_mixed_horizon_draw():
     Ns = synth.horizons_uniform_choice(256, seed=3000)
     assert len(Ns) == 256 and set(Ns) <= {32, 64, 128, 256, 512}
     assert 40_000 < sum(Ns) < 60_000
+
+
+def test_receding_horizon_sequence_generator():
+    from paper_2309_08079_amd import synth
+    import numpy as np
+    T, N = 6, 9
+    steps = synth.sequence(T, N, seed=11)
+    base = synth.problem(N + T - 1, seed=11)
+    assert len(steps) == T
+    for t, p in enumerate(steps):
+        assert p["Q"].shape == (N, 14, 14) and p["A"].shape == (N - 1, 14, 14) and p["x0"].shape == (14,)
+        # step t is the window t .. t+N-1 of one trajectory
+        assert np.array_equal(p["Q"], base["Q"][t:t + N]) and np.array_equal(p["B"], base["B"][t:t + N - 1])
+    assert np.array_equal(steps[0]["x0"], base["x0"])
+    # x0 follows x_{t+1} = A_t x_t + 0.05 w_t with w from seed + 1 (independent of any solver)
+    g = np.random.default_rng(12)
+    x = base["x0"].astype(np.float64)
+    for t in range(T - 1):
+        x = base["A"][t].astype(np.float64) @ x + 0.05 * g.standard_normal(14)
+        assert np.array_equal(steps[t + 1]["x0"], x.astype(np.float32))

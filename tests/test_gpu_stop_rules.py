@@ -175,3 +175,32 @@ def test_invalid_stop_rule_rejected_by_library(ctx):
     assert b"stop_rule" in ctx.lib.mpcpcg_last_error(ctx.h)
     with pytest.raises(M.MPCPCGError):
         ctx.mpcpcg_solve(p, stop="sometimes")
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-5])
+def test_warm_started_sequence(ctx, eps):
+    # receding-horizon steps of N = 64: every step starts from the oracle's multipliers of
+    # the previous step shifted by one knot (the same start on both sides, so no input of
+    # the oracle comes from the GPU), absolute rule as in the paper's eps sweep
+    steps = synth.sequence(5, 64, seed=7500)
+    prev = None
+    for t, p in enumerate(steps):
+        lam0 = None
+        if prev is not None:
+            lam0 = np.concatenate([prev[1:], prev[-1:]]).astype(np.float32).astype(np.float64)
+        out = ctx.mpcpcg_solve(dev(p), eps=eps, stop="absolute",
+                               lam0=None if lam0 is None else torch.from_numpy(lam0.astype(np.float32)).cuda())
+        torch.cuda.synchronize()
+        st = stats(out["stats"])[0]
+        it = int(st["iters"])
+        ref = orc.solve(p, eps=eps, stop="absolute", lam0=lam0, phi="fp32")
+        assert st["status"] == orc.OK and abs(it - ref["iters"]) <= 1, (t, it, ref["iters"])
+        same = orc.solve(p, eps=0.0, stop="absolute", max_iter=max(it, 1), lam0=lam0, phi="fp32") if it else ref
+        other = orc.solve(p, eps=0.0, stop="absolute", max_iter=max(it, 1), lam0=lam0, phi="fp64") if it else ref
+        tol = max(1e-5, 10.0 * max(rel(same[k], other[k]) for k in ("lam", "dx")))
+        assert rel(out["lam"].cpu().numpy(), same["lam"]) < tol, t
+        assert rel(out["dx"].cpu().numpy(), same["dx"]) < tol, t
+        if t > 0:
+            cold = orc.solve(p, eps=eps, stop="absolute", phi="fp32")
+            assert ref["iters"] <= cold["iters"], (t, ref["iters"], cold["iters"])
+        prev = ref["lam"]
