@@ -91,7 +91,7 @@ def ingest_counters(prof_dir):
     for name, key, factor in (("fetch", "fetch", fetch_factor), ("write", "write", write_factor)):
         acc = {}
         for r in rows(name):
-            m = re.match(r"void mpc::pcg_kernel<14, 7, (\d+), (\d)>", r["Kernel_Name"])
+            m = re.match(r"void mpc::pcg_kernel<14, 7, (\d+), (\d), 0>", r["Kernel_Name"])
             if not m or m.group(2) not in MODE_OF_TEMPLATE:
                 continue
             acc.setdefault((MODE_OF_TEMPLATE[m.group(2)], m.group(1)), []).append(float(r["Counter_Value"]))

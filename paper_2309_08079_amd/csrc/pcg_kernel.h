@@ -604,7 +604,8 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
     }
     // (5) D_b^-1 = theta_{b-1}^-1 for b >= 1; D_0^-1 = Q_0 exactly (Dd holds the Q_b row).
     //     Knot slots past the horizon have S_bb = I, so their D^-1 = I stays finite.
-    {
+    //     Only the preconditioner needs it (not the factorisation path).
+    if constexpr (PHASE == 0) {
       double Dt[NX];
 #pragma unroll
       for (int j = 0; j < NX; ++j) Dt[j] = Sd[j];
