@@ -35,22 +35,37 @@ FLOP_PER_KNOT_GRAD = 1960      # dQ, dA (two outer products each), dB, dR
 PEAK_VALU_TFLOPS = 78.6        # FP64 vector FMA issue rate of MI355X (= non-packed FP32)
 
 
+def kernel_sources():
+    """Every file the GPU library is built from (the HIP sources and the C header), relative
+    to the repository root: the counters recorded for one set of sources stay valid only
+    as long as none of them changes."""
+    import glob
+
+    root = os.path.dirname(os.path.abspath(__file__))
+    srcs = sorted(glob.glob(os.path.join(root, "paper_2309_08079_amd", "csrc", "*")))
+    return [os.path.relpath(p, root) for p in srcs] + ["include/mpcpcg.h"]
+
+
+def sources_sha256(names):
+    import hashlib
+
+    root = os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for src in names:
+        h.update(open(os.path.join(root, src), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(mode, kpw):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE passes (calibrated on a plain copy), or None once the kernel sources differ
     from those the counters were taken on."""
-    import glob
-    import hashlib
-
     root = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(root, "profiles", "pcg_kernel_traffic_256xN512.json")
     try:
         rec = json.load(open(path))
-        h = hashlib.sha256()
-        for src in rec["kernel_sources"]:
-            h.update(open(os.path.join(root, src), "rb").read())
-        srcs = sorted(glob.glob(os.path.join(root, "paper_2309_08079_amd", "csrc", "*")))
-        if h.hexdigest() != rec["kernel_sources_sha256"] or len(srcs) + 1 != len(rec["kernel_sources"]) \
+        names = kernel_sources()
+        if rec["kernel_sources"] != names or rec["kernel_sources_sha256"] != sources_sha256(names) \
                 or rec["per_launch"][mode]["knots_per_group"] != kpw:
             return None
         pl = rec["per_launch"][mode]
@@ -59,9 +74,6 @@ def measured_traffic(mode, kpw):
         return None
 
 
-KERNEL_SOURCES = ["paper_2309_08079_amd/csrc/dpp_asm.h", "paper_2309_08079_amd/csrc/lane_ops.h",
-                  "paper_2309_08079_amd/csrc/mpcpcg.hip", "paper_2309_08079_amd/csrc/pcg_kernel.h",
-                  "paper_2309_08079_amd/csrc/wide_kernels.h", "include/mpcpcg.h"]
 MODE_OF_TEMPLATE = {"1": "forward", "2": "adjoint"}
 
 
@@ -70,7 +82,6 @@ def ingest_counters(prof_dir):
     same two of the --copy-probe run) into the per-launch HBM bytes measured_traffic() reads.
     Host only: parses <prof_dir>/{fetch,write,cfetch,cwrite}/<name>_counter_collection.csv."""
     import csv
-    import hashlib
 
     root = os.path.dirname(os.path.abspath(__file__))
 
@@ -100,12 +111,10 @@ def ingest_counters(prof_dir):
             d[key + "_kib_raw"] = float(np.mean(v))
             d["dispatches"] = len(v)
             d[key + "_bytes"] = float(np.mean(v)) * 1024.0 * factor
-    h = hashlib.sha256()
-    for src in KERNEL_SOURCES:
-        h.update(open(os.path.join(root, src), "rb").read())
+    names = kernel_sources()
     rec = {"workload": "batched %d x N=%d, nx=%d, nu=%d, eps=%g, seeds %d+b (bench.py --step-only)"
                        % (BATCH, N_KNOTS, NX, NU, EPS, SEED0),
-           "kernel_sources_sha256": h.hexdigest(), "kernel_sources": KERNEL_SOURCES,
+           "kernel_sources_sha256": sources_sha256(names), "kernel_sources": names,
            "calibration": {"copy_bytes": copy_bytes, "fetch_counter_kib": copy_kib("cfetch"),
                            "write_counter_kib": copy_kib("cwrite"), "fetch_factor": fetch_factor,
                            "write_factor": write_factor},
