@@ -180,7 +180,10 @@ __device__ __forceinline__ void gj_inverse(double (&a)[L], int lane, bool *posit
     constexpr int k = decltype(kk)::value;
     const double piv = bc<k>(a[k]);
     if (positive) *positive = *positive && (piv > 0.0);
-    const double d = 1.0 / piv;
+    // reciprocal of the pivot: hardware estimate + one Newton step (full FP64 accuracy
+    // without the division's scaling and fix-up sequence)
+    double d = __builtin_amdgcn_rcp(piv);
+    d = __builtin_fma(d, __builtin_fma(-piv, d, 1.0), d);
     const bool me = (lane == k);
     const double f = a[k] * d;
     const double sc = me ? 0.0 : 1.0;
