@@ -310,10 +310,16 @@ def two_arm_batch(dev, stream, reps=3):
         bo = ctx.mpcpcg_backward(d, off, fo, gl, eps=EPS)
         bms = _time_ms(lambda: ctx.mpcpcg_backward(d, off, fo, gl, eps=EPS, out=bo), stream, reps)
         fst, bst = stats_to_numpy(fo["stats"]), stats_to_numpy(bo["stats"])
-        return {"problems": 32, "knots": K, "nx": 28, "nu": 14, "forward_ms": round(fms, 3),
-                "adjoint_ms": round(bms, 3), "solves_per_s_fwd_adj": 32 / ((fms + bms) * 1e-3),
+        ok = bool((fst["status"] == 0).all() and (bst["status"] == 0).all())
+        ctx.mpcpcg_set_method("factor")
+        ffms = _time_ms(lambda: ctx.mpcpcg_solve_batched(d, off, eps=EPS, out=fo), stream, reps)
+        fbms = _time_ms(lambda: ctx.mpcpcg_backward(d, off, fo, gl, eps=EPS, out=bo), stream, reps)
+        ok = ok and bool((stats_to_numpy(fo["stats"])["status"] == 0).all())
+        return {"problems": 32, "knots": K, "nx": 28, "nu": 14, "pcg_forward_ms": round(fms, 3),
+                "pcg_adjoint_ms": round(bms, 3), "pcg_solves_per_s_fwd_adj": 32 / ((fms + bms) * 1e-3),
                 "iters_forward_mean": float(fst["iters"].mean()), "iters_adjoint_mean": float(bst["iters"].mean()),
-                "all_ok": bool((fst["status"] == 0).all() and (bst["status"] == 0).all())}
+                "factor_forward_ms": round(ffms, 3), "factor_adjoint_ms": round(fbms, 3),
+                "factor_solves_per_s_fwd_adj": 32 / ((ffms + fbms) * 1e-3), "all_ok": ok}
     finally:
         ctx.close()
 

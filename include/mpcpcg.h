@@ -176,12 +176,13 @@ int mpcpcg_set_graph(mpcpcg_ctx *ctx, int32_t enable);
  *     iterative solve that the paper names as future work (Section VI).  FP64 throughout,
  *     exact up to rounding; eps, max_iter, warm_start and stop_rule are ignored;
  *     stats report iters = 0, status OK or BREAKDOWN (non-finite result), final_ratio = 0.
- *     Each problem is swept sequentially by one 16-lane group, so a call costs ~N steps
- *     whatever the batch: it wins when many problems are solved at once.  Needs
- *     ~6.5 KB of extra device workspace per knot of max_total_knots, allocated on first use.
- *     (nx, nu) = (14, 7) only; MPCPCG_EUNSUPPORTED otherwise.
- *   MPCPCG_METHOD_AUTO: per call, the factorisation when the batch would need several
- *     rounds of resident PCG workgroups (by a cost model of both), else PCG. */
+ *     Each problem is swept sequentially (one 16-lane group at (14, 7), one workgroup at
+ *     (28, 14)), so a call costs ~N steps whatever the batch: at (14, 7) it wins when many
+ *     problems are solved at once.  At (14, 7) it needs ~6.5 KB of extra device workspace
+ *     per knot of max_total_knots, allocated on first use.
+ *   MPCPCG_METHOD_AUTO: per call, at (14, 7) the factorisation when the batch would need
+ *     several rounds of resident PCG workgroups (by a cost model of both), else PCG; at
+ *     (28, 14) always the factorisation, which is faster there at every measured size. */
 enum { MPCPCG_METHOD_PCG = 0, MPCPCG_METHOD_FACTOR = 1, MPCPCG_METHOD_AUTO = 2 };
 int mpcpcg_set_method(mpcpcg_ctx *ctx, int32_t method);
 

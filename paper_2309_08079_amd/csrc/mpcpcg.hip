@@ -74,6 +74,7 @@ struct mpcpcg_ctx {
   // generic path (nx = 28)
   bool wide = false;
   double *w_S = nullptr, *w_Dinv = nullptr, *w_rhs = nullptr, *w_Qinv = nullptr, *w_RW = nullptr;
+  double *w_lam = nullptr;  // lambda of the factorisation path
   float *w_P = nullptr;
   std::map<std::vector<int64_t>, std::unique_ptr<WideSchedule>> wsched;
   std::string err;
@@ -305,8 +306,9 @@ int ensure_factor_ws(mpcpcg_ctx *c) {
 //   factorisation: ~4.1 us per knot of the longest horizon (the sequential sweep, all
 //        problems at once) plus ~260 us per round for its two parallel phases.
 bool use_factor(mpcpcg_ctx *c, const std::vector<int64_t> &off) {
-  if (c->wide || c->method == MPCPCG_METHOD_PCG) return false;
+  if (c->method == MPCPCG_METHOD_PCG) return false;
   if (c->method == MPCPCG_METHOD_FACTOR) return true;
+  if (c->wide) return true;  // the 28-state PCG runs one workgroup per problem: always slower
   int64_t knots = off.back(), nmax = 0;
   for (size_t b = 0; b + 1 < off.size(); ++b) nmax = std::max(nmax, off[b + 1] - off[b]);
   const double rounds = std::ceil((double)knots / 12288.0);
@@ -445,6 +447,7 @@ mpc::wide::WArgs wide_args(mpcpcg_ctx *c, const mpcpcg_problem *p, const mpcpcg_
   a.Q = p->Q; a.R = p->R; a.A = p->A; a.B = p->B;
   a.q = p->q; a.r = p->r; a.x0 = p->x0; a.e = p->e;
   a.S = c->w_S; a.Dinv = c->w_Dinv; a.P = c->w_P; a.rhs = c->w_rhs; a.Qinv = c->w_Qinv; a.RW = c->w_RW;
+  a.lamw = c->w_lam;
   if (o) { a.eps = o->eps; a.max_iter = o->max_iter; a.warm = o->warm_start; a.stop_abs = o->stop_rule; }
   return a;
 }
@@ -461,10 +464,24 @@ int wide_run(mpcpcg_ctx *c, const std::vector<int64_t> &off, mpc::wide::WArgs &a
   a.nprobs = w->nprobs;
   hipLaunchKernelGGL((mpc::wide::wide_form<kWNX, kWNU>), dim3(w->nknots), dim3(256), 0, s, a);
   HIPCHK(c, hipGetLastError());
-  hipLaunchKernelGGL((mpc::wide::wide_precond<kWNX, kWNU>), dim3(w->nknots), dim3(256), 0, s, a);
-  HIPCHK(c, hipGetLastError());
+  const bool fac = !form_only && use_factor(c, off);
+  if (!fac) {
+    hipLaunchKernelGGL((mpc::wide::wide_precond<kWNX, kWNU>), dim3(w->nknots), dim3(256), 0, s, a);
+    HIPCHK(c, hipGetLastError());
+  }
   if (form_only) return MPCPCG_OK;
   const size_t lds = wide_lds_bytes(w->maxN, c->nx, c->nu);
+  HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void *>(mpc::wide::wide_pcg<kWNX, kWNU>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  if (fac) {
+    // factorisation path: block LDL^T sweep per problem, then wide_pcg's epilogue only
+    hipLaunchKernelGGL((mpc::wide::wide_sweep<kWNX>), dim3(w->nprobs), dim3(256), 0, s, a);
+    HIPCHK(c, hipGetLastError());
+    a.from_ws = 1;
+    hipLaunchKernelGGL((mpc::wide::wide_pcg<kWNX, kWNU>), dim3(w->nprobs), dim3(mpc::wide::kWideThreads), lds, s, a);
+    HIPCHK(c, hipGetLastError());
+    return MPCPCG_OK;
+  }
   HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void *>(mpc::wide::wide_pcg<kWNX, kWNU>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL((mpc::wide::wide_pcg<kWNX, kWNU>), dim3(w->nprobs), dim3(mpc::wide::kWideThreads),
@@ -501,6 +518,7 @@ int mpcpcg_create(mpcpcg_ctx **out, int32_t nx, int32_t nu, int64_t max_total_kn
         hipMalloc(&c->w_Dinv, sizeof(double) * K * MM) != hipSuccess ||
         hipMalloc(&c->w_P, sizeof(float) * K * 3 * MM) != hipSuccess ||
         hipMalloc(&c->w_rhs, sizeof(double) * K * nx) != hipSuccess ||
+        hipMalloc(&c->w_lam, sizeof(double) * K * nx) != hipSuccess ||
         hipMalloc(&c->w_Qinv, sizeof(double) * K * MM) != hipSuccess ||
         hipMalloc(&c->w_RW, sizeof(double) * K * nu * (nu + nx)) != hipSuccess) {
       mpcpcg_destroy(c.release());
@@ -543,7 +561,7 @@ int mpcpcg_destroy(mpcpcg_ctx *c) {
     if (kv.second->d_knots) (void)hipFree(kv.second->d_knots);
     if (kv.second->d_probs) (void)hipFree(kv.second->d_probs);
   }
-  for (void *p : {(void *)c->w_S, (void *)c->w_Dinv, (void *)c->w_P, (void *)c->w_rhs, (void *)c->w_Qinv,
+  for (void *p : {(void *)c->w_S, (void *)c->w_Dinv, (void *)c->w_P, (void *)c->w_rhs, (void *)c->w_lam, (void *)c->w_Qinv,
                   (void *)c->w_RW})
     if (p) (void)hipFree(p);
   delete c;
@@ -668,8 +686,6 @@ int mpcpcg_set_method(mpcpcg_ctx *c, int32_t method) {
   if (!c) return MPCPCG_EINVAL;
   if (method != MPCPCG_METHOD_PCG && method != MPCPCG_METHOD_FACTOR && method != MPCPCG_METHOD_AUTO)
     return fail(c, MPCPCG_EINVAL, "method must be MPCPCG_METHOD_PCG, _FACTOR or _AUTO");
-  if (c->wide && method == MPCPCG_METHOD_FACTOR)
-    return fail(c, MPCPCG_EUNSUPPORTED, "the factorisation path is built for (nx, nu) = (14, 7)");
   c->method = method;
   return MPCPCG_OK;
 }

@@ -59,14 +59,17 @@ struct WArgs {
   int32_t warm;
   int32_t adjoint;
   int32_t stop_abs;   // 1: eta < eps; 0: sqrt(eta / eta_ref) < eps
-  int32_t pad;
+  int32_t from_ws;    // 1: wide_pcg skips PCG and takes lambda from lamw (factorisation path)
+  double *lamw;       // [K][NX] lambda of the factorisation path
 };
 
 // ---------------------------------------------------------------- LDS dense helpers
 // In-place Gauss-Jordan inverse of an n x n SPD matrix in LDS (row stride ld); SPD needs
 // no pivoting.  All threads of the block participate.
+// `nonpositive` (optional, shared): set to 1 when a pivot is not > 0, i.e. the matrix is not
+// positive definite.
 template <int NT>
-__device__ void lds_gj_inverse(double *a, int n, int ld) {
+__device__ void lds_gj_inverse(double *a, int n, int ld, int *nonpositive = nullptr) {
   __shared__ double piv_row[64];
   __shared__ double col[64];
   for (int k = 0; k < n; ++k) {
@@ -76,6 +79,7 @@ __device__ void lds_gj_inverse(double *a, int n, int ld) {
       col[t] = a[t * ld + k];
     }
     __syncthreads();
+    if (nonpositive && threadIdx.x == 0 && !(piv_row[k] > 0.0)) *nonpositive = 1;
     const double d = 1.0 / piv_row[k];
     for (int t = threadIdx.x; t < n * n; t += NT) {
       const int i = t / n, j = t % n;
@@ -255,6 +259,93 @@ __global__ void __launch_bounds__(256) wide_precond(const WArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- factorisation
+// Block LDL^T of the block-tridiagonal S of one problem per workgroup (the factorisation
+// path; the same recurrence as the 14-state sweep, with 28 x 28 blocks in LDS):
+//   D_0 = S_00, D_k = S_kk - S_{k,k-1} D_{k-1}^-1 S_{k-1,k}, y_k = rhs_k - S_{k,k-1} D_{k-1}^-1 y_{k-1},
+//   lambda_k = D_k^-1 (y_k - S_{k,k+1} lambda_{k+1}).
+// Reads the S blocks and rhs written by wide_form; overwrites Dinv with D_k^-1 and rhs with
+// y_k; writes lambda to lamw and the problem's stats (BREAKDOWN on a pivot <= 0 or a
+// non-finite lambda).
+template <int NX>
+__global__ void __launch_bounds__(256) wide_sweep(const WArgs a) {
+  constexpr int NT = 256;
+  constexpr int MM = NX * NX;
+  __shared__ double Sm[MM], D[MM], Sp[MM], Dp[MM], Spp[MM], L[MM], T[MM];
+  __shared__ double y[NX], yp[NX], lv[NX], tv[NX];
+  __shared__ int bad;
+  const ProbDescW pd = a.probs[blockIdx.x];
+  const int N = pd.N;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  for (int k = 0; k < N; ++k) {
+    const int64_t kb = pd.k0 + k;
+    __syncthreads();
+    for (int t = tid; t < MM; t += NT) {
+      Sm[t] = a.S[kb * 3 * MM + t];
+      D[t] = a.S[kb * 3 * MM + MM + t];
+      Sp[t] = a.S[kb * 3 * MM + 2 * MM + t];
+    }
+    for (int t = tid; t < NX; t += NT) y[t] = a.rhs[kb * NX + t];
+    __syncthreads();
+    if (k > 0) {
+      lds_gemm<NT>(L, Sm, false, NX, Dp, false, NX, NX, NX, NX, 1.0, false);   // S_{k,k-1} D_{k-1}^-1
+      lds_gemm<NT>(T, L, false, NX, Spp, false, NX, NX, NX, NX, 1.0, false);  // ... S_{k-1,k}
+      for (int t = tid; t < MM; t += NT) D[t] -= T[t];
+      for (int i = tid; i < NX; i += NT) {
+        double s = y[i];
+        for (int m = 0; m < NX; ++m) s = __builtin_fma(-L[i * NX + m], yp[m], s);
+        tv[i] = s;
+      }
+      __syncthreads();
+      for (int i = tid; i < NX; i += NT) y[i] = tv[i];
+    }
+    lds_gj_inverse<NT>(D, NX, NX, &bad);  // D_k^-1
+    __syncthreads();
+    for (int t = tid; t < MM; t += NT) {
+      a.Dinv[kb * MM + t] = D[t];
+      Dp[t] = D[t];
+      Spp[t] = Sp[t];
+    }
+    for (int t = tid; t < NX; t += NT) {
+      a.rhs[kb * NX + t] = y[t];
+      yp[t] = y[t];
+    }
+  }
+  __syncthreads();
+  for (int t = tid; t < NX; t += NT) lv[t] = 0.0;
+  bool finite = true;
+  for (int k = N - 1; k >= 0; --k) {
+    const int64_t kb = pd.k0 + k;
+    __syncthreads();
+    for (int i = tid; i < NX; i += NT) {
+      double s = a.rhs[kb * NX + i];
+      const double *sp = a.S + kb * 3 * MM + 2 * MM + i * NX;
+      for (int j = 0; j < NX; ++j) s = __builtin_fma(-sp[j], lv[j], s);
+      tv[i] = s;
+    }
+    __syncthreads();
+    for (int i = tid; i < NX; i += NT) {
+      double s = 0.0;
+      const double *dr = a.Dinv + kb * MM + i * NX;
+      for (int j = 0; j < NX; ++j) s = __builtin_fma(dr[j], tv[j], s);
+      finite = finite && (s == s) && !__builtin_isinf(s);
+      a.lamw[kb * NX + i] = s;
+      lv[i] = s;
+    }
+  }
+  if (!finite) bad = 1;
+  __syncthreads();
+  if (tid == 0) {
+    mpcpcg_stats st;
+    st.iters = 0;
+    st.status = bad ? MPCPCG_BREAKDOWN : MPCPCG_OK;
+    st.final_ratio = 0.0f;
+    st.reserved = 0;
+    a.stats[pd.id] = st;
+  }
+}
+
 // ---------------------------------------------------------------- PCG per problem
 constexpr int kWideThreads = 1024;
 constexpr int kWideRows = 8;  // rows per thread: N * NX <= 8192
@@ -339,6 +430,15 @@ __global__ void __launch_bounds__(kWideThreads) wide_pcg(const WArgs a) {
     }
   };
 
+  int status = MPCPCG_OK, it = 0;
+  double eta_ref = 0.0, eta_new = 0.0;
+  if (a.from_ws) {
+#pragma unroll
+    for (int s = 0; s < kWideRows; ++s) {
+      const int g = tid + s * kWideThreads;
+      lam[s] = g < rows ? a.lamw[k0 * NX + g] : 0.0;
+    }
+  } else {
   // eta_ref = rhs^T Phi^-1 rhs; r = rhs - S lambda_0
   put_f(g0);
   put_d(lam);
@@ -367,11 +467,11 @@ __global__ void __launch_bounds__(kWideThreads) wide_pcg(const WArgs a) {
     p[s] = (double)rt[s];
   }
   double eta = block_sum(pr, red);
-  const double eta_ref = block_sum(pe, red);
+  eta_ref = block_sum(pe, red);
   const double tau = a.stop_abs ? (double)a.eps : (double)a.eps * (double)a.eps * eta_ref;
   const int max_iter = a.max_iter > 0 ? a.max_iter : N * NX;
-  int status = MPCPCG_NOT_CONVERGED, it = 0;
-  double eta_new = eta;
+  status = MPCPCG_NOT_CONVERGED;
+  eta_new = eta;
   if (!(eta == eta) || !(eta_ref == eta_ref) || __builtin_isinf(eta) || __builtin_isinf(eta_ref)) {
     status = MPCPCG_BREAKDOWN;
   } else if (eta <= tau) {
@@ -415,6 +515,7 @@ __global__ void __launch_bounds__(kWideThreads) wide_pcg(const WArgs a) {
     }
     if (it > max_iter) it = max_iter;
   }
+  }  // PCG (not the factorisation path)
 
   // ---------------------------------------------------------------- epilogue
   // x rows: dZx_b = -Q_b^-1 (q_b - lambda_b) + S_{b,b+1} lambda_{b+1};
@@ -520,7 +621,7 @@ __global__ void __launch_bounds__(kWideThreads) wide_pcg(const WArgs a) {
       a.dR[(c0 + c) * NU * NU + i * NU + j] = (float)(0.5 * (ni * dj + nj * di));
     }
   }
-  if (tid == 0) {
+  if (tid == 0 && !a.from_ws) {
     mpcpcg_stats st;
     st.iters = it;
     st.status = status;

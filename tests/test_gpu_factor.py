@@ -130,14 +130,72 @@ def test_auto_selects_by_batch_size():
         c.close()
 
 
-def test_method_argument_checks():
-    from paper_2309_08079_amd.mpcpcg import Context, MPCPCGError
-    c = Context(28, 14, max_total_knots=512, max_batch=4)
-    try:
-        with pytest.raises(MPCPCGError):
-            c.mpcpcg_set_method("factor")     # 28-state problems: PCG only
-        c.mpcpcg_set_method("auto")           # accepted, always PCG there
-        with pytest.raises(MPCPCGError):
-            c.mpcpcg_set_method("cholesky")
-    finally:
-        c.close()
+def test_method_argument_checks(ctx):
+    from paper_2309_08079_amd.mpcpcg import MPCPCGError
+    with pytest.raises(MPCPCGError):
+        ctx.mpcpcg_set_method("cholesky")
+    rc = ctx.lib.mpcpcg_set_method(ctx.h, 7)
+    assert rc == -1
+
+
+@pytest.fixture(scope="module")
+def ctx28():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_08079_amd.mpcpcg import Context
+    c = Context(28, 14, max_total_knots=8192, max_batch=40)
+    c.mpcpcg_set_method("factor")
+    yield c
+    c.close()
+
+
+def wide(N, seed):
+    return synth.problem(N, nx=28, nu=14, seed=seed, q_lo=1e-2, q_hi=1e2)
+
+
+@pytest.mark.parametrize("N", [1, 2, 5, 64, 256])
+def test_wide_factor_single_matches_kkt(ctx28, N):
+    # the 28-state shape; kappa(S) ~ 2e4 here, so 1e-6 still leaves ~50x margin over the
+    # FP64 rounding of the factorisation
+    p = wide(N, 9500 + N)
+    out = ctx28.mpcpcg_solve(dev(p))
+    torch.cuda.synchronize()
+    st = stats(out["stats"])[0]
+    assert st["status"] == 0 and st["iters"] == 0
+    ex = kkt.kkt_solve(p)
+    assert rel(out["lam"].cpu().numpy(), ex["lam"]) < 1e-6
+    assert rel(out["dx"].cpu().numpy(), ex["dx"]) < 1e-6
+    if N > 1:
+        assert rel(out["du"].cpu().numpy(), ex["du"]) < 1e-6
+
+
+def test_wide_factor_two_arm_batch_forward_and_adjoint(ctx28):
+    # the 32-problem two-arm workload: horizons uniform on [64, 256] (seed 5000, the first
+    # forced to 256), problem seeds 5001 + b
+    Ns = synth.horizons_uniform_int(32, 64, 256, seed=5000, first=256)
+    probs = synth.batch(Ns, nx=28, nu=14, seed0=5001, q_lo=1e-2, q_hi=1e2)
+    packed, off = synth.pack(probs)
+    d = dev(packed)
+    fwd = ctx28.mpcpcg_solve_batched(d, off)
+    gl = 2 * fwd["lam"]
+    g = ctx28.mpcpcg_backward(d, off, fwd, gl)
+    torch.cuda.synchronize()
+    lam = fwd["lam"].cpu().numpy()
+    gln = gl.cpu().numpy().astype(np.float64)
+    dQ, dA = g["dQ"].cpu().numpy(), g["dA"].cpu().numpy()
+    assert (stats(fwd["stats"])["status"] == 0).all() and (stats(g["stats"])["status"] == 0).all()
+    for b in (0, 7, 31):
+        k0, k1 = off[b], off[b + 1]
+        ex = kkt.kkt_solve(probs[b])
+        assert rel(lam[k0:k1], ex["lam"]) < 1e-6, b
+        ref = kkt.adjoint_dense(probs[b], gln[k0:k1])
+        assert rel(dQ[k0:k1], ref["dQ"]) < 1e-5, b
+        assert rel(dA[k0 - b:k1 - b - 1], ref["dA"]) < 1e-5, b
+
+
+def test_wide_factor_reports_breakdown(ctx28):
+    p = wide(16, 9600)
+    p["Q"][5] = -p["Q"][5]
+    out = ctx28.mpcpcg_solve(dev(p))
+    torch.cuda.synchronize()
+    assert stats(out["stats"])[0]["status"] == 2
