@@ -13,4 +13,6 @@ Modules
             Schur product C G^-1 C^T, the LQR Riccati recursion, a banded Cholesky solve
             of S, and the dense adjoint (O4).
   exact  -- exact rational PCG with ``fractions.Fraction`` for tiny problems (O3).
+  nmpc   -- numpy FP64 control step around the solve: linearisation of a pendulum-chain
+            model into the LQ problem, the L1 merit and the parallel line search.
 """

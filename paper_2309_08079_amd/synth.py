@@ -126,3 +126,84 @@ def unpack_knots(arr, off):
 def unpack_controls(arr, off):
     """Split a control-indexed packed array back into per-problem views."""
     return [arr[off[b] - b:off[b + 1] - b - 1] for b in range(len(off) - 1)]
+
+
+# ---- nonlinear control steps (the line search and the SQP iteration around the solve) ----
+#
+# The paper's controller linearises a rigid-body arm model at every step, solves the LQ
+# subproblem, and line-searches the nonlinear problem.  The arm model is not available, so
+# a chain of nq = nx / 2 pendulum joints coupled by nonlinear torsional springs stands in
+# for it (nq torques, one per joint).  Only the draws live here; the dynamics themselves
+# are written out separately by the library and by the oracle.
+#
+#   chain_model:  gravity ~ U[5, 15]^nq (seed), timestep h = 0.01, damping 0.5, coupling 2.
+#   trajectory (PCG64 with `seed`, float64 draws in this order):
+#     q_init ~ U[-1,1]^nq, v_init ~ 0.5 N(0,1)^nq          x_init = [q_init, v_init]
+#     q_goal ~ U[-1,1]^nq                                   xref_k = [q_goal, 0] for all k
+#     Xn ~ N(0,1)^(N,nx)    X_k = (1 - t_k) x_init + t_k xref_k + 0.3 Xn_k, t_k = k / (N-1)
+#     Un ~ N(0,1)^(N-1,nu)  U_k = 0.5 Un_k
+#     Qd ~ U[1,10]^(N,nx), W ~ N(0,1)^(N,nx,4)     Q_k = diag(Qd_k) + 0.1 W_k W_k^T
+#     Rd ~ U[1e-3,1e-2]^(N-1,nu)                   R_k = diag(Rd_k)
+#   so the initial guess violates the dynamics everywhere and the goal is away from x_init.
+
+
+def chain_model(nq: int = 7, seed: int = 10000, h: float = 0.01, damping: float = 0.5,
+                coupling: float = 2.0) -> dict:
+    """Parameters of the pendulum-chain dynamics (gravity gains drawn from `seed`).
+
+    The scalars are rounded to float32, the precision in which the library takes them, so
+    that every consumer starts from the same values."""
+    grav = np.random.default_rng(seed).uniform(5.0, 15.0, nq)
+    f32 = lambda v: float(np.float32(v))
+    return dict(h=f32(h), damping=f32(damping), coupling=f32(coupling),
+                gravity=np.ascontiguousarray(grav, dtype=np.float32))
+
+
+def trajectory(N: int, nx: int = 14, nu: int = 7, seed: int = 11000) -> dict:
+    """One control step's nonlinear problem data: the current guess (X, U), the measured
+    state x_init, the tracking target xref and the cost weights Q, R (all float32).
+
+    Shapes: X [N,nx], U [N-1,nu], x_init [nx], xref [N,nx], Q [N,nx,nx], R [N-1,nu,nu].
+    """
+    if N < 1:
+        raise ValueError("N must be >= 1")
+    if nx != 2 * nu:
+        raise ValueError("the chain model has nx = 2 nu (positions and velocities)")
+    g = np.random.default_rng(seed)
+    M = N - 1
+    x_init = np.concatenate([g.uniform(-1.0, 1.0, nu), 0.5 * g.standard_normal(nu)])
+    goal = np.concatenate([g.uniform(-1.0, 1.0, nu), np.zeros(nu)])
+    Xn = g.standard_normal((N, nx))
+    Un = g.standard_normal((M, nu))
+    Qd = g.uniform(1.0, 10.0, (N, nx))
+    W = g.standard_normal((N, nx, 4))
+    Rd = g.uniform(1e-3, 1e-2, (M, nu))
+    t = (np.arange(N) / max(N - 1, 1))[:, None]
+    xref = np.tile(goal, (N, 1))
+    X = (1.0 - t) * x_init + t * xref + 0.3 * Xn
+    U = 0.5 * Un
+    Q = np.zeros((N, nx, nx))
+    for k in range(N):
+        Q[k] = np.diag(Qd[k]) + 0.1 * (W[k] @ W[k].T)
+    R = np.zeros((M, nu, nu))
+    for k in range(M):
+        R[k] = np.diag(Rd[k])
+    out = dict(X=X, U=U, x_init=x_init, xref=xref, Q=Q, R=R)
+    return {k: np.ascontiguousarray(v, dtype=np.float32) for k, v in out.items()}
+
+
+def trajectories(Ns, nx: int = 14, nu: int = 7, seed0: int = 11000):
+    """Trajectories b = 0..len(Ns)-1 drawn with seed ``seed0 + b``."""
+    return [trajectory(int(n), nx, nu, seed0 + b) for b, n in enumerate(Ns)]
+
+
+def pack_trajectories(trajs):
+    """Packed layout of the batched control-step entry points (as `pack`): X, xref, Q
+    stacked over knots, U, R over controls, x_init [batch, nx]; returns (dict, knot_off)."""
+    off = np.zeros(len(trajs) + 1, dtype=np.int64)
+    for b, t in enumerate(trajs):
+        off[b + 1] = off[b] + t["X"].shape[0]
+    cat = lambda key: np.ascontiguousarray(np.concatenate([t[key] for t in trajs], axis=0))
+    packed = {k: cat(k) for k in ("X", "U", "xref", "Q", "R")}
+    packed["x_init"] = np.ascontiguousarray(np.stack([t["x_init"] for t in trajs]))
+    return packed, off
