@@ -186,6 +186,70 @@ int mpcpcg_set_graph(mpcpcg_ctx *ctx, int32_t enable);
 enum { MPCPCG_METHOD_PCG = 0, MPCPCG_METHOD_FACTOR = 1, MPCPCG_METHOD_AUTO = 2 };
 int mpcpcg_set_method(mpcpcg_ctx *ctx, int32_t method);
 
+/* ---- The control step around the solve ---------------------------------------------
+ * One iteration of the paper's controller linearises the nonlinear problem at the
+ * current guess (Section III-A, Step 1), solves the LQ problem (the calls above), and
+ * picks the step length by a parallel line search on the L1 merit (Section III-A, Step 3;
+ * Section IV-C).  The robot model of the paper is not part of this library; these calls
+ * evaluate a fixed model family that stands in for it:
+ *
+ * Pendulum chain: nq = nx / 2 joints (so nu = nq: one torque per joint), state
+ * x = [q; v], explicit Euler step with timestep h:
+ *   q+ = q + h v,  v+ = v + h acc,
+ *   acc_i = u_i - g_i sin(q_i) - d v_i + kappa (sin(q_{i+1} - q_i) - sin(q_i - q_{i-1})),
+ * where the spring terms past either end of the chain are absent.
+ * Tracking cost J = sum_k 1/2 (x_k - xref_k)^T Q_k (x_k - xref_k) + sum_k 1/2 u_k^T R_k u_k.
+ * Constraints c = [x_0 - x_s, x_1 - f(x_0, u_0), ..., x_{N-1} - f(x_{N-2}, u_{N-2})].
+ *
+ * Layouts follow the batched solve: knot-indexed arrays are packed over knots, control-
+ * indexed arrays over controls (problem b's rows start at knot_off[b] - b), per-problem
+ * arrays are [batch][...].  All arrays are device memory owned by the caller, FP32 unless
+ * stated; calls are asynchronous on `stream`; arithmetic is FP64 inside. */
+typedef struct {
+  float h;               /* Euler timestep */
+  float damping;         /* d */
+  float coupling;        /* kappa */
+  const float *gravity;  /* [nx/2] gains g_i, shared by the batch */
+} mpcpcg_chain_model;
+
+typedef struct {
+  int32_t nx, nu, N;     /* N = total knots (knot_off[batch]); must match the context */
+  const float *X;        /* [N][nx] state guess */
+  const float *U;        /* [N-batch][nu] control guess (NULL if every N_b = 1) */
+  const float *x_init;   /* [batch][nx] measured initial states x_s */
+  const float *xref;     /* [N][nx] tracking targets */
+  const float *Q;        /* [N][nx][nx] state weights (symmetric) */
+  const float *R;        /* [N-batch][nu][nu] control weights (symmetric; NULL if every N_b = 1) */
+} mpcpcg_trajectory;
+
+/* Step 1: the LQ problem of the solve at the guess (X, U).  The cost is quadratic, so its
+ * expansion is exact: the problem's Q, R are the trajectory's weights (pass the same
+ * pointers), q_k = Q_k (x_k - xref_k), r_k = R_k u_k; A_k = df/dx, B_k = df/du at
+ * (x_k, u_k); e_k = x_{k+1} - f(x_k, u_k); x0 = x_s - x_0 (the required dx_0).
+ * Outputs q [N][nx], x0 [batch][nx], and (NULL allowed only if every N_b = 1)
+ * A [N-batch][nx][nx], B [N-batch][nx][nu], r [N-batch][nu], e [N-batch][nx].
+ * Returns OK or EINVAL (argument errors; message in mpcpcg_last_error). */
+int mpcpcg_linearize(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
+                     const mpcpcg_chain_model *model, const mpcpcg_trajectory *traj, float *A,
+                     float *B, float *q, float *r, float *x0, float *e, hipStream_t stream);
+
+/* Step 3: evaluate the trial iterates (X + a dX, U + a dU) for a in {1, 1/2, ..., 1/256}
+ * in parallel, score each by the L1 merit phi(a) = J + mu_b ||c||_1, and write the iterate
+ * with the smallest merit (the largest a among equal merits) to X_out, U_out.
+ * Penalty: mu_b = mu + max |lambda_b| when lambda ([N][nx], the solve's multipliers) is
+ * given, else mu; mu must be finite and >= 0.
+ * Outputs: merit [batch][MPCPCG_LS_STEPS] (FP64, in the order of a), choice [batch]
+ * (index j of a = 2^-j), X_out [N][nx], U_out [N-batch][nu].  X_out may be X and U_out
+ * may be U (in-place update); no other output may overlap an input.
+ * Uses ~150 B of context workspace per 32 knots (allocated on first use).  Calls that
+ * overlap on one context race on that workspace. */
+#define MPCPCG_LS_STEPS 9
+int mpcpcg_line_search(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
+                       const mpcpcg_chain_model *model, const mpcpcg_trajectory *traj,
+                       const float *dX, const float *dU, const float *lambda, float mu,
+                       float *X_out, float *U_out, double *merit, int32_t *choice,
+                       hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

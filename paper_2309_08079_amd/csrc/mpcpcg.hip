@@ -15,6 +15,7 @@
 
 #include "mpcpcg.h"
 #include "pcg_kernel.h"
+#include "ctrl_kernels.h"
 #include "tri_kernel.h"
 #include "wide_kernels.h"
 
@@ -47,6 +48,12 @@ struct Schedule {
   int grid[3] = {0, 0, 0};
 };
 
+// chunks of the control-step kernels (linearisation, line search) for one horizon signature
+struct CtrlSchedule {
+  mpc::ctrl::Chunk *d_chunks = nullptr;
+  int nchunks = 0;
+};
+
 struct WideSchedule {
   mpc::wide::KnotDesc *d_knots = nullptr;
   mpc::wide::ProbDescW *d_probs = nullptr;
@@ -77,6 +84,9 @@ struct mpcpcg_ctx {
   double *w_lam = nullptr;  // lambda of the factorisation path
   float *w_P = nullptr;
   std::map<std::vector<int64_t>, std::unique_ptr<WideSchedule>> wsched;
+  // control step: chunk lists and the line search's per-chunk partial sums (on first use)
+  std::map<std::vector<int64_t>, std::unique_ptr<CtrlSchedule>> csched;
+  double *ls_part = nullptr;
   std::string err;
 };
 
@@ -482,12 +492,75 @@ int wide_run(mpcpcg_ctx *c, const std::vector<int64_t> &off, mpc::wide::WArgs &a
     HIPCHK(c, hipGetLastError());
     return MPCPCG_OK;
   }
-  HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void *>(mpc::wide::wide_pcg<kWNX, kWNU>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL((mpc::wide::wide_pcg<kWNX, kWNU>), dim3(w->nprobs), dim3(mpc::wide::kWideThreads),
                      lds, s, a);
   HIPCHK(c, hipGetLastError());
   return MPCPCG_OK;
+}
+
+// ---- control step (linearisation, line search) ----------------------------------------
+
+int64_t ctrl_max_chunks(const mpcpcg_ctx *c) { return c->max_knots / mpc::ctrl::kChunk + c->max_batch; }
+
+int ctrl_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, CtrlSchedule **out) {
+  auto it = c->csched.find(off);
+  if (it != c->csched.end()) { *out = it->second.get(); return MPCPCG_OK; }
+  const int B = (int)off.size() - 1;
+  std::vector<mpc::ctrl::Chunk> ch;
+  for (int b = 0; b < B; ++b) {
+    const int N = (int)(off[b + 1] - off[b]);
+    const int nch = (N + mpc::ctrl::kChunk - 1) / mpc::ctrl::kChunk;
+    const int c0 = (int)ch.size();
+    for (int k = 0; k < N; k += mpc::ctrl::kChunk) {
+      mpc::ctrl::Chunk x;
+      x.pk0 = off[b]; x.b = b; x.N = N; x.lk0 = k; x.lk1 = std::min(N, k + mpc::ctrl::kChunk);
+      x.c0 = c0; x.nch = nch;
+      ch.push_back(x);
+    }
+  }
+  if ((int64_t)ch.size() > ctrl_max_chunks(c)) return fail(c, MPCPCG_EINVAL, "batch exceeds the control-step workspace");
+  auto cs = std::make_unique<CtrlSchedule>();
+  cs->nchunks = (int)ch.size();
+  HIPCHK(c, hipMalloc(&cs->d_chunks, sizeof(mpc::ctrl::Chunk) * ch.size()));
+  HIPCHK(c, hipMemcpy(cs->d_chunks, ch.data(), sizeof(mpc::ctrl::Chunk) * ch.size(), hipMemcpyHostToDevice));
+  *out = cs.get();
+  c->csched.emplace(off, std::move(cs));
+  return MPCPCG_OK;
+}
+
+int check_ctrl(mpcpcg_ctx *c, int batch, const int64_t *off, const mpcpcg_chain_model *m,
+               const mpcpcg_trajectory *t, bool *ctrl) {
+  if (batch < 1) return fail(c, MPCPCG_EINVAL, "batch must be >= 1");
+  if (batch > c->max_batch) return fail(c, MPCPCG_EINVAL, "batch %d exceeds the context limit %d", batch, c->max_batch);
+  if (!off) return fail(c, MPCPCG_EINVAL, "knot_off is NULL");
+  if (off[0] != 0) return fail(c, MPCPCG_EINVAL, "knot_off[0] must be 0");
+  *ctrl = false;
+  for (int b = 0; b < batch; ++b) {
+    const int64_t n = off[b + 1] - off[b];
+    if (n < 1) return fail(c, MPCPCG_EINVAL, "problem %d has N=%lld < 1", b, (long long)n);
+    if (n > (int64_t)1 << 30) return fail(c, MPCPCG_EINVAL, "problem %d horizon too long", b);
+    if (n > 1) *ctrl = true;
+  }
+  if (off[batch] > c->max_knots)
+    return fail(c, MPCPCG_EINVAL, "total knots %lld exceed the context limit %lld", (long long)off[batch], (long long)c->max_knots);
+  if (!m || !t) return fail(c, MPCPCG_EINVAL, "model and trajectory must be non-NULL");
+  if (t->nx != c->nx || t->nu != c->nu)
+    return fail(c, MPCPCG_EINVAL, "trajectory (nx, nu) = (%d, %d) differs from the context (%d, %d)", t->nx, t->nu, c->nx, c->nu);
+  if (!m->gravity) return fail(c, MPCPCG_EINVAL, "model gravity must be non-NULL");
+  if (!std::isfinite(m->h) || !std::isfinite(m->damping) || !std::isfinite(m->coupling))
+    return fail(c, MPCPCG_EINVAL, "model parameters must be finite");
+  if (!t->X || !t->x_init || !t->xref || !t->Q) return fail(c, MPCPCG_EINVAL, "X, x_init, xref and Q must be non-NULL");
+  if (*ctrl && (!t->U || !t->R)) return fail(c, MPCPCG_EINVAL, "U and R must be non-NULL when a horizon exceeds one knot");
+  return MPCPCG_OK;
+}
+
+mpc::ctrl::CtrlArgs ctrl_args(const mpcpcg_chain_model *m, const mpcpcg_trajectory *t, const CtrlSchedule *cs) {
+  mpc::ctrl::CtrlArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.X = t->X; a.U = t->U; a.xs = t->x_init; a.xref = t->xref; a.Q = t->Q; a.R = t->R;
+  a.grav = m->gravity; a.h = m->h; a.damp = m->damping; a.kap = m->coupling;
+  a.chunks = cs->d_chunks; a.nchunks = cs->nchunks;
+  return a;
 }
 
 }  // namespace
@@ -557,6 +630,9 @@ int mpcpcg_destroy(mpcpcg_ctx *c) {
   if (c->tws) (void)hipFree(c->tws);
   if (c->gang) (void)hipFree(c->gang);
   if (c->queue) (void)hipFree(c->queue);
+  for (auto &kv : c->csched)
+    if (kv.second->d_chunks) (void)hipFree(kv.second->d_chunks);
+  if (c->ls_part) (void)hipFree(c->ls_part);
   for (auto &kv : c->wsched) {
     if (kv.second->d_knots) (void)hipFree(kv.second->d_knots);
     if (kv.second->d_probs) (void)hipFree(kv.second->d_probs);
@@ -738,6 +814,59 @@ int mpcpcg_autotune(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const mpcp
   if (!best) return fail(c, MPCPCG_EINVAL, "no workgroup shape can run this batch");
   c->tuned[key] = best;
   if (kpw_out) *kpw_out = best;
+  return MPCPCG_OK;
+}
+
+int mpcpcg_linearize(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const mpcpcg_chain_model *m,
+                     const mpcpcg_trajectory *t, float *A, float *B, float *q, float *r, float *x0,
+                     float *e, hipStream_t s) {
+  if (!c) return MPCPCG_EINVAL;
+  bool ctrl = false;
+  int st = check_ctrl(c, batch, off, m, t, &ctrl);
+  if (st) return st;
+  if (!q || !x0) return fail(c, MPCPCG_EINVAL, "q and x0 must be non-NULL");
+  if (ctrl && (!A || !B || !r || !e))
+    return fail(c, MPCPCG_EINVAL, "A, B, r and e must be non-NULL when a horizon exceeds one knot");
+  CtrlSchedule *cs = nullptr;
+  if ((st = ctrl_schedule(c, std::vector<int64_t>(off, off + batch + 1), &cs))) return st;
+  mpc::ctrl::CtrlArgs a = ctrl_args(m, t, cs);
+  a.A = A; a.B = B; a.q = q; a.r = r; a.x0 = x0; a.e = e;
+  if (c->wide)
+    hipLaunchKernelGGL(mpc::ctrl::linearize_kernel<kWNX>, dim3(cs->nchunks), dim3(mpc::ctrl::kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(mpc::ctrl::linearize_kernel<kNX>, dim3(cs->nchunks), dim3(mpc::ctrl::kThreads), 0, s, a);
+  HIPCHK(c, hipGetLastError());
+  return MPCPCG_OK;
+}
+
+int mpcpcg_line_search(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const mpcpcg_chain_model *m,
+                       const mpcpcg_trajectory *t, const float *dX, const float *dU, const float *lambda,
+                       float mu, float *X_out, float *U_out, double *merit, int32_t *choice, hipStream_t s) {
+  if (!c) return MPCPCG_EINVAL;
+  bool ctrl = false;
+  int st = check_ctrl(c, batch, off, m, t, &ctrl);
+  if (st) return st;
+  if (!(mu >= 0.0f) || !std::isfinite(mu)) return fail(c, MPCPCG_EINVAL, "mu must be finite and >= 0");
+  if (!dX || !X_out || !merit || !choice) return fail(c, MPCPCG_EINVAL, "dX, X_out, merit and choice must be non-NULL");
+  if (ctrl && (!dU || !U_out)) return fail(c, MPCPCG_EINVAL, "dU and U_out must be non-NULL when a horizon exceeds one knot");
+  CtrlSchedule *cs = nullptr;
+  if ((st = ctrl_schedule(c, std::vector<int64_t>(off, off + batch + 1), &cs))) return st;
+  if (!c->ls_part)
+    HIPCHK(c, hipMalloc(&c->ls_part, sizeof(double) * mpc::ctrl::kParts * (size_t)ctrl_max_chunks(c)));
+  mpc::ctrl::CtrlArgs a = ctrl_args(m, t, cs);
+  a.dX = dX; a.dU = dU; a.lam = lambda; a.mu = mu;
+  a.part = c->ls_part; a.X_out = X_out; a.U_out = U_out; a.merit = merit; a.choice = choice;
+  const dim3 g(cs->nchunks), blk(mpc::ctrl::kThreads);
+  if (c->wide) {
+    hipLaunchKernelGGL(mpc::ctrl::merit_kernel<kWNX>, g, blk, 0, s, a);
+    HIPCHK(c, hipGetLastError());
+    hipLaunchKernelGGL(mpc::ctrl::ls_update_kernel<kWNX>, g, blk, 0, s, a);
+  } else {
+    hipLaunchKernelGGL(mpc::ctrl::merit_kernel<kNX>, g, blk, 0, s, a);
+    HIPCHK(c, hipGetLastError());
+    hipLaunchKernelGGL(mpc::ctrl::ls_update_kernel<kNX>, g, blk, 0, s, a);
+  }
+  HIPCHK(c, hipGetLastError());
   return MPCPCG_OK;
 }
 

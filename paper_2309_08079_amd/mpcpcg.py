@@ -40,6 +40,18 @@ class Schur(C.Structure):
     _fields_ = [("S", C.c_void_p), ("Pinv", C.c_void_p), ("gamma", C.c_void_p)]
 
 
+class ChainModel(C.Structure):
+    _fields_ = [("h", C.c_float), ("damping", C.c_float), ("coupling", C.c_float),
+                ("gravity", C.c_void_p)]
+
+
+class Trajectory(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("nu", C.c_int32), ("N", C.c_int32)] + [
+        (k, C.c_void_p) for k in ("X", "U", "x_init", "xref", "Q", "R")]
+
+
+LS_STEPS = 9   # MPCPCG_LS_STEPS: alpha = 2^-j, j = 0..8
+
 STATS_DTYPE = np.dtype([("iters", np.int32), ("status", np.int32), ("final_ratio", np.float32),
                         ("reserved", np.int32)])
 
@@ -67,9 +79,13 @@ def load_library(path: str = _LIB_PATH):
     lib.mpcpcg_set_method.argtypes = [vp, i32]
     lib.mpcpcg_set_graph.argtypes = [vp, i32]
     lib.mpcpcg_autotune.argtypes = [vp, i32, i64p, P, O, vp, vp, vp, vp, vp, C.POINTER(i32)]
+    M, T = C.POINTER(ChainModel), C.POINTER(Trajectory)
+    lib.mpcpcg_linearize.argtypes = [vp, i32, i64p, M, T] + [vp] * 6 + [vp]
+    lib.mpcpcg_line_search.argtypes = [vp, i32, i64p, M, T, vp, vp, vp, C.c_float] + [vp] * 4 + [vp]
     for f in ("mpcpcg_create", "mpcpcg_destroy", "mpcpcg_form_schur", "mpcpcg_solve",
               "mpcpcg_solve_batched", "mpcpcg_backward", "mpcpcg_set_knots_per_group",
-              "mpcpcg_set_graph", "mpcpcg_autotune", "mpcpcg_set_method"):
+              "mpcpcg_set_graph", "mpcpcg_autotune", "mpcpcg_set_method", "mpcpcg_linearize",
+              "mpcpcg_line_search"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -96,6 +112,23 @@ def _problem(d, nx, nu, N=0):
     if p.Q is None or p.q is None or p.x0 is None:
         raise MPCPCGError("Q, q and x0 are required")
     return p
+
+
+def _model(m):
+    """mpcpcg_chain_model from a dict with h, damping, coupling (floats) and gravity (device)."""
+    cm = ChainModel()
+    cm.h, cm.damping, cm.coupling = float(m["h"]), float(m["damping"]), float(m["coupling"])
+    cm.gravity = _ptr(m["gravity"])
+    return cm
+
+
+def _trajectory(d, nx, nu):
+    t = Trajectory()
+    t.nx, t.nu, t.N = nx, nu, int(d["X"].shape[0])
+    for k in ("X", "U", "x_init", "xref", "Q", "R"):
+        v = d.get(k)
+        setattr(t, k, None if v is None or v.numel() == 0 else _ptr(v))
+    return t
 
 
 def _opts(eps, max_iter, warm, stop="relative"):
@@ -240,6 +273,48 @@ class Context:
             C.byref(_opts(eps, max_iter, False, stop)), _ptr(lam), _ptr(dx), _ptr(du), stats.data_ptr(),
             _stream(), C.byref(k)), "mpcpcg_autotune")
         return k.value
+
+
+    # ---- control step around the solve ----------------------------------------------------
+    def mpcpcg_linearize(self, model, traj, knot_off, out=None):
+        """LQ problem (dict Q, R, A, B, q, r, x0, e of device tensors) at the guess in traj."""
+        off = np.ascontiguousarray(knot_off, dtype=np.int64)
+        B = len(off) - 1
+        K = int(off[-1])
+        M = K - B
+        nx, nu = self.nx, self.nu
+        dev = traj["X"].device
+        o = out or {}
+        z = lambda key, shape: o[key] if key in o else torch.empty(shape, device=dev)
+        lq = dict(A=z("A", (M, nx, nx)), B=z("B", (M, nx, nu)), q=z("q", (K, nx)), r=z("r", (M, nu)),
+                  x0=z("x0", (B, nx)), e=z("e", (M, nx)))
+        opt = lambda t: _ptr(t) if t.numel() else None
+        self._check(self.lib.mpcpcg_linearize(
+            self.h, B, off.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(_model(model)),
+            C.byref(_trajectory(traj, nx, nu)), *[opt(lq[k]) for k in ("A", "B", "q", "r", "x0", "e")],
+            _stream()), "mpcpcg_linearize")
+        lq["Q"], lq["R"] = traj["Q"], traj["R"]
+        return lq
+
+    def mpcpcg_line_search(self, model, traj, knot_off, dX, dU, lam=None, mu=0.0, out=None):
+        """Best of the 9 trial steps by the L1 merit: dict X, U (updated), merit [B, 9] float64,
+        choice [B] int32.  ``out`` may name traj's own X / U for an in-place update."""
+        off = np.ascontiguousarray(knot_off, dtype=np.int64)
+        B = len(off) - 1
+        dev = traj["X"].device
+        o = out or {}
+        X = o["X"] if "X" in o else torch.empty_like(traj["X"])
+        U = o["U"] if "U" in o else torch.empty_like(traj["U"])
+        merit = o["merit"] if "merit" in o else torch.empty((B, LS_STEPS), dtype=torch.float64, device=dev)
+        choice = o["choice"] if "choice" in o else torch.empty((B,), dtype=torch.int32, device=dev)
+        if merit.dtype != torch.float64 or choice.dtype != torch.int32:
+            raise MPCPCGError("merit must be float64 and choice int32")
+        opt = lambda t: _ptr(t) if t is not None and t.numel() else None
+        self._check(self.lib.mpcpcg_line_search(
+            self.h, B, off.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(_model(model)),
+            C.byref(_trajectory(traj, self.nx, self.nu)), _ptr(dX), opt(dU), opt(lam), float(mu),
+            _ptr(X), opt(U), merit.data_ptr(), choice.data_ptr(), _stream()), "mpcpcg_line_search")
+        return dict(X=X, U=U, merit=merit, choice=choice)
 
 
 def to_device(d, device="cuda"):

@@ -50,6 +50,31 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(mpcpcg.Opts) == 16
     assert ctypes.sizeof(mpcpcg.Problem) == 16 + 8 * 8
     assert mpcpcg.STATS_DTYPE.itemsize == 16
+    # mpcpcg_chain_model: three floats, padding, one pointer; mpcpcg_trajectory: three
+    # int32, padding, six pointers
+    assert ctypes.sizeof(mpcpcg.ChainModel) == 24 and mpcpcg.ChainModel.gravity.offset == 16
+    assert ctypes.sizeof(mpcpcg.Trajectory) == 16 + 6 * 8
+    m = re.search(r"#define MPCPCG_LS_STEPS (\d+)", open(HEADER).read())
+    assert m and int(m.group(1)) == mpcpcg.LS_STEPS
+
+
+def test_trajectory_generator_and_packing():
+    t = synth.trajectory(6, seed=5)
+    assert t["X"].shape == (6, 14) and t["U"].shape == (5, 7) and t["R"].shape == (5, 7, 7)
+    assert all(v.dtype == np.float32 and v.flags.c_contiguous for v in t.values())
+    assert np.allclose(t["xref"], t["xref"][0]) and np.all(t["xref"][:, 7:] == 0)
+    g = np.random.default_rng(5)
+    x_init = np.concatenate([g.uniform(-1.0, 1.0, 7), 0.5 * g.standard_normal(7)])
+    assert np.array_equal(t["x_init"], x_init.astype(np.float32))
+    m = synth.chain_model(7, seed=3)
+    assert m["gravity"].shape == (7,) and m["h"] == float(np.float32(0.01))
+    trajs = synth.trajectories([1, 4, 2], seed0=40)
+    packed, off = synth.pack_trajectories(trajs)
+    assert list(off) == [0, 1, 5, 7]
+    assert packed["U"].shape == (4, 7) and packed["x_init"].shape == (3, 14)
+    assert np.array_equal(packed["U"][off[1] - 1:off[2] - 2], trajs[1]["U"])
+    with pytest.raises(ValueError):
+        synth.trajectory(4, nx=14, nu=6)
 
 
 def test_generator_recipe_and_packing():

@@ -1,0 +1,224 @@
+"""GPU parity for the control step around the solve: linearisation and line search.
+
+Both sides work in FP64 on the same FP32 inputs (oracle/nmpc.py written from Section III-A
+Steps 1 and 3 and Section IV-C; the library's ctrl kernels).  Bars:
+* linearisation: FP32 outputs of FP64 arithmetic, so within one FP32 rounding:
+  |gpu - ref| <= 2^-23 |ref| + 1e-12 elementwise (the two sides associate a few sums
+  differently, which moves the FP64 value by ~1e-16 relative);
+* merits: FP64 sums of the same terms in a different order: 1e-11 relative;
+* the choice is an integer decided by FP64 merits on both sides: it must equal the
+  oracle's, unless the oracle's own best two merits lie within that 1e-11, in which case
+  the GPU's choice must be one of the oracle's minimisers;
+* the updated iterate is x + a dx formed in FP64 and rounded once: bit-exact.
+Search directions come from the oracle's exact KKT solve of the oracle's linearisation
+(scaled to force interior choices); no oracle input comes from the GPU.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import kkt, nmpc
+from paper_2309_08079_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_M = 1e-11
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_08079_amd.mpcpcg import Context
+    c = Context(14, 7, max_total_knots=1 << 14, max_batch=64)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctx28():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2309_08079_amd.mpcpcg import Context
+    c = Context(28, 14, max_total_knots=4096, max_batch=16)
+    yield c
+    c.close()
+
+
+def dev(d):
+    from paper_2309_08079_amd.mpcpcg import to_device
+    return to_device(d)
+
+
+def dmodel(m):
+    return dict(m, gravity=torch.from_numpy(m["gravity"]).cuda())
+
+
+def close32(gpu, ref):
+    gpu = np.asarray(gpu, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert gpu.shape == ref.shape
+    bad = np.abs(gpu - ref) > 2.0 ** -23 * np.abs(ref) + 1e-12
+    return not bad.any(), (np.argwhere(bad)[:3], gpu[bad][:3], ref[bad][:3])
+
+
+def check_linearize(c, trajs, m, nx, nu):
+    packed, off = synth.pack_trajectories(trajs)
+    lq = c.mpcpcg_linearize(dmodel(m), dev(packed), off)
+    torch.cuda.synchronize()
+    g = {k: lq[k].cpu().numpy() for k in ("A", "B", "q", "r", "x0", "e")}
+    for b, t in enumerate(trajs):
+        ref = nmpc.linearize(t, m)
+        k0, k1 = off[b], off[b + 1]
+        c0, c1 = k0 - b, k1 - b - 1
+        for key, got in (("q", g["q"][k0:k1]), ("x0", g["x0"][b]), ("A", g["A"][c0:c1]),
+                         ("B", g["B"][c0:c1]), ("r", g["r"][c0:c1]), ("e", g["e"][c0:c1])):
+            ok, info = close32(got, ref[key])
+            assert ok, (b, key, info)
+
+
+@pytest.mark.parametrize("N", [1, 2, 31, 32, 33, 130])
+def test_linearize_single_matches_oracle(ctx, N):
+    check_linearize(ctx, [synth.trajectory(N, seed=12000 + N)], synth.chain_model(7, seed=10002), 14, 7)
+
+
+def test_linearize_batched_ragged_matches_oracle(ctx):
+    Ns = [5, 1, 64, 33, 100, 2, 17]
+    check_linearize(ctx, synth.trajectories(Ns, seed0=12100), synth.chain_model(7, seed=10003), 14, 7)
+
+
+def test_linearize_wide_matches_oracle(ctx28):
+    Ns = [40, 1, 9]
+    check_linearize(ctx28, synth.trajectories(Ns, 28, 14, seed0=12200), synth.chain_model(14, seed=10004), 28, 14)
+
+
+def directions(t, m, kind, seed):
+    """A search direction from the oracle alone: the exact SQP step, scaled, or random."""
+    lq = nmpc.linearize(t, m)
+    ex = kkt.kkt_solve(lq)
+    if kind == "random":
+        g = np.random.default_rng(seed)
+        return g.standard_normal(ex["dx"].shape), g.standard_normal(ex["du"].shape), ex["lam"]
+    s = {"step": 1.0, "overshoot16": 16.0, "overshoot3": 3.0}[kind]
+    return s * ex["dx"], s * ex["du"], ex["lam"]
+
+
+def check_line_search(c, trajs, m, kinds, mu, use_lam, inplace=False, seed=0):
+    dirs = [directions(t, m, kinds[b % len(kinds)], seed + b) for b, t in enumerate(trajs)]
+    dX = np.concatenate([d[0] for d in dirs]).astype(np.float32)
+    dU = np.concatenate([d[1] for d in dirs]).astype(np.float32)
+    lam = np.concatenate([d[2] for d in dirs]).astype(np.float32)
+    packed, off = synth.pack_trajectories(trajs)
+    dt = dev(packed)
+    out = dict(X=dt["X"], U=dt["U"]) if inplace else None
+    res = c.mpcpcg_line_search(dmodel(m), dt, off, torch.from_numpy(dX).cuda(), torch.from_numpy(dU).cuda(),
+                               lam=torch.from_numpy(lam).cuda() if use_lam else None, mu=mu, out=out)
+    torch.cuda.synchronize()
+    if inplace:
+        assert res["X"].data_ptr() == dt["X"].data_ptr() and res["U"].data_ptr() == dt["U"].data_ptr()
+    merit, choice = res["merit"].cpu().numpy(), res["choice"].cpu().numpy()
+    Xg, Ug = res["X"].cpu().numpy(), res["U"].cpu().numpy()
+    picks = []
+    for b, t in enumerate(trajs):
+        k0, k1 = off[b], off[b + 1]
+        c0, c1 = k0 - b, k1 - b - 1
+        # the oracle sees exactly the FP32 directions the GPU received
+        ref = nmpc.line_search(t, m, dX[k0:k1], dU[c0:c1], lam=lam[k0:k1] if use_lam else None, mu=mu)
+        rm = ref["merit"]
+        assert np.all(np.abs(merit[b] - rm) <= TOL_M * np.abs(rm)), (b, merit[b], rm)
+        j = int(choice[b])
+        if j != ref["choice"]:
+            best = rm.min()
+            assert rm[j] <= best + TOL_M * abs(best), (b, j, ref["choice"], rm)
+            a = nmpc.ALPHAS[j]
+            wantX = (t["X"].astype(np.float64) + a * dX[k0:k1].astype(np.float64)).astype(np.float32)
+            wantU = (t["U"].astype(np.float64) + a * dU[c0:c1].astype(np.float64)).astype(np.float32)
+        else:
+            wantX, wantU = ref["X"], ref["U"]
+        assert np.array_equal(Xg[k0:k1], wantX), b
+        assert np.array_equal(Ug[c0:c1], wantU), b
+        picks.append(j)
+    return picks
+
+
+@pytest.mark.parametrize("kind,expect", [("step", None), ("overshoot16", 4), ("overshoot3", None),
+                                         ("random", None)])
+def test_line_search_single_matches_oracle(ctx, kind, expect):
+    m = synth.chain_model(7, seed=10005)
+    picks = check_line_search(ctx, [synth.trajectory(64, seed=12300)], m, [kind], mu=1.0, use_lam=True)
+    if expect is not None:
+        assert picks[0] == expect
+
+
+def test_line_search_batched_ragged_matches_oracle(ctx):
+    Ns = [1, 5, 32, 33, 64, 100, 2, 250]
+    m = synth.chain_model(7, seed=10006)
+    picks = check_line_search(ctx, synth.trajectories(Ns, seed0=12400), m,
+                              ["step", "overshoot16", "overshoot3", "random"], mu=1.0, use_lam=True, seed=5)
+    assert len(set(picks)) > 1   # the batch exercises more than one step length
+
+
+def test_line_search_fixed_penalty_and_in_place(ctx):
+    Ns = [20, 40]
+    m = synth.chain_model(7, seed=10007)
+    check_line_search(ctx, synth.trajectories(Ns, seed0=12500), m, ["overshoot3", "step"], mu=10.0,
+                      use_lam=False, inplace=True)
+
+
+def test_line_search_wide_matches_oracle(ctx28):
+    Ns = [64, 1, 33]
+    m = synth.chain_model(14, seed=10008)
+    check_line_search(ctx28, synth.trajectories(Ns, 28, 14, seed0=12600), m, ["overshoot16", "step", "random"],
+                      mu=1.0, use_lam=True, seed=9)
+
+
+def test_control_step_argument_checks(ctx):
+    from paper_2309_08079_amd import mpcpcg as M
+    m = synth.chain_model(7, seed=1)
+    t = dev(synth.trajectory(4, seed=1))
+    dX, dU = torch.zeros_like(t["X"]), torch.zeros_like(t["U"])
+    with pytest.raises(M.MPCPCGError, match="mu"):
+        ctx.mpcpcg_line_search(dmodel(m), t, [0, 4], dX, dU, mu=-1.0)
+    with pytest.raises(M.MPCPCGError, match="dU"):
+        ctx.mpcpcg_line_search(dmodel(m), t, [0, 4], dX, None)
+    bad = dict(m, h=float("nan"))
+    with pytest.raises(M.MPCPCGError, match="finite"):
+        ctx.mpcpcg_linearize(dmodel(bad), t, [0, 4])
+    with pytest.raises(M.MPCPCGError, match="N=0"):
+        ctx.mpcpcg_linearize(dmodel(m), t, [0, 4, 4])
+
+
+def test_sqp_iterations_on_gpu_match_oracle(ctx):
+    # the whole control-step loop on the GPU (linearise -> factorisation solve -> line
+    # search, iterate updated in place) against the same loop in the oracle with the exact
+    # KKT solve; both converge to the same local solution of the nonlinear problem
+    from paper_2309_08079_amd.mpcpcg import stats_to_numpy
+    m = synth.chain_model(7, seed=10009)
+    Ns = [16, 40]
+    trajs = synth.trajectories(Ns, seed0=12700)
+    packed, off = synth.pack_trajectories(trajs)
+    dt, dm = dev(packed), dmodel(m)
+    ctx.mpcpcg_set_method("factor")
+    try:
+        for it in range(6):
+            lq = ctx.mpcpcg_linearize(dm, dt, off)
+            sol = ctx.mpcpcg_solve_batched(lq, off)
+            ctx.mpcpcg_line_search(dm, dt, off, sol["dx"], sol["du"], lam=sol["lam"], mu=1.0,
+                                   out=dict(X=dt["X"], U=dt["U"]))
+        torch.cuda.synchronize()
+        assert (stats_to_numpy(sol["stats"])["status"] == 0).all()
+    finally:
+        ctx.mpcpcg_set_method("pcg")
+    Xg, Ug = dt["X"].cpu().numpy(), dt["U"].cpu().numpy()
+    for b, t in enumerate(trajs):
+        t = dict(t)
+        for it in range(6):
+            ex = kkt.kkt_solve(nmpc.linearize(t, m))
+            ls = nmpc.line_search(t, m, ex["dx"], ex["du"], lam=ex["lam"], mu=1.0)
+            t["X"], t["U"] = ls["X"], ls["U"]
+        k0, k1 = off[b], off[b + 1]
+        assert nmpc.violation(Xg[k0:k1], Ug[k0 - b:k1 - b - 1], t, m) < 1e-3
+        assert np.abs(Xg[k0:k1] - t["X"]).max() < 1e-4 * max(1.0, np.abs(t["X"]).max()), b
