@@ -250,6 +250,29 @@ int mpcpcg_line_search(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
                        float *X_out, float *U_out, double *merit, int32_t *choice,
                        hipStream_t stream);
 
+/* One control step as a single call (the paper's goal of one host-device synchronisation
+ * per control step, Section IV): sqp_iters (1..16) iterations of
+ *   mpcpcg_linearize -> mpcpcg_solve_batched (with *opts and the context's method)
+ *   -> mpcpcg_line_search (penalty mu + max |lambda_b|),
+ * each iteration starting from the previous one's iterate.  The first iteration reads the
+ * guess from traj->X / traj->U; the updated iterate goes to X_out / U_out, which may be
+ * traj->X / traj->U (in-place update, the usual receding-horizon use).  lambda [N][nx]
+ * receives the multipliers and is the warm start of every solve when opts->warm_start
+ * is set; merit, choice and stats are those of the last iteration.
+ * The LQ problem and the step live in context workspace (~1.4 KB per knot of
+ * max_total_knots at (14, 7), allocated on first use).  With graphs enabled
+ * (mpcpcg_set_graph), the first call with a given batch signature and argument set runs
+ * the launches directly, the second captures them into one hipGraph, and later calls
+ * replay it on `stream`: the whole step is then one graph launch.  The graph reads the
+ * arrays at replay time, so new values in the same buffers need no new capture; other
+ * pointers or scalars start the sequence again.  Calls that overlap on one context race
+ * on the workspace. */
+int mpcpcg_control_step(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
+                        const mpcpcg_chain_model *model, const mpcpcg_trajectory *traj,
+                        const mpcpcg_opts *opts, int32_t sqp_iters, float mu, float *lambda,
+                        float *X_out, float *U_out, double *merit, int32_t *choice,
+                        mpcpcg_stats *stats, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

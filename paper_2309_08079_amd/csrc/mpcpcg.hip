@@ -54,6 +54,15 @@ struct CtrlSchedule {
   int nchunks = 0;
 };
 
+// one captured control step per horizon signature: the graph is valid for the argument
+// signature it was captured with
+struct CtrlGraph {
+  std::vector<uint64_t> sig;
+  int calls = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
 struct WideSchedule {
   mpc::wide::KnotDesc *d_knots = nullptr;
   mpc::wide::ProbDescW *d_probs = nullptr;
@@ -87,6 +96,10 @@ struct mpcpcg_ctx {
   // control step: chunk lists and the line search's per-chunk partial sums (on first use)
   std::map<std::vector<int64_t>, std::unique_ptr<CtrlSchedule>> csched;
   double *ls_part = nullptr;
+  // control step: the LQ problem and the step between its stages (on first use), graphs
+  float *cs_ws = nullptr;
+  hipStream_t cap_stream = nullptr;
+  std::map<std::vector<int64_t>, std::unique_ptr<CtrlGraph>> cgraph;
   std::string err;
 };
 
@@ -633,6 +646,12 @@ int mpcpcg_destroy(mpcpcg_ctx *c) {
   for (auto &kv : c->csched)
     if (kv.second->d_chunks) (void)hipFree(kv.second->d_chunks);
   if (c->ls_part) (void)hipFree(c->ls_part);
+  for (auto &kv : c->cgraph) {
+    if (kv.second->exec) (void)hipGraphExecDestroy(kv.second->exec);
+    if (kv.second->graph) (void)hipGraphDestroy(kv.second->graph);
+  }
+  if (c->cs_ws) (void)hipFree(c->cs_ws);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (auto &kv : c->wsched) {
     if (kv.second->d_knots) (void)hipFree(kv.second->d_knots);
     if (kv.second->d_probs) (void)hipFree(kv.second->d_probs);
@@ -867,6 +886,99 @@ int mpcpcg_line_search(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const m
     hipLaunchKernelGGL(mpc::ctrl::ls_update_kernel<kNX>, g, blk, 0, s, a);
   }
   HIPCHK(c, hipGetLastError());
+  return MPCPCG_OK;
+}
+
+// The stages of one control step, launched on `s`: for each SQP iteration, linearise at
+// the current iterate, solve the LQ problem, line-search; iterations after the first read
+// the iterate from X_out / U_out.
+static int control_body(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const mpcpcg_chain_model *m,
+                        const mpcpcg_trajectory *t, const mpcpcg_opts *o, int32_t iters, float mu,
+                        float *lambda, float *X_out, float *U_out, double *merit, int32_t *choice,
+                        mpcpcg_stats *stats, hipStream_t s) {
+  const size_t K = (size_t)c->max_knots, nx = c->nx, nu = c->nu;
+  float *A = c->cs_ws, *B = A + K * nx * nx, *q = B + K * nx * nu, *r = q + K * nx;
+  float *x0 = r + K * nu, *e = x0 + (size_t)c->max_batch * nx, *dx = e + K * nx, *du = dx + K * nx;
+  mpcpcg_trajectory cur = *t;
+  mpcpcg_problem p;
+  p.nx = c->nx; p.nu = c->nu; p.N = t->N;
+  p.Q = t->Q; p.R = t->R; p.A = A; p.B = B; p.q = q; p.r = r; p.x0 = x0; p.e = e;
+  for (int it = 0; it < iters; ++it) {
+    int st = mpcpcg_linearize(c, batch, off, m, &cur, A, B, q, r, x0, e, s);
+    if (!st) st = mpcpcg_solve_batched(c, batch, off, &p, o, lambda, dx, du, stats, s);
+    if (!st) st = mpcpcg_line_search(c, batch, off, m, &cur, dx, du, lambda, mu, X_out, U_out, merit, choice, s);
+    if (st) return st;
+    cur.X = X_out;
+    cur.U = U_out;
+  }
+  return MPCPCG_OK;
+}
+
+int mpcpcg_control_step(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const mpcpcg_chain_model *m,
+                        const mpcpcg_trajectory *t, const mpcpcg_opts *o, int32_t sqp_iters, float mu,
+                        float *lambda, float *X_out, float *U_out, double *merit, int32_t *choice,
+                        mpcpcg_stats *stats, hipStream_t s) {
+  if (!c) return MPCPCG_EINVAL;
+  bool ctrl = false;
+  int st = check_ctrl(c, batch, off, m, t, &ctrl);
+  if (st) return st;
+  if ((st = check_opts(c, o))) return st;
+  if (sqp_iters < 1 || sqp_iters > 16) return fail(c, MPCPCG_EINVAL, "sqp_iters must be in [1, 16]");
+  if (!(mu >= 0.0f) || !std::isfinite(mu)) return fail(c, MPCPCG_EINVAL, "mu must be finite and >= 0");
+  if (!lambda || !X_out || !merit || !choice || !stats || (ctrl && !U_out))
+    return fail(c, MPCPCG_EINVAL, "lambda, X_out, U_out, merit, choice and stats must be non-NULL");
+  if (!c->cs_ws) {
+    const size_t K = (size_t)c->max_knots, nx = c->nx, nu = c->nu;
+    const size_t n = K * (nx * nx + nx * nu + 3 * nx + 2 * nu) + (size_t)c->max_batch * nx;
+    if (hipMalloc(&c->cs_ws, sizeof(float) * n) != hipSuccess) {
+      (void)hipGetLastError();
+      c->cs_ws = nullptr;
+      return fail(c, MPCPCG_ENOMEM, "cannot allocate the control-step workspace");
+    }
+  }
+  if (!c->use_graph) return control_body(c, batch, off, m, t, o, sqp_iters, mu, lambda, X_out, U_out, merit, choice, stats, s);
+
+  // everything the launches depend on, so that a replay is exactly a fresh call
+  std::vector<int64_t> key(off, off + batch + 1);
+  auto u64 = [](const void *p) { return (uint64_t)(uintptr_t)p; };
+  auto f32 = [](float v) { uint32_t b; std::memcpy(&b, &v, 4); return (uint64_t)b; };
+  std::vector<uint64_t> sig = {
+      f32(m->h), f32(m->damping), f32(m->coupling), u64(m->gravity),
+      u64(t->X), u64(t->U), u64(t->x_init), u64(t->xref), u64(t->Q), u64(t->R),
+      f32(o->eps), (uint64_t)(uint32_t)o->max_iter, (uint64_t)o->warm_start, (uint64_t)o->stop_rule,
+      (uint64_t)sqp_iters, f32(mu), u64(lambda), u64(X_out), u64(U_out), u64(merit), u64(choice), u64(stats),
+      (uint64_t)c->method, (uint64_t)c->kpw_override, (uint64_t)pick_kpw(c, key)};
+  auto &slot = c->cgraph[key];
+  if (!slot) slot = std::make_unique<CtrlGraph>();
+  CtrlGraph *g = slot.get();
+  if (g->sig != sig) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    g->exec = nullptr; g->graph = nullptr; g->calls = 0; g->sig = sig;
+  }
+  if (g->exec) {
+    HIPCHK(c, hipGraphLaunch(g->exec, s));
+    return MPCPCG_OK;
+  }
+  if (g->calls++ == 0)  // the first call runs eagerly and creates every schedule and workspace
+    return control_body(c, batch, off, m, t, o, sqp_iters, mu, lambda, X_out, U_out, merit, choice, stats, s);
+  // the second captures the same launches on the context's own stream and replays them
+  if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  const int saved = c->use_graph;
+  c->use_graph = 0;  // the solve's launches go into this graph, not into a graph of their own
+  st = control_body(c, batch, off, m, t, o, sqp_iters, mu, lambda, X_out, U_out, merit, choice, stats, c->cap_stream);
+  c->use_graph = saved;
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(c->cap_stream, &graph);
+  if (st || ec != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    if (st) return st;
+    return fail(c, MPCPCG_EHIP, "capturing the control step failed: %s", hipGetErrorString(ec));
+  }
+  g->graph = graph;
+  HIPCHK(c, hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
+  HIPCHK(c, hipGraphLaunch(g->exec, s));
   return MPCPCG_OK;
 }
 

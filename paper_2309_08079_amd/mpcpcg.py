@@ -82,10 +82,11 @@ def load_library(path: str = _LIB_PATH):
     M, T = C.POINTER(ChainModel), C.POINTER(Trajectory)
     lib.mpcpcg_linearize.argtypes = [vp, i32, i64p, M, T] + [vp] * 6 + [vp]
     lib.mpcpcg_line_search.argtypes = [vp, i32, i64p, M, T, vp, vp, vp, C.c_float] + [vp] * 4 + [vp]
+    lib.mpcpcg_control_step.argtypes = [vp, i32, i64p, M, T, O, i32, C.c_float] + [vp] * 6 + [vp]
     for f in ("mpcpcg_create", "mpcpcg_destroy", "mpcpcg_form_schur", "mpcpcg_solve",
               "mpcpcg_solve_batched", "mpcpcg_backward", "mpcpcg_set_knots_per_group",
               "mpcpcg_set_graph", "mpcpcg_autotune", "mpcpcg_set_method", "mpcpcg_linearize",
-              "mpcpcg_line_search"):
+              "mpcpcg_line_search", "mpcpcg_control_step"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -315,6 +316,27 @@ class Context:
             C.byref(_trajectory(traj, self.nx, self.nu)), _ptr(dX), opt(dU), opt(lam), float(mu),
             _ptr(X), opt(U), merit.data_ptr(), choice.data_ptr(), _stream()), "mpcpcg_line_search")
         return dict(X=X, U=U, merit=merit, choice=choice)
+
+
+    def mpcpcg_control_step(self, model, traj, knot_off, lam, X_out, U_out, sqp_iters=1, mu=0.0,
+                            eps=1e-6, max_iter=0, warm=False, stop="relative", out=None):
+        """sqp_iters x (linearise, solve, line search) as one call; lam [N, nx] receives the
+        multipliers (and is the warm start when ``warm``).  Returns dict merit, choice,
+        stats; the iterate is written to X_out / U_out (may be traj's own X / U)."""
+        off = np.ascontiguousarray(knot_off, dtype=np.int64)
+        B = len(off) - 1
+        dev = traj["X"].device
+        o = out or {}
+        merit = o["merit"] if "merit" in o else torch.empty((B, LS_STEPS), dtype=torch.float64, device=dev)
+        choice = o["choice"] if "choice" in o else torch.empty((B,), dtype=torch.int32, device=dev)
+        stats = o["stats"] if "stats" in o else torch.zeros((B, 4), dtype=torch.int32, device=dev)
+        opt = lambda t: _ptr(t) if t is not None and t.numel() else None
+        self._check(self.lib.mpcpcg_control_step(
+            self.h, B, off.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(_model(model)),
+            C.byref(_trajectory(traj, self.nx, self.nu)), C.byref(_opts(eps, max_iter, warm, stop)),
+            int(sqp_iters), float(mu), _ptr(lam), _ptr(X_out), opt(U_out), merit.data_ptr(),
+            choice.data_ptr(), stats.data_ptr(), _stream()), "mpcpcg_control_step")
+        return dict(merit=merit, choice=choice, stats=stats)
 
 
 def to_device(d, device="cuda"):

@@ -222,3 +222,79 @@ def test_sqp_iterations_on_gpu_match_oracle(ctx):
         k0, k1 = off[b], off[b + 1]
         assert nmpc.violation(Xg[k0:k1], Ug[k0 - b:k1 - b - 1], t, m) < 1e-3
         assert np.abs(Xg[k0:k1] - t["X"]).max() < 1e-4 * max(1.0, np.abs(t["X"]).max()), b
+
+
+# ---- the control step as one call (one graph launch) ---------------------------------------
+
+def run_steps(c, method, graph, trajs, m, steps, iters, warm):
+    from paper_2309_08079_amd.mpcpcg import stats_to_numpy
+    c.mpcpcg_set_method(method)
+    c.mpcpcg_set_graph(graph)
+    packed, off = synth.pack_trajectories(trajs)
+    dt, dm = dev(packed), dmodel(m)
+    lam = torch.zeros((int(off[-1]), 14), device="cuda")
+    outs = []
+    for step in range(steps):
+        r = c.mpcpcg_control_step(dm, dt, off, lam, dt["X"], dt["U"], sqp_iters=iters, mu=1.0, warm=warm)
+        torch.cuda.synchronize()
+        # unrelated eager work between replays
+        assert float(torch.ones(4096, device="cuda").sum()) == 4096.0
+        outs.append(dict(X=dt["X"].cpu().numpy(), U=dt["U"].cpu().numpy(), lam=lam.cpu().numpy(),
+                         merit=r["merit"].cpu().numpy(), choice=r["choice"].cpu().numpy(),
+                         stats=stats_to_numpy(r["stats"]).copy()))
+    c.mpcpcg_set_graph(True)
+    c.mpcpcg_set_method("pcg")
+    return outs, off
+
+
+@pytest.mark.parametrize("method", ["pcg", "factor"])
+def test_control_step_graph_replays_match_eager(ctx, method):
+    # calls 1 (direct launches), 2 (capture + launch) and 3..5 (replays) against the same
+    # steps with graphs disabled, every call compared bit for bit
+    from paper_2309_08079_amd.mpcpcg import Context
+    m = synth.chain_model(7, seed=10010)
+    Ns = [24, 64, 9]
+    trajs = synth.trajectories(Ns, seed0=12800)
+    other = Context(14, 7, max_total_knots=1 << 14, max_batch=64)
+    try:
+        got, off = run_steps(ctx, method, True, trajs, m, 5, 2, True)
+        ref, _ = run_steps(other, method, False, trajs, m, 5, 2, True)
+    finally:
+        other.close()
+    for step, (g, r) in enumerate(zip(got, ref)):
+        for k in ("X", "U", "lam", "merit", "choice"):
+            assert np.array_equal(g[k], r[k]), (step, k)
+        assert np.array_equal(g["stats"], r["stats"]), step
+        assert (g["stats"]["status"] == 0).all(), step
+
+
+def test_control_step_matches_oracle_sqp(ctx):
+    # three SQP iterations in one call (factorisation solve) against the oracle's loop with
+    # the exact KKT solve; both reach the same solution of the nonlinear problem
+    m = synth.chain_model(7, seed=10011)
+    Ns = [12, 33]
+    trajs = synth.trajectories(Ns, seed0=12900)
+    got, off = run_steps(ctx, "factor", True, trajs, m, 1, 3, False)
+    Xg, Ug = got[0]["X"], got[0]["U"]
+    for b, t in enumerate(trajs):
+        t = dict(t)
+        for it in range(3):
+            ex = kkt.kkt_solve(nmpc.linearize(t, m))
+            ls = nmpc.line_search(t, m, ex["dx"], ex["du"], lam=ex["lam"], mu=1.0)
+            t["X"], t["U"] = ls["X"], ls["U"]
+        k0, k1 = off[b], off[b + 1]
+        assert np.abs(Xg[k0:k1] - t["X"]).max() < 1e-4 * max(1.0, np.abs(t["X"]).max()), b
+        assert np.abs(Ug[k0 - b:k1 - b - 1] - t["U"]).max() < 1e-3 * max(1.0, np.abs(t["U"]).max()), b
+
+
+def test_control_step_call_argument_checks(ctx):
+    from paper_2309_08079_amd import mpcpcg as M
+    m = dmodel(synth.chain_model(7, seed=1))
+    t = dev(synth.trajectory(4, seed=1))
+    lam = torch.zeros((4, 14), device="cuda")
+    with pytest.raises(M.MPCPCGError, match="sqp_iters"):
+        ctx.mpcpcg_control_step(m, t, [0, 4], lam, t["X"], t["U"], sqp_iters=0)
+    with pytest.raises(M.MPCPCGError, match="mu"):
+        ctx.mpcpcg_control_step(m, t, [0, 4], lam, t["X"], t["U"], mu=float("nan"))
+    with pytest.raises(M.MPCPCGError, match="stop"):
+        ctx.mpcpcg_control_step(m, t, [0, 4], lam, t["X"], t["U"], stop="never")
