@@ -357,6 +357,86 @@ def factor_path(dev, stream, reps=3):
         ctx.close()
 
 
+def control_step(dev, stream, reps=20):
+    """The control step around the solve on the pendulum-chain stand-in model (model seed
+    10000, trajectory seeds 13000 + N): per horizon, the linearisation and line-search
+    kernels alone and one whole step (linearise, factorisation solve, line search) as three
+    calls vs one graph launch; then one step of a 256-problem batch at N = 128.  The line
+    search's algorithmic bytes per knot: X, dX, xref, lambda (4 nx floats), Q (nx^2), U, dU
+    (2 nu), R (nu^2) read; X, U written."""
+    import torch
+    from paper_2309_08079_amd import synth
+    from paper_2309_08079_amd.mpcpcg import Context, stats_to_numpy, to_device
+
+    m = synth.chain_model(NU, seed=10000)
+    dm = dict(m, gravity=torch.from_numpy(m["gravity"]).to(dev))
+    ls_bytes_knot = 4 * (4 * NX + NX * NX + 2 * NU + NU * NU) + 4 * (NX + NU)
+    rows = []
+    for N in (32, 64, 128, 256, 512):
+        packed, off = synth.pack_trajectories([synth.trajectory(N, NX, NU, seed=13000 + N)])
+        ctx = Context(NX, NU, max_total_knots=N, max_batch=1)
+        try:
+            ctx.mpcpcg_set_method("factor")
+            d = to_device(packed, dev)
+            X0, U0 = d["X"].clone(), d["U"].clone()
+            lam = torch.zeros((N, NX), device=dev)
+            lq = ctx.mpcpcg_linearize(dm, d, off)
+            lin_ms = _time_ms(lambda: ctx.mpcpcg_linearize(dm, d, off, out=lq), stream, reps)
+            sol = ctx.mpcpcg_solve_batched(lq, off)
+            lso = dict(X=torch.empty_like(d["X"]), U=torch.empty_like(d["U"]))
+            lso.update(ctx.mpcpcg_line_search(dm, d, off, sol["dx"], sol["du"], lam=sol["lam"], mu=1.0, out=lso))
+            ls_ms = _time_ms(lambda: ctx.mpcpcg_line_search(dm, d, off, sol["dx"], sol["du"], lam=sol["lam"],
+                                                            mu=1.0, out=lso), stream, reps)
+            solve_ms = _time_ms(lambda: ctx.mpcpcg_solve_batched(lq, off, out=sol), stream, reps)
+            times = {}
+            for graph in (False, True):
+                ctx.mpcpcg_set_graph(graph)
+                d["X"].copy_(X0)
+                d["U"].copy_(U0)
+                out = ctx.mpcpcg_control_step(dm, d, off, lam, d["X"], d["U"], mu=1.0)
+                times[graph] = _time_ms(lambda: ctx.mpcpcg_control_step(dm, d, off, lam, d["X"], d["U"], mu=1.0,
+                                                                        out=out), stream, reps)
+            ok = bool((stats_to_numpy(out["stats"])["status"] == 0).all())
+            rows.append({"N": N, "linearize_us": round(lin_ms * 1e3, 2), "solve_us": round(solve_ms * 1e3, 2),
+                         "line_search_us": round(ls_ms * 1e3, 2),
+                         "line_search_gbps": round(ls_bytes_knot * N / (ls_ms * 1e-3) / 1e9, 1),
+                         "step_us_three_calls": round(times[False] * 1e3, 2),
+                         "step_us_one_graph": round(times[True] * 1e3, 2),
+                         "control_rate_hz": round(1e3 / times[True], 1), "ok": ok})
+        finally:
+            ctx.close()
+    # batch: 256 problems of N = 128, one control step, the library's method choice
+    Bn, Nb = 256, 128
+    packed, off = synth.pack_trajectories(synth.trajectories([Nb] * Bn, NX, NU, seed0=14000))
+    K = int(off[-1])
+    ctx = Context(NX, NU, max_total_knots=K, max_batch=Bn)
+    try:
+        ctx.mpcpcg_set_method("auto")
+        d = to_device(packed, dev)
+        lam = torch.zeros((K, NX), device=dev)
+        out = ctx.mpcpcg_control_step(dm, d, off, lam, d["X"], d["U"], mu=1.0)
+        bms = _time_ms(lambda: ctx.mpcpcg_control_step(dm, d, off, lam, d["X"], d["U"], mu=1.0, out=out),
+                       stream, 5)
+        lq = ctx.mpcpcg_linearize(dm, d, off)
+        blin = _time_ms(lambda: ctx.mpcpcg_linearize(dm, d, off, out=lq), stream, reps)
+        sol = ctx.mpcpcg_solve_batched(lq, off)
+        lso = dict(X=torch.empty_like(d["X"]), U=torch.empty_like(d["U"]))
+        lso.update(ctx.mpcpcg_line_search(dm, d, off, sol["dx"], sol["du"], lam=sol["lam"], mu=1.0, out=lso))
+        bls = _time_ms(lambda: ctx.mpcpcg_line_search(dm, d, off, sol["dx"], sol["du"], lam=sol["lam"], mu=1.0,
+                                                      out=lso), stream, reps)
+        batch = {"problems": Bn, "knots": Nb, "step_ms_one_graph": round(bms, 3),
+                 "problem_steps_per_s": round(Bn / (bms * 1e-3), 1), "linearize_us": round(blin * 1e3, 2),
+                 "line_search_us": round(bls * 1e3, 2),
+                 "line_search_gbps": round(ls_bytes_knot * K / (bls * 1e-3) / 1e9, 1),
+                 "ok": bool((stats_to_numpy(out["stats"])["status"] == 0).all())}
+    finally:
+        ctx.close()
+    return {"model": "pendulum chain, 7 joints (nx=14, nu=7), h=0.01; factorisation solve for single "
+                     "problems, the library's automatic choice for the batch; line search over 9 steps, "
+                     "mu = 1 + max|lambda|",
+            "single": rows, "batch_256xN128": batch}
+
+
 def main():
     args = parse()
     if args.ingest_counters:
@@ -492,6 +572,7 @@ def main():
     seqs = warm_sequences(ctx, dev, stream)
     wide = two_arm_batch(dev, stream)
     fac = factor_path(dev, stream)
+    ctrl = control_step(dev, stream)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -527,6 +608,7 @@ def main():
         "warm_sequence": seqs,
         "two_arm_batch_32": wide,
         "factorisation_path": fac,
+        "control_step": ctrl,
         "roofline": {"bound": "alu", "kernel": "pcg_kernel<14,7,%d,%s>" % (kpw, dom_name),
                      "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_VALU_TFLOPS, "traffic": measured_traffic(dom_name, kpw)},

@@ -170,19 +170,21 @@ int mpcpcg_set_graph(mpcpcg_ctx *ctx, int32_t enable);
 
 /* Solution method of mpcpcg_solve, mpcpcg_solve_batched and mpcpcg_backward.
  *   MPCPCG_METHOD_PCG (default): PCG as above (Algorithm 1).
- *   MPCPCG_METHOD_FACTOR: direct solve of the same Schur system by block LDL^T
- *     factorisation of the block-tridiagonal S (D_0 = S_00, D_k = S_kk - S_{k,k-1}
- *     D_{k-1}^-1 S_{k-1,k}, forward and back substitution), the alternative to the
- *     iterative solve that the paper names as future work (Section VI).  FP64 throughout,
- *     exact up to rounding; eps, max_iter, warm_start and stop_rule are ignored;
- *     stats report iters = 0, status OK or BREAKDOWN (non-finite result), final_ratio = 0.
- *     Each problem is swept sequentially (one 16-lane group at (14, 7), one workgroup at
- *     (28, 14)), so a call costs ~N steps whatever the batch: at (14, 7) it wins when many
- *     problems are solved at once.  At (14, 7) it needs ~6.5 KB of extra device workspace
- *     per knot of max_total_knots, allocated on first use.
- *   MPCPCG_METHOD_AUTO: per call, at (14, 7) the factorisation when the batch would need
- *     several rounds of resident PCG workgroups (by a cost model of both), else PCG; at
- *     (28, 14) always the factorisation, which is faster there at every measured size. */
+ *   MPCPCG_METHOD_FACTOR: direct solve of the same Schur system, the alternative to the
+ *     iterative solve that the paper names as future work (Section VI).  At (14, 7) by
+ *     block cyclic reduction of the block-tridiagonal S (log2 N levels of parallel block
+ *     eliminations, one workgroup per problem); at (28, 14) by block LDL^T factorisation
+ *     (D_0 = S_00, D_k = S_kk - S_{k,k-1} D_{k-1}^-1 S_{k-1,k}, forward and back
+ *     substitution, one workgroup per problem).  FP64 throughout, exact up to rounding;
+ *     eps, max_iter, warm_start and stop_rule are ignored; stats report iters = 0, status
+ *     OK or BREAKDOWN (a non-positive pivot, i.e. S not positive definite, or a non-finite
+ *     result), final_ratio = 0.  Its cost does not depend on the conditioning of S.  At
+ *     (14, 7) it needs ~6.5 KB of extra device workspace per knot of max_total_knots,
+ *     allocated on first use.
+ *   MPCPCG_METHOD_AUTO: per call, at (14, 7) the factorisation when a cost model of both
+ *     (calibrated on ~100-iteration PCG solves) predicts it faster, which is the case when
+ *     the batch needs several rounds of resident PCG workgroups; else PCG.  At (28, 14)
+ *     always the factorisation, which is faster there at every measured size. */
 enum { MPCPCG_METHOD_PCG = 0, MPCPCG_METHOD_FACTOR = 1, MPCPCG_METHOD_AUTO = 2 };
 int mpcpcg_set_method(mpcpcg_ctx *ctx, int32_t method);
 

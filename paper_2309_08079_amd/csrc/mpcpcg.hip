@@ -323,20 +323,24 @@ int ensure_factor_ws(mpcpcg_ctx *c) {
 }
 
 // Whether a call takes the factorisation path: always for MPCPCG_METHOD_FACTOR; for
-// MPCPCG_METHOD_AUTO by a cost model measured on MI355X (N = 512, nx = 14):
+// MPCPCG_METHOD_AUTO by a cost model measured on MI355X (nx = 14):
 //   PCG: ~600 us per round of resident problems (768 workgroups of 16 knots, ~100
 //        iterations at ~6 us), rounds = ceil(knots / 12288);
-//   factorisation: ~4.1 us per knot of the longest horizon (the sequential sweep, all
-//        problems at once) plus ~260 us per round for its two parallel phases.
+//   factorisation: ~208 us per round for its two parallel phases (formation, primal
+//        step), plus the cyclic reduction, one workgroup per problem: ~25 + 0.73 N us for
+//        the longest horizon alone, up to 2.7x that when every CU holds a problem.
 bool use_factor(mpcpcg_ctx *c, const std::vector<int64_t> &off) {
   if (c->method == MPCPCG_METHOD_PCG) return false;
   if (c->method == MPCPCG_METHOD_FACTOR) return true;
   if (c->wide) return true;  // the 28-state PCG runs one workgroup per problem: always slower
+  const int64_t B = (int64_t)off.size() - 1;
   int64_t knots = off.back(), nmax = 0;
-  for (size_t b = 0; b + 1 < off.size(); ++b) nmax = std::max(nmax, off[b + 1] - off[b]);
+  for (int64_t b = 0; b < B; ++b) nmax = std::max(nmax, off[b + 1] - off[b]);
   const double rounds = std::ceil((double)knots / 12288.0);
   const double t_pcg = rounds * 600.0;
-  const double t_fac = 4.1 * (double)nmax + 260.0 * rounds + 60.0;
+  const double load = 1.0 + 1.7 * (double)std::min<int64_t>(B, c->cus) / (double)c->cus;
+  const double t_cr = (25.0 + 0.73 * (double)nmax) * load * std::ceil((double)B / (double)c->cus);
+  const double t_fac = 208.0 * rounds + t_cr;
   return t_fac < t_pcg;
 }
 
@@ -386,8 +390,7 @@ int run_factor(mpcpcg_ctx *c, KArgs a, int mode, Schedule *s, int N, hipStream_t
     t.probs = nullptr; t.nprobs = 1;
     t.single.k0 = 0; t.single.N = N; t.single.t0 = 0; t.single.nparts = 1; t.single.id = 0;
   }
-  const int per = mpc::kTriThreads / mpc::kGroup;
-  hipLaunchKernelGGL(mpc::tri_sweep<kNX>, dim3((t.nprobs + per - 1) / per), dim3(mpc::kTriThreads), 0, stream, t);
+  hipLaunchKernelGGL(mpc::cr_solve<kNX>, dim3(t.nprobs), dim3(mpc::kCrThreads), 0, stream, t);
   HIPCHK(c, hipGetLastError());
   return launch_phase(c, a, mode, 2, s, N, stream);
 }

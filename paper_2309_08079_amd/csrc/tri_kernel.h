@@ -1,22 +1,8 @@
-// Block-tridiagonal factorisation and solve of S lambda = rhs, one problem per 16-lane group.
-//
-// S is symmetric positive definite and block tridiagonal (N block rows of NX x NX), so its
-// block LDL^T factorisation needs no pivoting:
-//   D_0 = S_00,   L_k = S_{k,k-1} D_{k-1}^-1,   D_k = S_kk - L_k S_{k-1,k}      (k >= 1)
-//   y_0 = rhs_0,  y_k = rhs_k - L_k y_{k-1}
-//   lambda_{N-1} = D_{N-1}^-1 y_{N-1},   lambda_k = D_k^-1 (y_k - S_{k,k+1} lambda_{k+1}).
-// S is positive definite exactly when every D_k is; a pivot <= 0 in the inversion of some
-// D_k (or a non-finite result) is reported as MPCPCG_BREAKDOWN.
-// This is the direct alternative to PCG for the Schur system of MPCGPU (Section III-B):
-// it reaches the exact solution up to rounding in a fixed number of steps, with no
-// synchronisation between workgroups, at the price of a sequential sweep over the knots.
-// The forward sweep keeps D_k^-1 and y_k in the workspace for the back substitution.
-//
-// Work mapping: lane i of a group owns row i of every block, as in the PCG kernel; the
-// block products run on the fused DPP row broadcasts of lane_ops.h.  A workgroup is one
-// wave of four problems, so a batch spreads over the CUs; problems arrive longest-first so
-// the groups of a wave sweep similar lengths.
-// Arithmetic is FP64 throughout.
+// Direct solve of the block-tridiagonal Schur system S lambda = rhs by block cyclic
+// reduction (the alternative to PCG for the Schur system of MPCGPU, Section III-B; the
+// paper names a direct block-tridiagonal solve as future work, Section VI).  It reaches
+// the exact solution up to rounding in a fixed number of parallel steps, log2 N levels
+// per problem, with no synchronisation between workgroups.
 #pragma once
 #include "lane_ops.h"
 #include "mpcpcg.h"
@@ -25,9 +11,9 @@
 namespace mpc {
 
 struct TriArgs {
-  const double *s_ws;     // [knots][NX][3 NX]: rows of S_{b,b-1}, S_bb, S_{b,b+1}
-  double *rhs_ws;         // [knots][NX]: right-hand side in, y out
-  double *dinv_ws;        // [knots][NX][NX]: rows of D_b^-1
+  double *s_ws;           // [knots][NX][3 NX]: rows of S_{b,b-1}, S_bb, S_{b,b+1} (overwritten)
+  double *rhs_ws;         // [knots][NX]: right-hand side in (overwritten)
+  double *dinv_ws;        // [knots][NX][NX]: elimination workspace
   double *lam_ws;         // [knots][NX]: the solution
   const ProbDesc *probs;  // [nprobs] longest first, or nullptr for `single`
   ProbDesc single;
@@ -36,98 +22,144 @@ struct TriArgs {
   mpcpcg_stats *stats;    // indexed by ProbDesc::id
 };
 
-constexpr int kTriThreads = 64;  // one wave, four problems, per workgroup: problems spread over CUs
+// S is symmetric positive definite and block tridiagonal.  With stride s (1, 2, 4, ...), the active blocks are the
+// multiples of s; write L_i for the coupling of active block i to the active block before
+// it (S_{i,i-1} at s = 1) and D_i for its diagonal block.  One level:
+//   (a) every odd multiple j = s(2m+1) is eliminated:
+//         V_j = D_j^-1 L_j,   U_j = D_j^-1 L_{j+s}^T,   z_j = D_j^-1 y_j;
+//   (b) every even multiple i = 2sm absorbs its eliminated neighbours j = i -+ s:
+//         D_i -= L_i U_{i-s} + L_{i+s}^T V_{i+s},   y_i -= L_i z_{i-s} + L_{i+s}^T z_{i+s},
+//         L_i <- -L_i V_{i-s}  (the coupling to i - 2s).
+// The reduced systems are Schur complements of S, so they stay symmetric positive definite
+// (a pivot <= 0 in some D_j^-1 means S is not).  When block 0 is the last one active,
+// x_0 = D_0^-1 y_0, and the levels are undone in reverse order:
+//   x_j = z_j - V_j x_{j-s} - U_j x_{j+s}   (no U term when j + s >= N).
+// Work mapping: one workgroup per problem, one 16-lane group per block task, lane r owns
+// row r as in the other kernels; a workgroup barrier separates the sub-steps.  Storage is
+// the factorisation workspace: each knot's S row slots hold L and D (V once the knot is
+// eliminated: D_j is inverted in registers first), its third slot keeps S_{b,b+1} for the
+// primal step; dinv_ws holds U, rhs_ws holds y and then z, lam_ws the solution.  FP64
+// throughout.
+constexpr int kCrThreads = 512;
 
 template <int NX>
-__global__ void __launch_bounds__(kTriThreads) tri_sweep(const TriArgs a) {
+__global__ void __launch_bounds__(kCrThreads) cr_solve(const TriArgs a) {
+  constexpr int G = kCrThreads / kGroup;  // block tasks in flight per workgroup
   const int lane = threadIdx.x & (kGroup - 1);
-  const int g = blockIdx.x * (kTriThreads / kGroup) + (threadIdx.x >> 4);
-  if (g >= a.nprobs) return;  // whole groups leave together
-  const ProbDesc P = a.probs ? a.probs[g] : a.single;
+  const int grp = threadIdx.x / kGroup;
+  const ProbDesc P = a.probs ? a.probs[blockIdx.x] : a.single;
+  const int N = P.N;
   const bool rowv = lane < NX;
   const int rl = rowv ? lane : 0;
-  // each step depends on the previous one, so the next knot's rows are loaded while the
-  // current knot is processed
-  auto load_s = [&](int64_t kb, double (&Sm)[NX], double (&Sd)[NX], double (&Sp)[NX], double &r) {
-    const double *srow = a.s_ws + (kb * NX + rl) * (3 * NX);
+  // row r of the (L | D | V) slots of knot k, of U_k, and entries of the vectors
+  auto srow = [&](int k) { return a.s_ws + ((P.k0 + k) * NX + rl) * (3 * NX); };
+  auto urow = [&](int k) { return a.dinv_ws + ((P.k0 + k) * NX + rl) * NX; };
+  auto vec = [&](double *v, int k) { return v + (P.k0 + k) * NX + rl; };
+  // row r of L_k^T, i.e. column r of L_k (owned by the lanes of knot k's rows)
+  auto load_lt = [&](int k, double (&out)[NX]) {
+    const double *base = a.s_ws + (P.k0 + k) * NX * (3 * NX) + rl;
 #pragma unroll
-    for (int j = 0; j < NX; ++j) {
-      Sm[j] = rowv ? srow[j] : 0.0;
-      Sd[j] = rowv ? srow[NX + j] : 0.0;
-      Sp[j] = rowv ? srow[2 * NX + j] : 0.0;
-    }
-    r = rowv ? a.rhs_ws[kb * NX + lane] : 0.0;
+    for (int c = 0; c < NX; ++c) out[c] = rowv ? base[c * (3 * NX)] : 0.0;
   };
-
-  // forward sweep
-  double Dinv[NX], Spp[NX], yp = 0.0;
-  bool pd = true;
+  auto load_row = [&](const double *src, double (&out)[NX]) {
 #pragma unroll
-  for (int j = 0; j < NX; ++j) { Dinv[j] = 0.0; Spp[j] = 0.0; }
-  double Sm[NX], D[NX], Sp[NX], y;
-  load_s(P.k0, Sm, D, Sp, y);
-  for (int k = 0; k < P.N; ++k) {
-    const int64_t kb = P.k0 + k;
-    double nSm[NX], nSd[NX], nSp[NX], ny;
-    load_s(P.k0 + (k + 1 < P.N ? k + 1 : k), nSm, nSd, nSp, ny);
-    if (k > 0) {
-      double L[NX], T[NX];
-      mm_nn<NX, NX>(Sm, Dinv, L);  // L_k = S_{k,k-1} D_{k-1}^-1
-      mm_nn<NX, NX>(L, Spp, T);    // L_k S_{k-1,k}
-#pragma unroll
-      for (int j = 0; j < NX; ++j) D[j] -= T[j];
-      y -= row_dot<NX>(L, yp);
-    }
-    gj_inverse<NX>(D, lane, &pd);  // D_k^-1; S is SPD iff every D_k is
+    for (int c = 0; c < NX; ++c) out[c] = rowv ? src[c] : 0.0;
+  };
+  auto store_row = [&](double *dst, const double (&v)[NX]) {
     if (rowv) {
-      double *drow = a.dinv_ws + (kb * NX + lane) * NX;
 #pragma unroll
-      for (int j = 0; j < NX; ++j) drow[j] = D[j];
-      a.rhs_ws[kb * NX + lane] = y;
+      for (int c = 0; c < NX; ++c) dst[c] = v[c];
     }
-#pragma unroll
-    for (int j = 0; j < NX; ++j) { Dinv[j] = D[j]; Spp[j] = Sp[j]; }
-    yp = y;
-#pragma unroll
-    for (int j = 0; j < NX; ++j) { Sm[j] = nSm[j]; D[j] = nSd[j]; Sp[j] = nSp[j]; }
-    y = ny;
-  }
-
-  // back substitution (the rows of knot k - 1 are loaded while knot k is solved)
-  auto load_b = [&](int64_t kb, double (&Spr)[NX], double (&Dr)[NX], double &yv) {
-    const double *srow = a.s_ws + (kb * NX + rl) * (3 * NX);
-    const double *drow = a.dinv_ws + (kb * NX + rl) * NX;
-#pragma unroll
-    for (int j = 0; j < NX; ++j) {
-      Spr[j] = rowv ? srow[2 * NX + j] : 0.0;
-      Dr[j] = rowv ? drow[j] : 0.0;
-    }
-    yv = rowv ? a.rhs_ws[kb * NX + lane] : 0.0;
   };
-  double lnext = 0.0;
-  bool finite = true;
-  double Spb[NX], Dr[NX], yb;
-  load_b(P.k0 + P.N - 1, Spb, Dr, yb);
-  for (int k = P.N - 1; k >= 0; --k) {
-    const int64_t kb = P.k0 + k;
-    double nSp[NX], nDr[NX], nyb;
-    load_b(P.k0 + (k > 0 ? k - 1 : 0), nSp, nDr, nyb);
-    const double t = yb - row_dot<NX>(Spb, lnext);
-    double lam = row_dot<NX>(Dr, t);
-    if (!rowv) lam = 0.0;
-    finite = finite && (lam == lam) && !__builtin_isinf(lam);
-    if (rowv) a.lam_ws[kb * NX + lane] = lam;
-    lnext = lam;
+  auto load_v = [&](double *v, int k) { return rowv ? *vec(v, k) : 0.0; };
+
+  bool pd = true;
+  int s = 1;
+  for (; s < N; s *= 2) {
+    const int nodd = (N - s + 2 * s - 1) / (2 * s);  // j = s(2m+1) < N
+    for (int m = grp; m < nodd; m += G) {
+      const int j = s * (2 * m + 1);
+      double D[NX], T[NX], C[NX];
+      load_row(srow(j) + NX, D);
+      gj_inverse<NX>(D, lane, &pd);                        // D_j^-1
+      load_row(srow(j), T);                                // L_j (rows by lane)
+      mm_nn<NX, NX>(D, T, C);                              // V_j
+      store_row(srow(j) + NX, C);                          // (over D_j, consumed above)
+      const double z = row_dot<NX>(D, load_v(a.rhs_ws, j));
+      if (j + s < N) {
+        load_lt(j + s, T);                                 // L_{j+s}^T (rows by lane)
+        mm_nn<NX, NX>(D, T, C);                            // U_j
+        store_row(urow(j), C);
+      }
+      if (rowv) *vec(a.rhs_ws, j) = z;
+    }
+    __syncthreads();
+    const int neven = (N - 1) / (2 * s) + 1;  // i = 2sm < N
+    for (int m = grp; m < neven; m += G) {
+      const int i = 2 * s * m;
+      double D[NX], L[NX], T[NX], C[NX];
+      load_row(srow(i) + NX, D);
+      double y = load_v(a.rhs_ws, i);
+      if (i >= s) {  // left neighbour i - s
+        load_row(srow(i), L);
+        load_row(urow(i - s), T);
+        mm_nn<NX, NX>(L, T, C);                            // L_i U_{i-s}
 #pragma unroll
-    for (int j = 0; j < NX; ++j) { Spb[j] = nSp[j]; Dr[j] = nDr[j]; }
-    yb = nyb;
+        for (int c = 0; c < NX; ++c) D[c] -= C[c];
+        y -= row_dot<NX>(L, load_v(a.rhs_ws, i - s));
+        load_row(srow(i - s) + NX, T);
+        mm_nn<NX, NX>(L, T, C);                            // L_i V_{i-s}
+#pragma unroll
+        for (int c = 0; c < NX; ++c) C[c] = -C[c];
+        store_row(srow(i), C);
+      }
+      if (i + s < N) {  // right neighbour i + s
+        load_lt(i + s, L);                                 // row r of L_{i+s}^T
+        load_row(srow(i + s) + NX, T);
+        mm_nn<NX, NX>(L, T, C);                            // L_{i+s}^T V_{i+s}
+#pragma unroll
+        for (int c = 0; c < NX; ++c) D[c] -= C[c];
+        y -= row_dot<NX>(L, load_v(a.rhs_ws, i + s));
+      }
+      store_row(srow(i) + NX, D);
+      if (rowv) *vec(a.rhs_ws, i) = y;
+    }
+    __syncthreads();
   }
-  const uint64_t bad = __ballot(!finite || !pd);
-  const bool group_bad = ((bad >> (threadIdx.x & 48)) & 0xffffull) != 0;
-  if (lane == 0) {
+  if (grp == 0) {  // the last active block
+    double D[NX];
+    load_row(srow(0) + NX, D);
+    gj_inverse<NX>(D, lane, &pd);
+    const double x = row_dot<NX>(D, load_v(a.rhs_ws, 0));
+    if (rowv) *vec(a.lam_ws, 0) = x;
+  }
+  __syncthreads();
+  for (s /= 2; s >= 1; s /= 2) {
+    const int nodd = (N - s + 2 * s - 1) / (2 * s);
+    for (int m = grp; m < nodd; m += G) {
+      const int j = s * (2 * m + 1);
+      double T[NX];
+      load_row(srow(j) + NX, T);
+      double x = load_v(a.rhs_ws, j) - row_dot<NX>(T, load_v(a.lam_ws, j - s));
+      if (j + s < N) {
+        load_row(urow(j), T);
+        x -= row_dot<NX>(T, load_v(a.lam_ws, j + s));
+      }
+      if (rowv) *vec(a.lam_ws, j) = x;
+    }
+    __syncthreads();
+  }
+  // breakdown: a non-positive pivot anywhere, or a non-finite solution entry
+  bool bad = !pd;
+  for (int t = threadIdx.x; t < N * NX; t += kCrThreads) {
+    const double v = a.lam_ws[P.k0 * NX + t];
+    bad = bad || !(v == v) || __builtin_isinf(v);
+  }
+  bad = __syncthreads_or(bad);
+  if (threadIdx.x == 0) {
     mpcpcg_stats st;
     st.iters = 0;
-    st.status = group_bad ? MPCPCG_BREAKDOWN : MPCPCG_OK;
+    st.status = bad ? MPCPCG_BREAKDOWN : MPCPCG_OK;
     st.final_ratio = 0.0f;
     st.reserved = 0;
     a.stats[P.id] = st;
