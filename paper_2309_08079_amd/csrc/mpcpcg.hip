@@ -310,9 +310,10 @@ void free_schedule(Schedule *s) {
 int ensure_factor_ws(mpcpcg_ctx *c) {
   if (c->f_s) return MPCPCG_OK;
   const size_t K = (size_t)c->max_knots;
-  if (hipMalloc(&c->f_s, K * kNX * 3 * kNX * sizeof(double)) != hipSuccess ||
+  // blocks stored by columns padded to 16 rows (see fws_index)
+  if (hipMalloc(&c->f_s, K * 3 * kNX * mpc::kGroup * sizeof(double)) != hipSuccess ||
       hipMalloc(&c->f_rhs, K * kNX * sizeof(double)) != hipSuccess ||
-      hipMalloc(&c->f_dinv, K * kNX * kNX * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->f_dinv, K * kNX * mpc::kGroup * sizeof(double)) != hipSuccess ||
       hipMalloc(&c->f_lam, K * kNX * sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
     for (double **q : {&c->f_s, &c->f_rhs, &c->f_dinv, &c->f_lam})

@@ -122,7 +122,7 @@ struct KArgs {
   double *rinv_ws;       // [controls][NU][NU + NX]  R^-1 rows and (R^-1 B^T) rows
   // factorisation path: S rows [knots][NX][3 NX] and rhs [knots][NX] written by phase 1,
   // lambda [knots][NX] read by phase 2
-  double *s_ws, *rhs_ws, *lam_ws;
+  double *s_ws, *rhs_ws, *lam_ws;  // factorisation workspace (layout: fws_index)
   // options
   float eps;
   int32_t max_iter;
@@ -148,6 +148,14 @@ __device__ __forceinline__ double uni(double v) {
 // 256-VGPR budget; smaller shapes target three.
 template <int KPW>
 constexpr int waves_per_eu() { return KPW >= 32 ? 2 : 3; }
+// Factorisation workspace: element (r, c) of block t (0: S_{b,b-1}, 1: S_bb, 2: S_{b,b+1})
+// of packed knot k.  Blocks are stored by columns padded to kGroup rows, so one column is
+// one 128-byte line and the 16 lanes of a knot group (lane = row) read or write it whole.
+template <int NX>
+__device__ __forceinline__ int64_t fws_index(int64_t k, int t, int c, int r) {
+  return ((k * 3 + t) * NX + c) * kGroup + r;
+}
+
 // PHASE 0: formation, PCG and epilogue fused.  PHASE 1 (factorisation path): formation only,
 // S rows and the right-hand side written to s_ws / rhs_ws.  PHASE 2: formation, lambda
 // read from lam_ws (the block-tridiagonal solve), then the epilogue.
@@ -497,9 +505,9 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
     double Dd[NX];
     if constexpr (PHASE == 2) {
       // the epilogue needs only S_{b,b+1} (the rest of its inputs are in the workspace)
-      const double *srow = a.s_ws + (kb * NX + (rowv ? lane : 0)) * (3 * NX);
+      const double *sp = a.s_ws + fws_index<NX>(act ? kb : 0, 2, 0, lane);
 #pragma unroll
-      for (int j = 0; j < NX; ++j) { Sm[j] = 0.0; Sd[j] = 0.0; Dd[j] = 0.0; Sp[j] = (act && rowv) ? srow[2 * NX + j] : 0.0; }
+      for (int j = 0; j < NX; ++j) { Sm[j] = 0.0; Sd[j] = 0.0; Dd[j] = 0.0; Sp[j] = (act && rowv) ? sp[j * kGroup] : 0.0; }
       rhs = 0.0;
     } else {
     {
@@ -669,16 +677,15 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
     }
     if constexpr (PHASE == 1) {
       if (act) {
-        double *srow = a.s_ws + (kb * NX + (rowv ? lane : 0)) * (3 * NX);
-        if (rowv) {
+        // all 16 lanes store (rows >= NX hold zeros), so every column is one whole line
+        double *col = a.s_ws + fws_index<NX>(kb, 0, 0, lane);
 #pragma unroll
-          for (int j = 0; j < NX; ++j) {
-            srow[j] = Sm[j];
-            srow[NX + j] = Sd[j];
-            srow[2 * NX + j] = Sp[j];
-          }
-          a.rhs_ws[kb * NX + lane] = rhs;
+        for (int j = 0; j < NX; ++j) {
+          col[j * kGroup] = Sm[j];
+          col[(NX + j) * kGroup] = Sd[j];
+          col[(2 * NX + j) * kGroup] = Sp[j];
         }
+        if (rowv) a.rhs_ws[kb * NX + lane] = rhs;
       }
     }
 

@@ -11,9 +11,9 @@
 namespace mpc {
 
 struct TriArgs {
-  double *s_ws;           // [knots][NX][3 NX]: rows of S_{b,b-1}, S_bb, S_{b,b+1} (overwritten)
+  double *s_ws;           // [knots][3][NX][kGroup]: S_{b,b-1}, S_bb, S_{b,b+1} by columns (fws_index; overwritten)
   double *rhs_ws;         // [knots][NX]: right-hand side in (overwritten)
-  double *dinv_ws;        // [knots][NX][NX]: elimination workspace
+  double *dinv_ws;        // [knots][NX][kGroup]: elimination workspace, by columns
   double *lam_ws;         // [knots][NX]: the solution
   const ProbDesc *probs;  // [nprobs] longest first, or nullptr for `single`
   ProbDesc single;
@@ -36,9 +36,9 @@ struct TriArgs {
 //   x_j = z_j - V_j x_{j-s} - U_j x_{j+s}   (no U term when j + s >= N).
 // Work mapping: one workgroup per problem, one 16-lane group per block task, lane r owns
 // row r as in the other kernels; a workgroup barrier separates the sub-steps.  Storage is
-// the factorisation workspace: each knot's S row slots hold L and D (V once the knot is
-// eliminated: D_j is inverted in registers first), its third slot keeps S_{b,b+1} for the
-// primal step; dinv_ws holds U, rhs_ws holds y and then z, lam_ws the solution.  FP64
+// the factorisation workspace: each knot's first two S blocks hold L and D (V once the
+// knot is eliminated: D_j is inverted in registers first), its third keeps S_{b,b+1} for
+// the primal step; dinv_ws holds U, rhs_ws holds y and then z, lam_ws the solution.  FP64
 // throughout.
 constexpr int kCrThreads = 512;
 
@@ -51,25 +51,25 @@ __global__ void __launch_bounds__(kCrThreads) cr_solve(const TriArgs a) {
   const int N = P.N;
   const bool rowv = lane < NX;
   const int rl = rowv ? lane : 0;
-  // row r of the (L | D | V) slots of knot k, of U_k, and entries of the vectors
-  auto srow = [&](int k) { return a.s_ws + ((P.k0 + k) * NX + rl) * (3 * NX); };
-  auto urow = [&](int k) { return a.dinv_ws + ((P.k0 + k) * NX + rl) * NX; };
+  // Blocks are stored by columns (fws_index): entry (r, c) of block t of knot k at
+  // blk(k, t)[c * kGroup] for lane r, so a 16-lane group moves whole 128-byte lines.
+  // Rows >= NX are zero in every block, so all 16 lanes store.
+  auto blk = [&](int k, int t) { return a.s_ws + fws_index<NX>(P.k0 + k, t, 0, lane); };
+  auto ublk = [&](int k) { return a.dinv_ws + ((P.k0 + k) * NX) * kGroup + lane; };
   auto vec = [&](double *v, int k) { return v + (P.k0 + k) * NX + rl; };
-  // row r of L_k^T, i.e. column r of L_k (owned by the lanes of knot k's rows)
+  // row r of L_k^T, i.e. column r of L_k: one contiguous column per lane
   auto load_lt = [&](int k, double (&out)[NX]) {
-    const double *base = a.s_ws + (P.k0 + k) * NX * (3 * NX) + rl;
+    const double *col = a.s_ws + fws_index<NX>(P.k0 + k, 0, rl, 0);
 #pragma unroll
-    for (int c = 0; c < NX; ++c) out[c] = rowv ? base[c * (3 * NX)] : 0.0;
+    for (int c = 0; c < NX; ++c) out[c] = rowv ? col[c] : 0.0;
   };
   auto load_row = [&](const double *src, double (&out)[NX]) {
 #pragma unroll
-    for (int c = 0; c < NX; ++c) out[c] = rowv ? src[c] : 0.0;
+    for (int c = 0; c < NX; ++c) out[c] = rowv ? src[c * kGroup] : 0.0;
   };
   auto store_row = [&](double *dst, const double (&v)[NX]) {
-    if (rowv) {
 #pragma unroll
-      for (int c = 0; c < NX; ++c) dst[c] = v[c];
-    }
+    for (int c = 0; c < NX; ++c) dst[c * kGroup] = v[c];
   };
   auto load_v = [&](double *v, int k) { return rowv ? *vec(v, k) : 0.0; };
 
@@ -80,16 +80,16 @@ __global__ void __launch_bounds__(kCrThreads) cr_solve(const TriArgs a) {
     for (int m = grp; m < nodd; m += G) {
       const int j = s * (2 * m + 1);
       double D[NX], T[NX], C[NX];
-      load_row(srow(j) + NX, D);
+      load_row(blk(j, 1), D);
       gj_inverse<NX>(D, lane, &pd);                        // D_j^-1
-      load_row(srow(j), T);                                // L_j (rows by lane)
+      load_row(blk(j, 0), T);                              // L_j (rows by lane)
       mm_nn<NX, NX>(D, T, C);                              // V_j
-      store_row(srow(j) + NX, C);                          // (over D_j, consumed above)
+      store_row(blk(j, 1), C);                             // (over D_j, consumed above)
       const double z = row_dot<NX>(D, load_v(a.rhs_ws, j));
       if (j + s < N) {
         load_lt(j + s, T);                                 // L_{j+s}^T (rows by lane)
         mm_nn<NX, NX>(D, T, C);                            // U_j
-        store_row(urow(j), C);
+        store_row(ublk(j), C);
       }
       if (rowv) *vec(a.rhs_ws, j) = z;
     }
@@ -98,37 +98,37 @@ __global__ void __launch_bounds__(kCrThreads) cr_solve(const TriArgs a) {
     for (int m = grp; m < neven; m += G) {
       const int i = 2 * s * m;
       double D[NX], L[NX], T[NX], C[NX];
-      load_row(srow(i) + NX, D);
+      load_row(blk(i, 1), D);
       double y = load_v(a.rhs_ws, i);
       if (i >= s) {  // left neighbour i - s
-        load_row(srow(i), L);
-        load_row(urow(i - s), T);
+        load_row(blk(i, 0), L);
+        load_row(ublk(i - s), T);
         mm_nn<NX, NX>(L, T, C);                            // L_i U_{i-s}
 #pragma unroll
         for (int c = 0; c < NX; ++c) D[c] -= C[c];
         y -= row_dot<NX>(L, load_v(a.rhs_ws, i - s));
-        load_row(srow(i - s) + NX, T);
+        load_row(blk(i - s, 1), T);
         mm_nn<NX, NX>(L, T, C);                            // L_i V_{i-s}
 #pragma unroll
         for (int c = 0; c < NX; ++c) C[c] = -C[c];
-        store_row(srow(i), C);
+        store_row(blk(i, 0), C);
       }
       if (i + s < N) {  // right neighbour i + s
         load_lt(i + s, L);                                 // row r of L_{i+s}^T
-        load_row(srow(i + s) + NX, T);
+        load_row(blk(i + s, 1), T);
         mm_nn<NX, NX>(L, T, C);                            // L_{i+s}^T V_{i+s}
 #pragma unroll
         for (int c = 0; c < NX; ++c) D[c] -= C[c];
         y -= row_dot<NX>(L, load_v(a.rhs_ws, i + s));
       }
-      store_row(srow(i) + NX, D);
+      store_row(blk(i, 1), D);
       if (rowv) *vec(a.rhs_ws, i) = y;
     }
     __syncthreads();
   }
   if (grp == 0) {  // the last active block
     double D[NX];
-    load_row(srow(0) + NX, D);
+    load_row(blk(0, 1), D);
     gj_inverse<NX>(D, lane, &pd);
     const double x = row_dot<NX>(D, load_v(a.rhs_ws, 0));
     if (rowv) *vec(a.lam_ws, 0) = x;
@@ -139,10 +139,10 @@ __global__ void __launch_bounds__(kCrThreads) cr_solve(const TriArgs a) {
     for (int m = grp; m < nodd; m += G) {
       const int j = s * (2 * m + 1);
       double T[NX];
-      load_row(srow(j) + NX, T);
+      load_row(blk(j, 1), T);
       double x = load_v(a.rhs_ws, j) - row_dot<NX>(T, load_v(a.lam_ws, j - s));
       if (j + s < N) {
-        load_row(urow(j), T);
+        load_row(ublk(j), T);
         x -= row_dot<NX>(T, load_v(a.lam_ws, j + s));
       }
       if (rowv) *vec(a.lam_ws, j) = x;
