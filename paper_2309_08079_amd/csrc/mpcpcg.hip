@@ -617,8 +617,8 @@ int mpcpcg_create(mpcpcg_ctx **out, int32_t nx, int32_t nu, int64_t max_total_kn
     *out = c.release();
     return MPCPCG_OK;
   }
-  const size_t qb = sizeof(double) * K * nx * nx;
-  const size_t rb = sizeof(double) * K * nu * (nu + nx);
+  const size_t qb = sizeof(double) * K * nx * mpc::kGroup;        // Q^-1 by columns
+  const size_t rb = sizeof(double) * K * (nu + nx) * mpc::kURows;  // (R^-1 | R^-1 B^T) by columns
   const size_t tb = tws_bytes() * (size_t)c->max_tasks;
   const size_t gb = sizeof(Gang) * (size_t)max_batch;
   if (hipMalloc(&c->qinv_ws, qb) != hipSuccess || hipMalloc(&c->rinv_ws, rb) != hipSuccess ||

@@ -118,8 +118,8 @@ struct KArgs {
   void *tws;             // TaskWS<NX>[ntasks]
   Gang *gang;            // [nprobs]
   int *queue;            // [0] head, [1] workgroups finished, [2] launch generation
-  double *qinv_ws;       // [knots][NX][NX]   Q_b^-1 rows
-  double *rinv_ws;       // [controls][NU][NU + NX]  R^-1 rows and (R^-1 B^T) rows
+  double *qinv_ws;       // [knots][NX][kGroup]   Q_b^-1 by columns (row r at r)
+  double *rinv_ws;       // [controls][NU + NX][kURows]  (R^-1 | R^-1 B^T) by columns
   // factorisation path: S rows [knots][NX][3 NX] and rhs [knots][NX] written by phase 1,
   // lambda [knots][NX] read by phase 2
   double *s_ws, *rhs_ws, *lam_ws;  // factorisation workspace (layout: fws_index)
@@ -148,6 +148,9 @@ __device__ __forceinline__ double uni(double v) {
 // 256-VGPR budget; smaller shapes target three.
 template <int KPW>
 constexpr int waves_per_eu() { return KPW >= 32 ? 2 : 3; }
+// Rows of a control block as stored by columns (NU = 7 rows padded to 8: half a line).
+constexpr int kURows = 8;
+
 // Factorisation workspace: element (r, c) of block t (0: S_{b,b-1}, 1: S_bb, 2: S_{b,b+1})
 // of packed knot k.  Blocks are stored by columns padded to kGroup rows, so one column is
 // one 128-byte line and the 16 lanes of a knot group (lane = row) read or write it whole.
@@ -562,12 +565,12 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       if (hasPrev && lane < NU && rv) rprev = (double)rv[(cb - 1) * NU + lane];
       rhs -= row_dot<NU>(U, rprev);
       mm_nt<NU, NX>(Rr, Br, W);
-      if (MODE != kForm && hasPrev && lane < NU) {
-        double *w = a.rinv_ws + ((cb - 1) * NU + lane) * (NU + NX);
+      if (MODE != kForm && hasPrev && lane < kURows) {  // lane NU stores the zero pad row
+        double *w = a.rinv_ws + (cb - 1) * (NU + NX) * kURows + lane;
 #pragma unroll
-        for (int j = 0; j < NU; ++j) w[j] = Rr[j];
+        for (int j = 0; j < NU; ++j) w[j * kURows] = Rr[j];
 #pragma unroll
-        for (int j = 0; j < NX; ++j) w[NU + j] = W[j];
+        for (int j = 0; j < NX; ++j) w[(NU + j) * kURows] = W[j];
       }
     }
     {
@@ -587,10 +590,10 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
 #pragma unroll
       for (int j = 0; j < NX; ++j) Dd[j] = Qi[j];
       gj_inverse<NX>(Qi, lane);
-      if (MODE != kForm && act && rowv) {
-        double *w = a.qinv_ws + (kb * NX + lane) * NX;
+      if (MODE != kForm && act) {  // all 16 lanes: rows >= NX are zero, columns are whole lines
+        double *w = a.qinv_ws + kb * NX * kGroup + lane;
 #pragma unroll
-        for (int j = 0; j < NX; ++j) w[j] = Qi[j];
+        for (int j = 0; j < NX; ++j) w[j * kGroup] = Qi[j];
       }
 #pragma unroll
       for (int j = 0; j < NX; ++j) Sd[j] += Qi[j];
@@ -899,9 +902,9 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
 #pragma unroll
       for (int j = 0; j < NX; ++j) Qi[j] = 0.0;
       if (act && rowv) {
-        const double *w = a.qinv_ws + (kb * NX + lane) * NX;
+        const double *w = a.qinv_ws + kb * NX * kGroup + lane;
 #pragma unroll
-        for (int j = 0; j < NX; ++j) Qi[j] = w[j];
+        for (int j = 0; j < NX; ++j) Qi[j] = w[j * kGroup];
       }
       const double xrow = -row_dot<NX>(Qi, qmin) + row_dot<NX>(Sp, lp);
       double Rr[NX], W[NX];
@@ -909,11 +912,11 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       for (int j = 0; j < NX; ++j) { Rr[j] = 0.0; W[j] = 0.0; }
       double rprev = 0.0;
       if (hasPrev && lane < NU) {
-        const double *w = a.rinv_ws + ((cb - 1) * NU + lane) * (NU + NX);
+        const double *w = a.rinv_ws + (cb - 1) * (NU + NX) * kURows + lane;
 #pragma unroll
-        for (int j = 0; j < NU; ++j) Rr[j] = w[j];
+        for (int j = 0; j < NU; ++j) Rr[j] = w[j * kURows];
 #pragma unroll
-        for (int j = 0; j < NX; ++j) W[j] = w[NU + j];
+        for (int j = 0; j < NX; ++j) W[j] = w[(NU + j) * kURows];
         if (rv) rprev = (double)rv[(cb - 1) * NU + lane];
       }
       const double urow = -row_dot<NU>(Rr, rprev) - row_dot<NX>(W, lam);
