@@ -148,6 +148,10 @@ __device__ __forceinline__ double uni(double v) {
 // 256-VGPR budget; smaller shapes target three.
 template <int KPW>
 constexpr int waves_per_eu() { return KPW >= 32 ? 2 : 3; }
+// The formation-only and epilogue-only kernels of the factorisation path hold no PCG state:
+// two waves per SIMD give them the registers of the formation without spills.
+template <int KPW, int PHASE>
+constexpr int phase_waves_per_eu() { return PHASE ? 2 : waves_per_eu<KPW>(); }
 // Rows of a control block as stored by columns (NU = 7 rows padded to 8: half a line).
 constexpr int kURows = 8;
 
@@ -163,7 +167,7 @@ __device__ __forceinline__ int64_t fws_index(int64_t k, int t, int c, int r) {
 // S rows and the right-hand side written to s_ws / rhs_ws.  PHASE 2: formation, lambda
 // read from lam_ws (the block-tridiagonal solve), then the epilogue.
 template <int NX, int NU, int KPW, int MODE, int PHASE = 0>
-__global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_eu(waves_per_eu<KPW>(), waves_per_eu<KPW>())))
+__global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_eu(phase_waves_per_eu<KPW, PHASE>(), phase_waves_per_eu<KPW, PHASE>())))
     pcg_kernel(const KArgs a) {
   static_assert(NX == 14 && NU <= NX, "the fused row kernels are written for 14-row blocks");
   constexpr int NT = KPW * kGroup;
