@@ -502,7 +502,7 @@ int wide_run(mpcpcg_ctx *c, const std::vector<int64_t> &off, mpc::wide::WArgs &a
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   if (fac) {
     // factorisation path: block LDL^T sweep per problem, then wide_pcg's epilogue only
-    hipLaunchKernelGGL((mpc::wide::wide_sweep<kWNX>), dim3(w->nprobs), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((mpc::wide::wide_cr<kWNX>), dim3(w->nprobs), dim3(mpc::wide::kCrWaves * 64), 0, s, a);
     HIPCHK(c, hipGetLastError());
     a.from_ws = 1;
     hipLaunchKernelGGL((mpc::wide::wide_pcg<kWNX, kWNU>), dim3(w->nprobs), dim3(mpc::wide::kWideThreads), lds, s, a);

@@ -259,84 +259,224 @@ __global__ void __launch_bounds__(256) wide_precond(const WArgs a) {
   }
 }
 
-// ---------------------------------------------------------------- factorisation
-// Block LDL^T of the block-tridiagonal S of one problem per workgroup (the factorisation
-// path; the same recurrence as the 14-state sweep, with 28 x 28 blocks in LDS):
-//   D_0 = S_00, D_k = S_kk - S_{k,k-1} D_{k-1}^-1 S_{k-1,k}, y_k = rhs_k - S_{k,k-1} D_{k-1}^-1 y_{k-1},
-//   lambda_k = D_k^-1 (y_k - S_{k,k+1} lambda_{k+1}).
-// Reads the S blocks and rhs written by wide_form; overwrites Dinv with D_k^-1 and rhs with
-// y_k; writes lambda to lamw and the problem's stats (BREAKDOWN on a pivot <= 0 or a
-// non-finite lambda).
+// ---------------------------------------------------------------- cyclic reduction
+// Block cyclic reduction of the block-tridiagonal S of one problem per workgroup, the same
+// recurrences as the 14-state kernel (tri_kernel.h): with stride s the odd multiples j are
+// eliminated (V_j = D_j^-1 L_j, U_j = D_j^-1 L_{j+s}^T, z_j = D_j^-1 y_j), the even
+// multiples i absorb them (D_i -= L_i U_{i-s} + L_{i+s}^T V_{i+s}, y_i -= L_i z_{i-s} +
+// L_{i+s}^T z_{i+s}, L_i <- -L_i V_{i-s}), then x_0 = D_0^-1 y_0 and the levels are undone,
+// x_j = z_j - V_j x_{j-s} - U_j x_{j+s}.  The reduced systems are Schur complements of S,
+// so a pivot <= 0 means S is not positive definite (BREAKDOWN).
+// Work mapping: one wave per block task, lane r < NX owns row r.  Matrix products and the
+// Gauss-Jordan inverse read the operands from the wave's own two LDS staging blocks (the
+// row of the right operand is the same address for every lane: a broadcast read), with
+// a loop over the inner index; matrix-vector products broadcast the vector from its owner
+// lanes.  A wave only ever reads LDS it wrote itself, in program order.
+// Storage: S blocks (b,b-1), (b,b) hold L and D (V once the knot is eliminated), block
+// (b,b+1) is kept for the primal step; Dinv holds U, rhs holds y then z, lamw the solution.
+constexpr int kCrWaves = 8;
+
+__device__ __forceinline__ double lane_value(double v, int m) {  // v of lane m (m uniform)
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), m);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), m);
+  return __hiloint2double(hi, lo);
+}
+
+// order this wave's LDS accesses: its earlier writes complete before its later reads
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
 template <int NX>
-__global__ void __launch_bounds__(256) wide_sweep(const WArgs a) {
-  constexpr int NT = 256;
+struct WaveBlocks {
+  int lane;
+  bool rowv;
+  int r;  // row of this lane (clamped for lanes >= NX, whose results are never stored)
+  __device__ __forceinline__ WaveBlocks(int l) : lane(l), rowv(l < NX), r(l < NX ? l : 0) {}
+  // rows of a global block into a staging block (transposed: columns become rows)
+  __device__ __forceinline__ void rows_to(double *buf, const double *B) const {
+    if (rowv)
+#pragma unroll 4
+      for (int j = 0; j < NX; ++j) buf[r * NX + j] = B[r * NX + j];
+  }
+  __device__ __forceinline__ void cols_to(double *buf, const double *B) const {
+    if (rowv)
+#pragma unroll 4
+      for (int c = 0; c < NX; ++c) buf[r * NX + c] = B[c * NX + r];
+  }
+  __device__ __forceinline__ void regs_to(double *buf, const double (&v)[NX]) const {
+    if (rowv)
+#pragma unroll
+      for (int j = 0; j < NX; ++j) buf[r * NX + j] = v[j];
+  }
+  __device__ __forceinline__ void load(const double *B, double (&o)[NX]) const {
+#pragma unroll
+    for (int j = 0; j < NX; ++j) o[j] = rowv ? B[r * NX + j] : 0.0;
+  }
+  __device__ __forceinline__ void store(double *B, const double (&v)[NX]) const {
+    if (rowv)
+#pragma unroll
+      for (int j = 0; j < NX; ++j) B[r * NX + j] = v[j];
+  }
+  // C = X Y with X, Y staged
+  __device__ __forceinline__ void mm(const double *X, const double *Y, double (&C)[NX]) const {
+#pragma unroll
+    for (int j = 0; j < NX; ++j) C[j] = 0.0;
+#pragma unroll 1
+    for (int m = 0; m < NX; ++m) {
+      const double x = X[r * NX + m];
+      const double *y = Y + m * NX;
+#pragma unroll
+      for (int j = 0; j < NX; ++j) C[j] = __builtin_fma(x, y[j], C[j]);
+    }
+  }
+  // (X v)_r with X staged and v distributed over the lanes (lane m holds v_m)
+  __device__ __forceinline__ double mv_staged(const double *X, double v) const {
+    double acc = 0.0;
+#pragma unroll 4
+    for (int m = 0; m < NX; ++m) acc = __builtin_fma(X[r * NX + m], lane_value(v, m), acc);
+    return acc;
+  }
+  __device__ __forceinline__ double mv(const double (&X)[NX], double v) const {
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < NX; ++m) acc = __builtin_fma(X[m], lane_value(v, m), acc);
+    return acc;
+  }
+  // in-place Gauss-Jordan inverse of the SPD matrix whose rows are in `a` (and staged in
+  // buf on return); `pd` ends false on a pivot <= 0
+  __device__ __forceinline__ void gj_inverse(double (&a)[NX], double *buf, bool &pd) const {
+    regs_to(buf, a);
+    wave_lds_order();
+    for (int k = 0; k < NX; ++k) {
+      const double piv = buf[k * NX + k];
+      pd = pd && (piv > 0.0);
+      double d = __builtin_amdgcn_rcp(piv);
+      d = __builtin_fma(d, __builtin_fma(-piv, d, 1.0), d);
+      const bool me = lane == k;
+      const double f = buf[r * NX + k] * d;
+      const double *pk = buf + k * NX;
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        const double v = me ? a[j] * d : __builtin_fma(-f, pk[j], a[j]);
+        a[j] = (j == k) ? (me ? d : -f) : v;
+      }
+      wave_lds_order();  // every lane has read row k before any lane rewrites its row
+      regs_to(buf, a);
+      wave_lds_order();
+    }
+  }
+};
+
+template <int NX>
+__global__ void __launch_bounds__(kCrWaves * 64) wide_cr(const WArgs a) {
   constexpr int MM = NX * NX;
-  __shared__ double Sm[MM], D[MM], Sp[MM], Dp[MM], Spp[MM], L[MM], T[MM];
-  __shared__ double y[NX], yp[NX], lv[NX], tv[NX];
+  __shared__ __attribute__((aligned(16))) double stage[kCrWaves][2][MM];
   __shared__ int bad;
   const ProbDescW pd = a.probs[blockIdx.x];
   const int N = pd.N;
-  const int tid = threadIdx.x;
-  if (tid == 0) bad = 0;
-  for (int k = 0; k < N; ++k) {
-    const int64_t kb = pd.k0 + k;
-    __syncthreads();
-    for (int t = tid; t < MM; t += NT) {
-      Sm[t] = a.S[kb * 3 * MM + t];
-      D[t] = a.S[kb * 3 * MM + MM + t];
-      Sp[t] = a.S[kb * 3 * MM + 2 * MM + t];
-    }
-    for (int t = tid; t < NX; t += NT) y[t] = a.rhs[kb * NX + t];
-    __syncthreads();
-    if (k > 0) {
-      lds_gemm<NT>(L, Sm, false, NX, Dp, false, NX, NX, NX, NX, 1.0, false);   // S_{k,k-1} D_{k-1}^-1
-      lds_gemm<NT>(T, L, false, NX, Spp, false, NX, NX, NX, NX, 1.0, false);  // ... S_{k-1,k}
-      for (int t = tid; t < MM; t += NT) D[t] -= T[t];
-      for (int i = tid; i < NX; i += NT) {
-        double s = y[i];
-        for (int m = 0; m < NX; ++m) s = __builtin_fma(-L[i * NX + m], yp[m], s);
-        tv[i] = s;
+  const int64_t k0 = pd.k0;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const WaveBlocks<NX> W(lane);
+  double *bx = stage[w][0], *by = stage[w][1];
+  if (threadIdx.x == 0) bad = 0;
+  auto blk = [&](int k, int t) { return a.S + ((k0 + k) * 3 + t) * MM; };
+  auto ublk = [&](int k) { return a.Dinv + (k0 + k) * MM; };
+  auto vld = [&](const double *v, int k) { return W.rowv ? v[(k0 + k) * NX + lane] : 0.0; };
+  bool ok = true;
+  int s = 1;
+  for (; s < N; s *= 2) {
+    const int nodd = (N - s + 2 * s - 1) / (2 * s);  // j = s(2m+1) < N
+    for (int m = w; m < nodd; m += kCrWaves) {
+      const int j = s * (2 * m + 1);
+      double D[NX], C[NX];
+      W.load(blk(j, 1), D);
+      W.gj_inverse(D, bx, ok);                 // D_j^-1, rows in D and staged in bx
+      const double z = W.mv(D, vld(a.rhs, j));
+      W.rows_to(by, blk(j, 0));                // L_j
+      wave_lds_order();
+      W.mm(bx, by, C);                         // V_j
+      W.store(blk(j, 1), C);                   // over D_j (read above)
+      if (j + s < N) {
+        wave_lds_order();
+        W.cols_to(by, blk(j + s, 0));          // L_{j+s}^T
+        wave_lds_order();
+        W.mm(bx, by, C);                       // U_j
+        W.store(ublk(j), C);
       }
-      __syncthreads();
-      for (int i = tid; i < NX; i += NT) y[i] = tv[i];
+      if (W.rowv) a.rhs[(k0 + j) * NX + lane] = z;
     }
-    lds_gj_inverse<NT>(D, NX, NX, &bad);  // D_k^-1
     __syncthreads();
-    for (int t = tid; t < MM; t += NT) {
-      a.Dinv[kb * MM + t] = D[t];
-      Dp[t] = D[t];
-      Spp[t] = Sp[t];
+    const int neven = (N - 1) / (2 * s) + 1;  // i = 2sm < N
+    for (int m = w; m < neven; m += kCrWaves) {
+      const int i = 2 * s * m;
+      double D[NX], C[NX];
+      W.load(blk(i, 1), D);
+      double y = vld(a.rhs, i);
+      if (i >= s) {  // left neighbour i - s
+        wave_lds_order();
+        W.rows_to(bx, blk(i, 0));              // L_i
+        W.rows_to(by, ublk(i - s));            // U_{i-s}
+        wave_lds_order();
+        W.mm(bx, by, C);
+#pragma unroll
+        for (int c = 0; c < NX; ++c) D[c] -= C[c];
+        y -= W.mv_staged(bx, vld(a.rhs, i - s));
+        wave_lds_order();
+        W.rows_to(by, blk(i - s, 1));          // V_{i-s}
+        wave_lds_order();
+        W.mm(bx, by, C);
+#pragma unroll
+        for (int c = 0; c < NX; ++c) C[c] = -C[c];
+        W.store(blk(i, 0), C);                 // coupling to i - 2s
+      }
+      if (i + s < N) {  // right neighbour i + s
+        wave_lds_order();
+        W.cols_to(bx, blk(i + s, 0));          // L_{i+s}^T
+        W.rows_to(by, blk(i + s, 1));          // V_{i+s}
+        wave_lds_order();
+        W.mm(bx, by, C);
+#pragma unroll
+        for (int c = 0; c < NX; ++c) D[c] -= C[c];
+        y -= W.mv_staged(bx, vld(a.rhs, i + s));
+      }
+      W.store(blk(i, 1), D);
+      if (W.rowv) a.rhs[(k0 + i) * NX + lane] = y;
     }
-    for (int t = tid; t < NX; t += NT) {
-      a.rhs[kb * NX + t] = y[t];
-      yp[t] = y[t];
-    }
+    __syncthreads();
+  }
+  if (w == 0) {  // the last active block
+    double D[NX];
+    W.load(blk(0, 1), D);
+    W.gj_inverse(D, bx, ok);
+    const double x = W.mv(D, vld(a.rhs, 0));
+    if (W.rowv) a.lamw[k0 * NX + lane] = x;
   }
   __syncthreads();
-  for (int t = tid; t < NX; t += NT) lv[t] = 0.0;
-  bool finite = true;
-  for (int k = N - 1; k >= 0; --k) {
-    const int64_t kb = pd.k0 + k;
-    __syncthreads();
-    for (int i = tid; i < NX; i += NT) {
-      double s = a.rhs[kb * NX + i];
-      const double *sp = a.S + kb * 3 * MM + 2 * MM + i * NX;
-      for (int j = 0; j < NX; ++j) s = __builtin_fma(-sp[j], lv[j], s);
-      tv[i] = s;
+  for (s /= 2; s >= 1; s /= 2) {
+    const int nodd = (N - s + 2 * s - 1) / (2 * s);
+    for (int m = w; m < nodd; m += kCrWaves) {
+      const int j = s * (2 * m + 1);
+      double T[NX];
+      W.load(blk(j, 1), T);
+      double x = vld(a.rhs, j) - W.mv(T, vld(a.lamw, j - s));
+      if (j + s < N) {
+        W.load(ublk(j), T);
+        x -= W.mv(T, vld(a.lamw, j + s));
+      }
+      if (W.rowv) a.lamw[(k0 + j) * NX + lane] = x;
     }
     __syncthreads();
-    for (int i = tid; i < NX; i += NT) {
-      double s = 0.0;
-      const double *dr = a.Dinv + kb * MM + i * NX;
-      for (int j = 0; j < NX; ++j) s = __builtin_fma(dr[j], tv[j], s);
-      finite = finite && (s == s) && !__builtin_isinf(s);
-      a.lamw[kb * NX + i] = s;
-      lv[i] = s;
-    }
   }
-  if (!finite) bad = 1;
+  bool fin = ok;
+  for (int t = threadIdx.x; t < N * NX; t += kCrWaves * 64) {
+    const double v = a.lamw[k0 * NX + t];
+    fin = fin && (v == v) && !__builtin_isinf(v);
+  }
+  if (__syncthreads_or(!fin) && threadIdx.x == 0) bad = 1;
   __syncthreads();
-  if (tid == 0) {
+  if (threadIdx.x == 0) {
     mpcpcg_stats st;
     st.iters = 0;
     st.status = bad ? MPCPCG_BREAKDOWN : MPCPCG_OK;
@@ -345,6 +485,7 @@ __global__ void __launch_bounds__(256) wide_sweep(const WArgs a) {
     a.stats[pd.id] = st;
   }
 }
+
 
 // ---------------------------------------------------------------- PCG per problem
 constexpr int kWideThreads = 1024;
