@@ -171,9 +171,30 @@ def cpu_baseline(packed_np, off, n_sample):
     orc.backward_batch(sub, sub_off, f, 2 * f["lam"], eps=EPS, threads=threads)
     wall = time.perf_counter() - t0
     cpu = time.process_time() - c0
+    # single forward solves on one thread (the sweep's problems, seeds 2000 + N), median of 5
+    single = {}
+    for n in (32, 128, 512):
+        p = synth.problem(n, NX, NU, seed=2000 + n)
+        ts = []
+        for _ in range(5):
+            t1 = time.perf_counter()
+            orc.solve(p, eps=EPS)
+            ts.append(time.perf_counter() - t1)
+        single[str(n)] = round(float(np.median(ts)) * 1e6, 1)
     return dict(value=n_sample / wall, unit="solves/s", cores=threads, kind="oracle",
                 sample="first %d of the %d problems (N=%d), forward + adjoint, FP64 C with "
-                       "OpenMP over problems; %.1f s wall, %.1f s CPU" % (n_sample, BATCH, N_KNOTS, wall, cpu))
+                       "OpenMP over problems; %.1f s wall, %.1f s CPU" % (n_sample, BATCH, N_KNOTS, wall, cpu),
+                single_solve_us_1_thread=single, cpu_model=_cpu_model())
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def _time_ms(fn, stream, reps):

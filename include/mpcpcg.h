@@ -181,10 +181,12 @@ int mpcpcg_set_graph(mpcpcg_ctx *ctx, int32_t enable);
  *     result), final_ratio = 0.  Its cost does not depend on the conditioning of S.  At
  *     (14, 7) it needs ~6.5 KB of extra device workspace per knot of max_total_knots,
  *     allocated on first use.
- *   MPCPCG_METHOD_AUTO: per call, at (14, 7) the factorisation when a cost model of both
- *     (calibrated on ~100-iteration PCG solves) predicts it faster, which is the case when
- *     the batch needs several rounds of resident PCG workgroups; else PCG.  At (28, 14)
- *     always the factorisation, which is faster there at every measured size. */
+ *   MPCPCG_METHOD_AUTO: per call, at (14, 7) the faster of the two by a cost model
+ *     measured on MI355X, which prices PCG at ~100 iterations for cold starts and ~45 for
+ *     warm starts (opts->warm_start; the adjoint counts as cold).  On the Kuka-shaped
+ *     problems this takes the factorisation for cold solves and batches, and PCG for
+ *     warm-started single solves.  At (28, 14) always the factorisation, which is faster
+ *     there at every measured size. */
 enum { MPCPCG_METHOD_PCG = 0, MPCPCG_METHOD_FACTOR = 1, MPCPCG_METHOD_AUTO = 2 };
 int mpcpcg_set_method(mpcpcg_ctx *ctx, int32_t method);
 

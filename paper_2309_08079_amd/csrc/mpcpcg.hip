@@ -324,24 +324,29 @@ int ensure_factor_ws(mpcpcg_ctx *c) {
 }
 
 // Whether a call takes the factorisation path: always for MPCPCG_METHOD_FACTOR; for
-// MPCPCG_METHOD_AUTO by a cost model measured on MI355X (nx = 14):
-//   PCG: ~600 us per round of resident problems (768 workgroups of 16 knots, ~100
-//        iterations at ~6 us), rounds = ceil(knots / 12288);
-//   factorisation: ~208 us per round for its two parallel phases (formation, primal
-//        step), plus the cyclic reduction, one workgroup per problem: ~25 + 0.73 N us for
-//        the longest horizon alone, up to 2.7x that when every CU holds a problem.
-bool use_factor(mpcpcg_ctx *c, const std::vector<int64_t> &off) {
+// MPCPCG_METHOD_AUTO by a cost model measured on MI355X (nx = 14, microseconds):
+//   PCG: rounds of resident problems (12,288 knots each), each ~40 + iters x (3.3 + 2.0 f)
+//        with f the fraction of the device the batch fills; iters ~100 for cold starts and
+//        ~45 for warm-started receding-horizon solves;
+//   factorisation: its two parallel phases, ~25 + 138 per 12,288 knots, plus the cyclic
+//        reduction, one workgroup per problem: ~25 + 0.55 N for the longest horizon alone,
+//        up to 2.2x that when every CU holds a problem.
+// The adjoint (warm = false) is priced as a cold solve.
+bool use_factor(mpcpcg_ctx *c, const std::vector<int64_t> &off, bool warm) {
   if (c->method == MPCPCG_METHOD_PCG) return false;
   if (c->method == MPCPCG_METHOD_FACTOR) return true;
   if (c->wide) return true;  // the 28-state PCG runs one workgroup per problem: always slower
   const int64_t B = (int64_t)off.size() - 1;
-  int64_t knots = off.back(), nmax = 0;
+  int64_t nmax = 0;
   for (int64_t b = 0; b < B; ++b) nmax = std::max(nmax, off[b + 1] - off[b]);
-  const double rounds = std::ceil((double)knots / 12288.0);
-  const double t_pcg = rounds * 600.0;
-  const double load = 1.0 + 1.7 * (double)std::min<int64_t>(B, c->cus) / (double)c->cus;
-  const double t_cr = (25.0 + 0.73 * (double)nmax) * load * std::ceil((double)B / (double)c->cus);
-  const double t_fac = 208.0 * rounds + t_cr;
+  const double knots = (double)off.back(), per_round = 12288.0;
+  const double rounds = std::ceil(knots / per_round);
+  const double fill = std::min(1.0, knots / per_round);
+  const double iters = warm ? 45.0 : 100.0;
+  const double t_pcg = rounds * (40.0 + iters * (3.3 + 2.0 * fill));
+  const double load = 1.0 + 1.2 * (double)std::min<int64_t>(B, c->cus) / (double)c->cus;
+  const double t_cr = (25.0 + 0.55 * (double)nmax) * load * std::ceil((double)B / (double)c->cus);
+  const double t_fac = 25.0 + 138.0 * knots / per_round + t_cr;
   return t_fac < t_pcg;
 }
 
@@ -491,7 +496,7 @@ int wide_run(mpcpcg_ctx *c, const std::vector<int64_t> &off, mpc::wide::WArgs &a
   a.nprobs = w->nprobs;
   hipLaunchKernelGGL((mpc::wide::wide_form<kWNX, kWNU>), dim3(w->nknots), dim3(256), 0, s, a);
   HIPCHK(c, hipGetLastError());
-  const bool fac = !form_only && use_factor(c, off);
+  const bool fac = !form_only && use_factor(c, off, a.warm != 0);
   if (!fac) {
     hipLaunchKernelGGL((mpc::wide::wide_precond<kWNX, kWNU>), dim3(w->nknots), dim3(256), 0, s, a);
     HIPCHK(c, hipGetLastError());
@@ -708,7 +713,7 @@ int mpcpcg_solve(mpcpcg_ctx *c, const mpcpcg_problem *p, const mpcpcg_opts *o, f
   }
   KArgs a = base_args(c, p, o);
   a.lam = lambda; a.dx = dx; a.du = du; a.stats = stats;
-  if (use_factor(c, std::vector<int64_t>{0, p->N})) return run_factor(c, a, mpc::kForward, nullptr, p->N, s);
+  if (use_factor(c, std::vector<int64_t>{0, p->N}, o->warm_start != 0)) return run_factor(c, a, mpc::kForward, nullptr, p->N, s);
   return launch_single(c, a, p->N, single_kpw(c, p->N), mpc::kForward, s);
 }
 
@@ -727,7 +732,7 @@ int mpcpcg_solve_batched(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const
     w.lam = lambda; w.dx = dx; w.du = du; w.stats = stats;
     return wide_run(c, key, w, false, s);
   }
-  const bool fac = use_factor(c, key);
+  const bool fac = use_factor(c, key, o->warm_start != 0);
   Schedule *sc = nullptr;
   if ((st = get_schedule(c, key, fac ? 16 : pick_kpw(c, key), &sc))) return st;
   KArgs a = base_args(c, p, o);
@@ -761,7 +766,7 @@ int mpcpcg_backward(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const mpcp
     w.dgamma = dgamma; w.stats = stats;
     return wide_run(c, key, w, false, s);
   }
-  const bool fac = use_factor(c, key);
+  const bool fac = use_factor(c, key, false);  // the adjoint solve starts cold
   Schedule *sc = nullptr;
   if ((st = get_schedule(c, key, fac ? 16 : pick_kpw(c, key), &sc))) return st;
   KArgs a = base_args(c, p, o);

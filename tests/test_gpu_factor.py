@@ -111,21 +111,27 @@ def test_factor_reports_breakdown(ctx):
     assert stats(out["stats"])[0]["status"] == 2
 
 
-def test_auto_selects_by_batch_size():
+def test_auto_selects_by_cost_model():
+    # cold solves price PCG at ~100 iterations (the factorisation wins, one problem or
+    # many); a warm-started single solve at ~45 (PCG wins)
     from paper_2309_08079_amd.mpcpcg import Context
     c = Context(14, 7, max_total_knots=256 * 512, max_batch=256)
     try:
         c.mpcpcg_set_method("auto")
         one = synth.problem(512, seed=9400)
-        o1 = c.mpcpcg_solve(dev(one))
+        d1 = dev(one)
+        o1 = c.mpcpcg_solve(d1)
+        ow = c.mpcpcg_solve(d1, lam0=torch.zeros((512, 14), device="cuda"))
         probs = synth.batch([512] * 256, seed0=9401)
         packed, off = synth.pack(probs)
         ob = c.mpcpcg_solve_batched(dev(packed), off)
         torch.cuda.synchronize()
-        assert stats(o1["stats"])[0]["iters"] > 0          # one problem: PCG
-        assert (stats(ob["stats"])["iters"] == 0).all()    # several rounds: factorisation
+        assert stats(o1["stats"])[0]["iters"] == 0         # one cold problem: factorisation
+        assert stats(ow["stats"])[0]["iters"] > 0          # warm-started: PCG
+        assert (stats(ob["stats"])["iters"] == 0).all()    # many problems: factorisation
         ex = kkt.kkt_solve(probs[5])
         assert rel(ob["lam"].cpu().numpy()[5 * 512:6 * 512], ex["lam"]) < 1e-6
+        assert rel(o1["lam"].cpu().numpy(), kkt.kkt_solve(one)["lam"]) < 1e-6
     finally:
         c.close()
 
