@@ -67,6 +67,12 @@ struct WideSchedule {
   mpc::wide::KnotDesc *d_knots = nullptr;
   mpc::wide::ProbDescW *d_probs = nullptr;
   int nknots = 0, nprobs = 0, maxN = 0;
+  // block tasks of the cyclic reduction: per level (stride 1, 2, 4, ...) the eliminated
+  // blocks (also the back-substitution's) and the absorbing blocks; one root per problem
+  std::vector<int> stride, n_odd, n_even;
+  std::vector<int64_t> at_odd, at_even;  // offsets into d_tasks
+  int64_t at_root = 0;
+  mpc::wide::CrTask *d_tasks = nullptr;
 };
 
 }  // namespace
@@ -91,6 +97,7 @@ struct mpcpcg_ctx {
   bool wide = false;
   double *w_S = nullptr, *w_Dinv = nullptr, *w_rhs = nullptr, *w_Qinv = nullptr, *w_RW = nullptr;
   double *w_lam = nullptr;  // lambda of the factorisation path
+  int *w_flag = nullptr;    // per-problem breakdown flags of the factorisation path
   float *w_P = nullptr;
   std::map<std::vector<int64_t>, std::unique_ptr<WideSchedule>> wsched;
   // control step: chunk lists and the line search's per-chunk partial sums (on first use)
@@ -464,6 +471,23 @@ int wide_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, WideSchedule *
   w->nknots = (int)kd.size();
   w->nprobs = B;
   w->maxN = maxN;
+  std::vector<mpc::wide::CrTask> tasks;
+  for (int s = 1; s < maxN; s *= 2) {
+    w->stride.push_back(s);
+    w->at_odd.push_back((int64_t)tasks.size());
+    for (int b = 0; b < B; ++b)
+      for (int j = s; j < pd[b].N; j += 2 * s) tasks.push_back(mpc::wide::CrTask{b, j});
+    w->n_odd.push_back((int)((int64_t)tasks.size() - w->at_odd.back()));
+    w->at_even.push_back((int64_t)tasks.size());
+    for (int b = 0; b < B; ++b)
+      if (pd[b].N > s)
+        for (int i = 0; i < pd[b].N; i += 2 * s) tasks.push_back(mpc::wide::CrTask{b, i});
+    w->n_even.push_back((int)((int64_t)tasks.size() - w->at_even.back()));
+  }
+  w->at_root = (int64_t)tasks.size();
+  for (int b = 0; b < B; ++b) tasks.push_back(mpc::wide::CrTask{b, 0});
+  HIPCHK(c, hipMalloc(&w->d_tasks, sizeof(mpc::wide::CrTask) * tasks.size()));
+  HIPCHK(c, hipMemcpy(w->d_tasks, tasks.data(), sizeof(mpc::wide::CrTask) * tasks.size(), hipMemcpyHostToDevice));
   HIPCHK(c, hipMalloc(&w->d_knots, sizeof(mpc::wide::KnotDesc) * kd.size()));
   HIPCHK(c, hipMalloc(&w->d_probs, sizeof(mpc::wide::ProbDescW) * B));
   HIPCHK(c, hipMemcpy(w->d_knots, kd.data(), sizeof(mpc::wide::KnotDesc) * kd.size(), hipMemcpyHostToDevice));
@@ -507,7 +531,26 @@ int wide_run(mpcpcg_ctx *c, const std::vector<int64_t> &off, mpc::wide::WArgs &a
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   if (fac) {
     // factorisation path: block LDL^T sweep per problem, then wide_pcg's epilogue only
-    hipLaunchKernelGGL((mpc::wide::wide_cr<kWNX>), dim3(w->nprobs), dim3(mpc::wide::kCrWaves * 64), 0, s, a);
+    // cyclic reduction: one launch per sub-step of a level over the tasks of every problem
+    namespace mw = mpc::wide;
+    const dim3 blk(mw::kCrWaves * 64);
+    auto grid = [](int n) { return dim3((n + mw::kCrWaves - 1) / mw::kCrWaves); };
+    hipLaunchKernelGGL(mw::wide_cr_init, dim3((w->nprobs + 255) / 256), dim3(256), 0, s, c->w_flag, w->nprobs);
+    for (size_t l = 0; l < w->stride.size(); ++l) {
+      if (w->n_odd[l])
+        hipLaunchKernelGGL((mw::wide_cr_step<kWNX, mw::kCrOdd>), grid(w->n_odd[l]), blk, 0, s, a,
+                           w->d_tasks + w->at_odd[l], w->n_odd[l], w->stride[l], c->w_flag);
+      if (w->n_even[l])
+        hipLaunchKernelGGL((mw::wide_cr_step<kWNX, mw::kCrEven>), grid(w->n_even[l]), blk, 0, s, a,
+                           w->d_tasks + w->at_even[l], w->n_even[l], w->stride[l], c->w_flag);
+    }
+    hipLaunchKernelGGL((mw::wide_cr_step<kWNX, mw::kCrRoot>), grid(w->nprobs), blk, 0, s, a,
+                       w->d_tasks + w->at_root, w->nprobs, 0, c->w_flag);
+    for (size_t l = w->stride.size(); l-- > 0;)
+      if (w->n_odd[l])
+        hipLaunchKernelGGL((mw::wide_cr_step<kWNX, mw::kCrBack>), grid(w->n_odd[l]), blk, 0, s, a,
+                           w->d_tasks + w->at_odd[l], w->n_odd[l], w->stride[l], c->w_flag);
+    hipLaunchKernelGGL(mw::wide_cr_finish<kWNX>, dim3(w->nprobs), dim3(256), 0, s, a, (const int *)c->w_flag);
     HIPCHK(c, hipGetLastError());
     a.from_ws = 1;
     hipLaunchKernelGGL((mpc::wide::wide_pcg<kWNX, kWNU>), dim3(w->nprobs), dim3(mpc::wide::kWideThreads), lds, s, a);
@@ -614,6 +657,7 @@ int mpcpcg_create(mpcpcg_ctx **out, int32_t nx, int32_t nu, int64_t max_total_kn
         hipMalloc(&c->w_P, sizeof(float) * K * 3 * MM) != hipSuccess ||
         hipMalloc(&c->w_rhs, sizeof(double) * K * nx) != hipSuccess ||
         hipMalloc(&c->w_lam, sizeof(double) * K * nx) != hipSuccess ||
+        hipMalloc(&c->w_flag, sizeof(int) * (size_t)max_batch) != hipSuccess ||
         hipMalloc(&c->w_Qinv, sizeof(double) * K * MM) != hipSuccess ||
         hipMalloc(&c->w_RW, sizeof(double) * K * nu * (nu + nx)) != hipSuccess) {
       mpcpcg_destroy(c.release());
@@ -664,9 +708,10 @@ int mpcpcg_destroy(mpcpcg_ctx *c) {
   for (auto &kv : c->wsched) {
     if (kv.second->d_knots) (void)hipFree(kv.second->d_knots);
     if (kv.second->d_probs) (void)hipFree(kv.second->d_probs);
+    if (kv.second->d_tasks) (void)hipFree(kv.second->d_tasks);
   }
   for (void *p : {(void *)c->w_S, (void *)c->w_Dinv, (void *)c->w_P, (void *)c->w_rhs, (void *)c->w_lam, (void *)c->w_Qinv,
-                  (void *)c->w_RW})
+                  (void *)c->w_RW, (void *)c->w_flag})
     if (p) (void)hipFree(p);
   delete c;
   return MPCPCG_OK;

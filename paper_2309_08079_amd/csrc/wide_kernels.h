@@ -260,14 +260,16 @@ __global__ void __launch_bounds__(256) wide_precond(const WArgs a) {
 }
 
 // ---------------------------------------------------------------- cyclic reduction
-// Block cyclic reduction of the block-tridiagonal S of one problem per workgroup, the same
+// Block cyclic reduction of the block-tridiagonal S of every problem of a batch, the same
 // recurrences as the 14-state kernel (tri_kernel.h): with stride s the odd multiples j are
 // eliminated (V_j = D_j^-1 L_j, U_j = D_j^-1 L_{j+s}^T, z_j = D_j^-1 y_j), the even
 // multiples i absorb them (D_i -= L_i U_{i-s} + L_{i+s}^T V_{i+s}, y_i -= L_i z_{i-s} +
 // L_{i+s}^T z_{i+s}, L_i <- -L_i V_{i-s}), then x_0 = D_0^-1 y_0 and the levels are undone,
 // x_j = z_j - V_j x_{j-s} - U_j x_{j+s}.  The reduced systems are Schur complements of S,
 // so a pivot <= 0 means S is not positive definite (BREAKDOWN).
-// Work mapping: one wave per block task, lane r < NX owns row r.  Matrix products and the
+// Work mapping: one launch per sub-step of a level, over the block tasks of all problems
+// (so a level spreads over the whole device), one wave per task, lane r < NX owns row r;
+// the launches on one stream order the levels.  Matrix products and the
 // Gauss-Jordan inverse read the operands from the wave's own two LDS staging blocks (the
 // row of the right operand is the same address for every lane: a broadcast read), with
 // a loop over the inner index; matrix-vector products broadcast the vector from its owner
@@ -369,113 +371,122 @@ struct WaveBlocks {
   }
 };
 
-template <int NX>
-__global__ void __launch_bounds__(kCrWaves * 64) wide_cr(const WArgs a) {
+// One block task of the reduction (see the recurrences above).  The stride s is the same
+// for every problem of a launch; a problem whose horizon is <= s has no task at that level.
+struct CrTask {
+  int32_t prob;  // index into WArgs::probs
+  int32_t j;     // block of the task
+};
+
+enum CrStep { kCrOdd = 0, kCrEven = 1, kCrRoot = 2, kCrBack = 3 };
+
+// One sub-step of one level for every problem of the batch: wave w of workgroup g runs
+// task g * kCrWaves + w.  `flag` is set for a problem whose reduced blocks lose positive
+// definiteness.
+template <int NX, int STEP>
+__global__ void __launch_bounds__(kCrWaves * 64) wide_cr_step(const WArgs a, const CrTask *tasks, int ntasks,
+                                                                int s, int *flag) {
   constexpr int MM = NX * NX;
   __shared__ __attribute__((aligned(16))) double stage[kCrWaves][2][MM];
-  __shared__ int bad;
-  const ProbDescW pd = a.probs[blockIdx.x];
-  const int N = pd.N;
-  const int64_t k0 = pd.k0;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int t = blockIdx.x * kCrWaves + w;
+  if (t >= ntasks) return;  // whole waves leave; no workgroup barrier follows
+  const CrTask tk = tasks[t];
+  const ProbDescW pd = a.probs[tk.prob];
+  const int N = pd.N, j = tk.j;
+  const int64_t k0 = pd.k0;
   const WaveBlocks<NX> W(lane);
   double *bx = stage[w][0], *by = stage[w][1];
-  if (threadIdx.x == 0) bad = 0;
-  auto blk = [&](int k, int t) { return a.S + ((k0 + k) * 3 + t) * MM; };
+  auto blk = [&](int k, int t2) { return a.S + ((k0 + k) * 3 + t2) * MM; };
   auto ublk = [&](int k) { return a.Dinv + (k0 + k) * MM; };
   auto vld = [&](const double *v, int k) { return W.rowv ? v[(k0 + k) * NX + lane] : 0.0; };
   bool ok = true;
-  int s = 1;
-  for (; s < N; s *= 2) {
-    const int nodd = (N - s + 2 * s - 1) / (2 * s);  // j = s(2m+1) < N
-    for (int m = w; m < nodd; m += kCrWaves) {
-      const int j = s * (2 * m + 1);
-      double D[NX], C[NX];
-      W.load(blk(j, 1), D);
-      W.gj_inverse(D, bx, ok);                 // D_j^-1, rows in D and staged in bx
-      const double z = W.mv(D, vld(a.rhs, j));
-      W.rows_to(by, blk(j, 0));                // L_j
+  if constexpr (STEP == kCrOdd) {  // eliminate j = s(2m+1)
+    double D[NX], C[NX];
+    W.load(blk(j, 1), D);
+    W.gj_inverse(D, bx, ok);                 // D_j^-1, rows in D and staged in bx
+    const double z = W.mv(D, vld(a.rhs, j));
+    W.rows_to(by, blk(j, 0));                // L_j
+    wave_lds_order();
+    W.mm(bx, by, C);                         // V_j
+    W.store(blk(j, 1), C);                   // over D_j (read above)
+    if (j + s < N) {
       wave_lds_order();
-      W.mm(bx, by, C);                         // V_j
-      W.store(blk(j, 1), C);                   // over D_j (read above)
-      if (j + s < N) {
-        wave_lds_order();
-        W.cols_to(by, blk(j + s, 0));          // L_{j+s}^T
-        wave_lds_order();
-        W.mm(bx, by, C);                       // U_j
-        W.store(ublk(j), C);
-      }
-      if (W.rowv) a.rhs[(k0 + j) * NX + lane] = z;
+      W.cols_to(by, blk(j + s, 0));          // L_{j+s}^T
+      wave_lds_order();
+      W.mm(bx, by, C);                       // U_j
+      W.store(ublk(j), C);
     }
-    __syncthreads();
-    const int neven = (N - 1) / (2 * s) + 1;  // i = 2sm < N
-    for (int m = w; m < neven; m += kCrWaves) {
-      const int i = 2 * s * m;
-      double D[NX], C[NX];
-      W.load(blk(i, 1), D);
-      double y = vld(a.rhs, i);
-      if (i >= s) {  // left neighbour i - s
-        wave_lds_order();
-        W.rows_to(bx, blk(i, 0));              // L_i
-        W.rows_to(by, ublk(i - s));            // U_{i-s}
-        wave_lds_order();
-        W.mm(bx, by, C);
+    if (W.rowv) a.rhs[(k0 + j) * NX + lane] = z;
+  } else if constexpr (STEP == kCrEven) {  // i = 2sm absorbs i - s and i + s
+    const int i = j;
+    double D[NX], C[NX];
+    W.load(blk(i, 1), D);
+    double y = vld(a.rhs, i);
+    if (i >= s) {
+      W.rows_to(bx, blk(i, 0));              // L_i
+      W.rows_to(by, ublk(i - s));            // U_{i-s}
+      wave_lds_order();
+      W.mm(bx, by, C);
 #pragma unroll
-        for (int c = 0; c < NX; ++c) D[c] -= C[c];
-        y -= W.mv_staged(bx, vld(a.rhs, i - s));
-        wave_lds_order();
-        W.rows_to(by, blk(i - s, 1));          // V_{i-s}
-        wave_lds_order();
-        W.mm(bx, by, C);
+      for (int c = 0; c < NX; ++c) D[c] -= C[c];
+      y -= W.mv_staged(bx, vld(a.rhs, i - s));
+      wave_lds_order();
+      W.rows_to(by, blk(i - s, 1));          // V_{i-s}
+      wave_lds_order();
+      W.mm(bx, by, C);
 #pragma unroll
-        for (int c = 0; c < NX; ++c) C[c] = -C[c];
-        W.store(blk(i, 0), C);                 // coupling to i - 2s
-      }
-      if (i + s < N) {  // right neighbour i + s
-        wave_lds_order();
-        W.cols_to(bx, blk(i + s, 0));          // L_{i+s}^T
-        W.rows_to(by, blk(i + s, 1));          // V_{i+s}
-        wave_lds_order();
-        W.mm(bx, by, C);
-#pragma unroll
-        for (int c = 0; c < NX; ++c) D[c] -= C[c];
-        y -= W.mv_staged(bx, vld(a.rhs, i + s));
-      }
-      W.store(blk(i, 1), D);
-      if (W.rowv) a.rhs[(k0 + i) * NX + lane] = y;
+      for (int c = 0; c < NX; ++c) C[c] = -C[c];
+      W.store(blk(i, 0), C);                 // coupling to i - 2s
     }
-    __syncthreads();
-  }
-  if (w == 0) {  // the last active block
+    if (i + s < N) {
+      wave_lds_order();
+      W.cols_to(bx, blk(i + s, 0));          // L_{i+s}^T
+      W.rows_to(by, blk(i + s, 1));          // V_{i+s}
+      wave_lds_order();
+      W.mm(bx, by, C);
+#pragma unroll
+      for (int c = 0; c < NX; ++c) D[c] -= C[c];
+      y -= W.mv_staged(bx, vld(a.rhs, i + s));
+    }
+    W.store(blk(i, 1), D);
+    if (W.rowv) a.rhs[(k0 + i) * NX + lane] = y;
+  } else if constexpr (STEP == kCrRoot) {  // x_0 = D_0^-1 y_0
     double D[NX];
     W.load(blk(0, 1), D);
     W.gj_inverse(D, bx, ok);
     const double x = W.mv(D, vld(a.rhs, 0));
     if (W.rowv) a.lamw[k0 * NX + lane] = x;
-  }
-  __syncthreads();
-  for (s /= 2; s >= 1; s /= 2) {
-    const int nodd = (N - s + 2 * s - 1) / (2 * s);
-    for (int m = w; m < nodd; m += kCrWaves) {
-      const int j = s * (2 * m + 1);
-      double T[NX];
-      W.load(blk(j, 1), T);
-      double x = vld(a.rhs, j) - W.mv(T, vld(a.lamw, j - s));
-      if (j + s < N) {
-        W.load(ublk(j), T);
-        x -= W.mv(T, vld(a.lamw, j + s));
-      }
-      if (W.rowv) a.lamw[(k0 + j) * NX + lane] = x;
+  } else {  // x_j = z_j - V_j x_{j-s} - U_j x_{j+s}
+    double T[NX];
+    W.load(blk(j, 1), T);
+    double x = vld(a.rhs, j) - W.mv(T, vld(a.lamw, j - s));
+    if (j + s < N) {
+      W.load(ublk(j), T);
+      x -= W.mv(T, vld(a.lamw, j + s));
     }
-    __syncthreads();
+    if (W.rowv) a.lamw[(k0 + j) * NX + lane] = x;
   }
-  bool fin = ok;
-  for (int t = threadIdx.x; t < N * NX; t += kCrWaves * 64) {
-    const double v = a.lamw[k0 * NX + t];
+  if (!ok && lane == 0) flag[tk.prob] = 1;  // every writer stores the same value
+}
+
+// Clears the breakdown flags before the first level (a kernel, so the sequence can be
+// captured in a graph).
+__global__ void wide_cr_init(int *flag, int nprobs) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < nprobs) flag[p] = 0;
+}
+
+// Stats of every problem: BREAKDOWN on a non-positive pivot or a non-finite solution.
+template <int NX>
+__global__ void __launch_bounds__(256) wide_cr_finish(const WArgs a, const int *flag) {
+  const ProbDescW pd = a.probs[blockIdx.x];
+  bool fin = true;
+  for (int t = threadIdx.x; t < pd.N * NX; t += 256) {
+    const double v = a.lamw[pd.k0 * NX + t];
     fin = fin && (v == v) && !__builtin_isinf(v);
   }
-  if (__syncthreads_or(!fin) && threadIdx.x == 0) bad = 1;
-  __syncthreads();
+  const bool bad = __syncthreads_or(!fin) || flag[blockIdx.x] != 0;
   if (threadIdx.x == 0) {
     mpcpcg_stats st;
     st.iters = 0;
