@@ -518,9 +518,10 @@ int wide_run(mpcpcg_ctx *c, const std::vector<int64_t> &off, mpc::wide::WArgs &a
   a.probs = w->d_probs;
   a.nknots = w->nknots;
   a.nprobs = w->nprobs;
+  const bool fac = !form_only && use_factor(c, off, a.warm != 0);
+  a.no_dinv = fac ? 1 : 0;
   hipLaunchKernelGGL((mpc::wide::wide_form<kWNX, kWNU>), dim3(w->nknots), dim3(256), 0, s, a);
   HIPCHK(c, hipGetLastError());
-  const bool fac = !form_only && use_factor(c, off, a.warm != 0);
   if (!fac) {
     hipLaunchKernelGGL((mpc::wide::wide_precond<kWNX, kWNU>), dim3(w->nknots), dim3(256), 0, s, a);
     HIPCHK(c, hipGetLastError());

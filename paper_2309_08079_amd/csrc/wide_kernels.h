@@ -60,6 +60,7 @@ struct WArgs {
   int32_t adjoint;
   int32_t stop_abs;   // 1: eta < eps; 0: sqrt(eta / eta_ref) < eps
   int32_t from_ws;    // 1: wide_pcg skips PCG and takes lambda from lamw (factorisation path)
+  int32_t no_dinv;    // 1: wide_form skips D^-1 (only the preconditioner needs it)
   double *lamw;       // [K][NX] lambda of the factorisation path
 };
 
@@ -211,6 +212,7 @@ __global__ void __launch_bounds__(256) wide_form(const WArgs a) {
     Sb[MM + t] = Th[t];
   }
   // (5) D_b^-1 = theta^-1, D_0^-1 = Q_0
+  if (a.no_dinv) return;
   if (b == 0) {
     for (int t = tid; t < MM; t += NT) a.Dinv[kb * MM + t] = X[t];
   } else {
