@@ -143,6 +143,8 @@ def parse():
     ap.add_argument("--ingest-counters", default="", metavar="DIR",
                     help="host only: turn the rocprofv3 FETCH_SIZE / WRITE_SIZE passes under DIR into "
                          "profiles/pcg_kernel_traffic_256xN512.json and exit")
+    ap.add_argument("--only", choices=("factorisation_path", "control_step", "two_arm_batch"), default="",
+                    help="run one of the extra measurements alone and print its JSON (for profiling)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="run one plain device-to-device copy of MIB MiB and exit (hardware-counter "
                          "calibration: bytes a copy of known size reads and writes)")
@@ -483,6 +485,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": 4 * n}))
+        return
+    if args.only:
+        fn = {"factorisation_path": factor_path, "control_step": control_step, "two_arm_batch": two_arm_batch}[args.only]
+        print(json.dumps({args.only: fn(dev, torch.cuda.current_stream())}))
         return
     probs = synth.batch([N_KNOTS] * BATCH, NX, NU, seed0=SEED0)
     packed_np, off = synth.pack(probs)

@@ -334,3 +334,44 @@ def test_control_step_wide_graph_and_oracle(ctx28):
             t["X"], t["U"] = ls["X"], ls["U"]
         k0, k1 = off[b], off[b + 1]
         assert np.abs(Xg[k0:k1] - t["X"]).max() < 1e-4 * max(1.0, np.abs(t["X"]).max()), b
+
+
+def test_single_knot_batch_has_no_controls(ctx):
+    # every horizon is one knot: no controls, no dynamics; U, R, A, B, r, e are absent
+    m = synth.chain_model(7, seed=10013)
+    trajs = synth.trajectories([1, 1, 1], seed0=13200)
+    packed, off = synth.pack_trajectories(trajs)
+    dt = dev(packed)
+    assert dt["U"].numel() == 0
+    lq = ctx.mpcpcg_linearize(dmodel(m), dt, off)
+    torch.cuda.synchronize()
+    for b, t in enumerate(trajs):
+        ref = nmpc.linearize(t, m)
+        assert close32(lq["q"].cpu().numpy()[b:b + 1], ref["q"])[0]
+        assert close32(lq["x0"].cpu().numpy()[b], ref["x0"])[0]
+    dX = torch.from_numpy(np.stack([kkt.kkt_solve(nmpc.linearize(t, m))["dx"][0] for t in trajs]).astype(np.float32)).cuda()
+    res = ctx.mpcpcg_line_search(dmodel(m), dt, off, dX, None, mu=2.0)
+    torch.cuda.synchronize()
+    for b, t in enumerate(trajs):
+        ref = nmpc.line_search(t, m, dX.cpu().numpy()[b:b + 1], np.zeros((0, 7)), mu=2.0)
+        assert np.all(np.abs(res["merit"].cpu().numpy()[b] - ref["merit"]) <= TOL_M * np.abs(ref["merit"]))
+        assert int(res["choice"][b]) == ref["choice"]
+        assert np.array_equal(res["X"].cpu().numpy()[b:b + 1], ref["X"])
+
+
+def test_zero_direction_ties_keep_the_full_step(ctx):
+    # with dX = dU = 0 all nine merits are equal: the first (alpha = 1) is taken and the
+    # iterate is unchanged bit for bit
+    m = synth.chain_model(7, seed=10014)
+    trajs = synth.trajectories([40, 7], seed0=13300)
+    packed, off = synth.pack_trajectories(trajs)
+    dt = dev(packed)
+    res = ctx.mpcpcg_line_search(dmodel(m), dt, off, torch.zeros_like(dt["X"]), torch.zeros_like(dt["U"]), mu=1.0)
+    torch.cuda.synchronize()
+    merit = res["merit"].cpu().numpy()
+    assert np.all(merit == merit[:, :1])
+    assert (res["choice"].cpu().numpy() == 0).all()
+    assert torch.equal(res["X"], dt["X"]) and torch.equal(res["U"], dt["U"])
+    for b, t in enumerate(trajs):
+        ref = nmpc.merit(t["X"], t["U"], t, m, 1.0)
+        assert abs(merit[b, 0] - ref) <= TOL_M * abs(ref)
