@@ -382,9 +382,9 @@ int launch_phase(mpcpcg_ctx *c, KArgs a, int mode, int phase, Schedule *s, int N
   return MPCPCG_OK;
 }
 
-// Factorisation path: formation to the workspace (phase 1), the block LDL^T sweep of every
-// problem, then the epilogue from the swept lambda (phase 2).  s == nullptr: one problem
-// of N knots.
+// Factorisation path: formation to the workspace (phase 1), the block cyclic reduction of
+// every problem, then the epilogue from the solved lambda (phase 2).  s == nullptr: one
+// problem of N knots.
 int run_factor(mpcpcg_ctx *c, KArgs a, int mode, Schedule *s, int N, hipStream_t stream) {
   int st = ensure_factor_ws(c);
   if (st) return st;
