@@ -245,7 +245,7 @@ int mpcpcg_linearize(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
  * Outputs: merit [batch][MPCPCG_LS_STEPS] (FP64, in the order of a), choice [batch]
  * (index j of a = 2^-j), X_out [N][nx], U_out [N-batch][nu].  X_out may be X and U_out
  * may be U (in-place update); no other output may overlap an input.
- * Uses ~150 B of context workspace per 32 knots (allocated on first use).  Calls that
+ * Uses ~150 B of context workspace per 8 knots (allocated on first use).  Calls that
  * overlap on one context race on that workspace. */
 #define MPCPCG_LS_STEPS 9
 int mpcpcg_line_search(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,

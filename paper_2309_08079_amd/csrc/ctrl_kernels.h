@@ -10,8 +10,9 @@
 // Cost: J = sum_k 1/2 (x_k - xref_k)^T Q_k (x_k - xref_k) + sum_k 1/2 u_k^T R_k u_k.
 // Constraints: c = [x_0 - x_s, x_1 - f(x_0, u_0), ..., x_{N-1} - f(x_{N-2}, u_{N-2})].
 //
-// Work mapping: a batch is cut into chunks of kChunk knots of one problem; one 256-thread
-// workgroup per chunk, one thread per (knot, row) item.  There are no atomics and no
+// Work mapping: a batch is cut into chunks of up to kMaxChunk knots of one problem (the host
+// takes 8 when the batch is small, for latency, and 32 when it fills the device); one
+// 256-thread workgroup per chunk, one thread per (knot, row) item.  There are no atomics and no
 // memory clears: the line search writes per-chunk partial sums, and every chunk of a
 // problem then reduces the same partials in the same order, so all of them take the same
 // decision without synchronising.  Arithmetic is FP64 on the FP32 inputs; FP32 results
@@ -24,7 +25,7 @@
 namespace mpc {
 namespace ctrl {
 
-constexpr int kChunk = 32;    // knots per workgroup
+constexpr int kMaxChunk = 32;  // knots per workgroup: 8 for small batches, 32 for large ones
 constexpr int kThreads = 256;
 constexpr int kAlphas = 9;    // alpha = 2^-j, j = 0..8
 constexpr int kParts = 2 * kAlphas + 1;  // cost(alpha), ||c(alpha)||_1, max |lambda|
@@ -189,25 +190,28 @@ __global__ void __launch_bounds__(kThreads) merit_kernel(const CtrlArgs a) {
     }
   }
 
-  // dynamics rows: |q+ - (q + h v)| + |v+ - (v + h acc)| of joint i, knot k -> k + 1
-  for (int t = threadIdx.x; t < nkc * NQ; t += kThreads) {
-    const int lk = C.lk0 + t / NQ, i = t % NQ;
+  // dynamics rows: |q+ - (q + h v)| + |v+ - (v + h acc)| of joint i, knot k -> k + 1, one
+  // item per (step length, knot, joint): the sines dominate, so the items of a chunk are
+  // spread over all its threads.  The terms are summed per step length in item order
+  // below, the same order for every step length, so equal trial points give equal merits.
+  __shared__ double dyn[kAlphas][kMaxChunk * NQ];
+  const int ndyn = nkc * NQ;
+  for (int t = threadIdx.x; t < ndyn * kAlphas; t += kThreads) {
+    const int j = t / ndyn, rest = t % ndyn;
+    const int lk = C.lk0 + rest / NQ, i = rest % NQ;
     const int64_t kg = C.pk0 + lk, kc = cbase + lk;
     const float *x = a.X + kg * NX, *dx = a.dX + kg * NX;
     const double h = a.h, d = a.damp, kap = a.kap, g = a.grav[i];
-#pragma unroll 1
-    for (int j = 0; j < kAlphas; ++j) {
-      const double al = alpha_of(j);
-      double qa[NQ];
+    const double al = alpha_of(j);
+    double qa[NQ];
 #pragma unroll
-      for (int m = 0; m < NQ; ++m) qa[m] = (double)x[m] + al * (double)dx[m];
-      const double v = (double)x[NQ + i] + al * (double)dx[NQ + i];
-      const double u = (double)a.U[kc * NU + i] + al * (double)a.dU[kc * NU + i];
-      const double qn = (double)x[NX + i] + al * (double)dx[NX + i];
-      const double vn = (double)x[NX + NQ + i] + al * (double)dx[NX + NQ + i];
-      const double acc = chain_acc<NQ>(qa, i, v, u, g, d, kap);
-      viol[j] += fabs(qn - (qa[i] + h * v)) + fabs(vn - (v + h * acc));
-    }
+    for (int m = 0; m < NQ; ++m) qa[m] = (double)x[m] + al * (double)dx[m];
+    const double v = (double)x[NQ + i] + al * (double)dx[NQ + i];
+    const double u = (double)a.U[kc * NU + i] + al * (double)a.dU[kc * NU + i];
+    const double qn = (double)x[NX + i] + al * (double)dx[NX + i];
+    const double vn = (double)x[NX + NQ + i] + al * (double)dx[NX + NQ + i];
+    const double acc = chain_acc<NQ>(qa, i, v, u, g, d, kap);
+    dyn[j][rest] = fabs(qn - (qa[i] + h * v)) + fabs(vn - (v + h * acc));
   }
 
   // workgroup reduction in a fixed order
@@ -231,6 +235,8 @@ __global__ void __launch_bounds__(kThreads) merit_kernel(const CtrlArgs a) {
     const int j = threadIdx.x;
     double s = red[0][j];
     for (int ww = 1; ww < kThreads / 64; ++ww) s = (j == 2 * kAlphas) ? fmax(s, red[ww][j]) : s + red[ww][j];
+    if (j >= kAlphas && j < 2 * kAlphas)
+      for (int t = 0; t < ndyn; ++t) s += dyn[j - kAlphas][t];
     a.part[(int64_t)blockIdx.x * kParts + j] = s;
   }
 }
@@ -240,15 +246,27 @@ template <int NX>
 __global__ void __launch_bounds__(kThreads) ls_update_kernel(const CtrlArgs a) {
   constexpr int NQ = NX / 2, NU = NQ;
   const Chunk C = a.chunks[blockIdx.x];
+  // The problem's partials, reduced in a fixed order (the same in every chunk): member m of
+  // the group of value j sums chunks m, m + kLanes, ... in order, then the group's sums
+  // are added in member order.
+  constexpr int kLanes = kThreads / kParts;  // 13 members per value
+  __shared__ double sub[kParts][kLanes];
   __shared__ double tot[kParts];
   __shared__ int pick;
-  if (threadIdx.x < kParts) {  // the problem's chunks in order: the same sums in every chunk
-    const int j = threadIdx.x;
+  if (threadIdx.x < kParts * kLanes) {
+    const int j = threadIdx.x / kLanes, m = threadIdx.x % kLanes;
     double s = 0.0;
-    for (int c = 0; c < C.nch; ++c) {
+    for (int c = m; c < C.nch; c += kLanes) {
       const double v = a.part[(int64_t)(C.c0 + c) * kParts + j];
       s = (j == 2 * kAlphas) ? fmax(s, v) : s + v;
     }
+    sub[j][m] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < kParts) {
+    const int j = threadIdx.x;
+    double s = sub[j][0];
+    for (int m = 1; m < kLanes; ++m) s = (j == 2 * kAlphas) ? fmax(s, sub[j][m]) : s + sub[j][m];
     tot[j] = s;
   }
   __syncthreads();

@@ -566,20 +566,26 @@ int wide_run(mpcpcg_ctx *c, const std::vector<int64_t> &off, mpc::wide::WArgs &a
 
 // ---- control step (linearisation, line search) ----------------------------------------
 
-int64_t ctrl_max_chunks(const mpcpcg_ctx *c) { return c->max_knots / mpc::ctrl::kChunk + c->max_batch; }
+// Chunk length of the control-step kernels: short chunks spread a small batch over more
+// workgroups (latency); long ones keep a large batch's per-workgroup overhead low.
+constexpr int kCtrlShort = 8, kCtrlLong = mpc::ctrl::kMaxChunk;
+constexpr int64_t kCtrlLongFrom = 16384;  // knots in the batch
+
+int64_t ctrl_max_chunks(const mpcpcg_ctx *c) { return c->max_knots / kCtrlShort + c->max_batch; }
 
 int ctrl_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, CtrlSchedule **out) {
   auto it = c->csched.find(off);
   if (it != c->csched.end()) { *out = it->second.get(); return MPCPCG_OK; }
   const int B = (int)off.size() - 1;
+  const int len = off.back() >= kCtrlLongFrom ? kCtrlLong : kCtrlShort;
   std::vector<mpc::ctrl::Chunk> ch;
   for (int b = 0; b < B; ++b) {
     const int N = (int)(off[b + 1] - off[b]);
-    const int nch = (N + mpc::ctrl::kChunk - 1) / mpc::ctrl::kChunk;
+    const int nch = (N + len - 1) / len;
     const int c0 = (int)ch.size();
-    for (int k = 0; k < N; k += mpc::ctrl::kChunk) {
+    for (int k = 0; k < N; k += len) {
       mpc::ctrl::Chunk x;
-      x.pk0 = off[b]; x.b = b; x.N = N; x.lk0 = k; x.lk1 = std::min(N, k + mpc::ctrl::kChunk);
+      x.pk0 = off[b]; x.b = b; x.N = N; x.lk0 = k; x.lk1 = std::min(N, k + len);
       x.c0 = c0; x.nch = nch;
       ch.push_back(x);
     }
