@@ -124,3 +124,44 @@ def test_receding_horizon_sequence_generator():
     for t in range(T - 1):
         x = base["A"][t].astype(np.float64) @ x + 0.05 * g.standard_normal(14)
         assert np.array_equal(steps[t + 1]["x0"], x.astype(np.float32))
+
+
+C_CALLER = r"""
+#include "mpcpcg.h"
+#include <stdio.h>
+int main(void) {
+  mpcpcg_ctx *ctx = 0;
+  /* argument errors are reported before any device call */
+  int unsupported = mpcpcg_create(&ctx, 3, 1, 16, 1);
+  int einval_method = mpcpcg_set_method(0, MPCPCG_METHOD_AUTO);
+  int einval_ls = mpcpcg_line_search(0, 1, 0, 0, 0, 0, 0, 0, 0.0f, 0, 0, 0, 0, 0);
+  printf("%d %d %d %d %d %d %d %d %d\n", unsupported, einval_method, einval_ls, ctx == 0,
+         (int)sizeof(mpcpcg_problem), (int)sizeof(mpcpcg_opts), (int)sizeof(mpcpcg_stats),
+         (int)sizeof(mpcpcg_chain_model), (int)sizeof(mpcpcg_trajectory));
+  return 0;
+}
+"""
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmpcpcg.so not built")
+def test_header_is_c_and_the_library_links(tmp_path):
+    # a plain C99 caller compiles against include/mpcpcg.h, links libmpcpcg.so and sees the
+    # same struct layouts as the binding; calls with bad arguments return before any device
+    # work, so this runs without a GPU
+    import subprocess
+    from paper_2309_08079_amd import mpcpcg
+    src = tmp_path / "caller.c"
+    src.write_text(C_CALLER)
+    exe = tmp_path / "caller"
+    libdir = os.path.dirname(LIB)
+    cmd = ["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include",
+           "-D__HIP_PLATFORM_AMD__", str(src), "-L", libdir, "-lmpcpcg", "-o", str(exe)]
+    subprocess.run(cmd, check=True, capture_output=True)
+    env = dict(os.environ, LD_LIBRARY_PATH=libdir + ":/opt/rocm/lib:" + os.environ.get("LD_LIBRARY_PATH", ""))
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True, env=env).stdout.split()
+    unsupported, einval_method, einval_ls, ctx_null = (int(v) for v in out[:4])
+    assert unsupported == mpcpcg.EUNSUPPORTED and einval_method == mpcpcg.EINVAL and einval_ls == mpcpcg.EINVAL
+    assert ctx_null == 1
+    sizes = [int(v) for v in out[4:]]
+    assert sizes == [ctypes.sizeof(mpcpcg.Problem), ctypes.sizeof(mpcpcg.Opts), mpcpcg.STATS_DTYPE.itemsize,
+                     ctypes.sizeof(mpcpcg.ChainModel), ctypes.sizeof(mpcpcg.Trajectory)]
