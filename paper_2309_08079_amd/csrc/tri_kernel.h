@@ -57,21 +57,30 @@ __global__ void __launch_bounds__(kCrThreads) cr_solve(const TriArgs a) {
   auto blk = [&](int k, int t) { return a.s_ws + fws_index<NX>(P.k0 + k, t, 0, lane); };
   auto ublk = [&](int k) { return a.dinv_ws + ((P.k0 + k) * NX) * kGroup + lane; };
   auto vec = [&](double *v, int k) { return v + (P.k0 + k) * NX + rl; };
+  // Loads are unconditional (a lane past the block's rows reads an in-bounds address) and
+  // then masked, so they compile to straight-line code.
   // row r of L_k^T, i.e. column r of L_k: one contiguous column per lane
   auto load_lt = [&](int k, double (&out)[NX]) {
     const double *col = a.s_ws + fws_index<NX>(P.k0 + k, 0, rl, 0);
 #pragma unroll
-    for (int c = 0; c < NX; ++c) out[c] = rowv ? col[c] : 0.0;
+    for (int c = 0; c < NX; ++c) {
+      const double v = col[c];
+      out[c] = rowv ? v : 0.0;
+    }
   };
+  // a row of a stored block (rows >= NX are stored zeros)
   auto load_row = [&](const double *src, double (&out)[NX]) {
 #pragma unroll
-    for (int c = 0; c < NX; ++c) out[c] = rowv ? src[c * kGroup] : 0.0;
+    for (int c = 0; c < NX; ++c) out[c] = src[c * kGroup];
   };
   auto store_row = [&](double *dst, const double (&v)[NX]) {
 #pragma unroll
     for (int c = 0; c < NX; ++c) dst[c * kGroup] = v[c];
   };
-  auto load_v = [&](double *v, int k) { return rowv ? *vec(v, k) : 0.0; };
+  auto load_v = [&](double *v, int k) {
+    const double x = *vec(v, k);
+    return rowv ? x : 0.0;
+  };
 
   bool pd = true;
   int s = 1;

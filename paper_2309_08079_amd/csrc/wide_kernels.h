@@ -314,9 +314,13 @@ struct WaveBlocks {
 #pragma unroll
       for (int j = 0; j < NX; ++j) buf[r * NX + j] = v[j];
   }
+  // unconditional loads from the clamped row, then masked: straight-line code
   __device__ __forceinline__ void load(const double *B, double (&o)[NX]) const {
 #pragma unroll
-    for (int j = 0; j < NX; ++j) o[j] = rowv ? B[r * NX + j] : 0.0;
+    for (int j = 0; j < NX; ++j) {
+      const double v = B[r * NX + j];
+      o[j] = rowv ? v : 0.0;
+    }
   }
   __device__ __forceinline__ void store(double *B, const double (&v)[NX]) const {
     if (rowv)
@@ -358,13 +362,17 @@ struct WaveBlocks {
       pd = pd && (piv > 0.0);
       double d = __builtin_amdgcn_rcp(piv);
       d = __builtin_fma(d, __builtin_fma(-piv, d, 1.0), d);
+      // pivot row: a_kj d; other rows: a_ij - f a_kj (f = a_ik d); column k: d / -f.
+      // Written as c * a_kj + s * a_ij with (s, c) = (0, d) on the pivot lane and (1, -f)
+      // elsewhere, so every lane runs the same instructions.
       const bool me = lane == k;
       const double f = buf[r * NX + k] * d;
+      const double sc = me ? 0.0 : 1.0, c = me ? d : -f;
       const double *pk = buf + k * NX;
 #pragma unroll
       for (int j = 0; j < NX; ++j) {
-        const double v = me ? a[j] * d : __builtin_fma(-f, pk[j], a[j]);
-        a[j] = (j == k) ? (me ? d : -f) : v;
+        const double v = __builtin_fma(c, pk[j], sc * a[j]);
+        a[j] = (j == k) ? c : v;
       }
       wave_lds_order();  // every lane has read row k before any lane rewrites its row
       regs_to(buf, a);
@@ -401,7 +409,10 @@ __global__ void __launch_bounds__(kCrWaves * 64) wide_cr_step(const WArgs a, con
   double *bx = stage[w][0], *by = stage[w][1];
   auto blk = [&](int k, int t2) { return a.S + ((k0 + k) * 3 + t2) * MM; };
   auto ublk = [&](int k) { return a.Dinv + (k0 + k) * MM; };
-  auto vld = [&](const double *v, int k) { return W.rowv ? v[(k0 + k) * NX + lane] : 0.0; };
+  auto vld = [&](const double *v, int k) {
+    const double x = v[(k0 + k) * NX + W.r];
+    return W.rowv ? x : 0.0;
+  };
   bool ok = true;
   if constexpr (STEP == kCrOdd) {  // eliminate j = s(2m+1)
     double D[NX], C[NX];
