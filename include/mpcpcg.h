@@ -246,7 +246,8 @@ int mpcpcg_linearize(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
  * (index j of a = 2^-j), X_out [N][nx], U_out [N-batch][nu].  X_out may be X and U_out
  * may be U (in-place update); no other output may overlap an input.
  * Uses ~150 B of context workspace per 8 knots (allocated on first use).  Calls that
- * overlap on one context race on that workspace. */
+ * overlap on one context race on that workspace.  Returns OK, EINVAL (argument errors;
+ * message in mpcpcg_last_error) or EHIP. */
 #define MPCPCG_LS_STEPS 9
 int mpcpcg_line_search(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
                        const mpcpcg_chain_model *model, const mpcpcg_trajectory *traj,
@@ -270,7 +271,9 @@ int mpcpcg_line_search(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
  * replay it on `stream`: the whole step is then one graph launch.  The graph reads the
  * arrays at replay time, so new values in the same buffers need no new capture; other
  * pointers or scalars start the sequence again.  Calls that overlap on one context race
- * on the workspace. */
+ * on the workspace.  Returns OK, EINVAL (argument errors; message in mpcpcg_last_error),
+ * ENOMEM (workspace) or EHIP (a launch or the capture failed); convergence of each solve
+ * is in stats as for mpcpcg_solve_batched. */
 int mpcpcg_control_step(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
                         const mpcpcg_chain_model *model, const mpcpcg_trajectory *traj,
                         const mpcpcg_opts *opts, int32_t sqp_iters, float mu, float *lambda,
