@@ -562,7 +562,9 @@ def main():
                           "iters_forward_mean": float(it_f.mean()), "iters_adjoint_mean": float(it_b.mean())}))
         return
 
-    # one launch per solve: single problem latency and 256 sequential launches
+    # one launch per solve: single problem latency and 256 sequential launches, with the
+    # library's own workgroup shape per horizon (the pin above is for the batched step)
+    ctx.mpcpcg_set_knots_per_group(0)
     single = {"Q": d["Q"][:N_KNOTS], "q": d["q"][:N_KNOTS], "x0": d["x0"][0]}
     for k in ("R", "A", "B", "r", "e"):
         single[k] = d[k][: N_KNOTS - 1]

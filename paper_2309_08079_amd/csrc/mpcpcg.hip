@@ -207,7 +207,11 @@ KArgs base_args(mpcpcg_ctx *c, const mpcpcg_problem *p, const mpcpcg_opts *o) {
 
 int single_kpw(mpcpcg_ctx *c, int N) {
   if (c->kpw_override) return c->kpw_override;
-  return N <= 32 ? 32 : 16;   // one workgroup when it fits, else the 3-waves/SIMD shape
+  // one workgroup when it fits (no gang barrier; the smallest such shape has the cheapest
+  // workgroup barriers), else the 3-waves/SIMD shape
+  for (int k : kKpwChoices)
+    if (N <= k) return k;
+  return 16;
 }
 
 int launch_single(mpcpcg_ctx *c, KArgs &a, int N, int kpw, int mode, hipStream_t s) {
