@@ -274,7 +274,8 @@ def warm_sequences(ctx, dev, stream, T=100, N=128):
     """The paper's solve-time study: a receding-horizon sequence of T problems of N knots,
     absolute stopping rule eta' < eps for eps in {1e-4, 5e-5, 1e-5}, each step solved in
     one launch, warm-started from the previous lambda shifted by one knot or cold.  Reports
-    iterations and the distribution of per-solve device time."""
+    iterations and the distribution of per-solve device time, and the same distribution for
+    the direct factorisation of each step."""
     import torch
     from paper_2309_08079_amd import synth
     from paper_2309_08079_amd.mpcpcg import stats_to_numpy, to_device
@@ -310,6 +311,23 @@ def warm_sequences(ctx, dev, stream, T=100, N=128):
                          "us_p10": float(np.percentile(us, 10)), "us_p50": float(np.percentile(us, 50)),
                          "us_p90": float(np.percentile(us, 90)), "us_max": float(us.max())}
         res["eps_%g" % eps] = row
+    # the same sequence through the factorisation (exact, so neither eps nor the start
+    # matters): the alternative the automatic method choice weighs against warm PCG
+    ctx.mpcpcg_set_method("factor")
+    try:
+        for t in range(T):
+            o = dict(out, stats=out["stats"][t:t + 1])
+            ev[t][0].record(stream)
+            ctx.mpcpcg_solve(steps[t], eps=1e-5, out=o, stop="absolute")
+            ev[t][1].record(stream)
+        torch.cuda.synchronize()
+    finally:
+        ctx.mpcpcg_set_method("pcg")
+    us = np.array([a.elapsed_time(b) * 1e3 for a, b in ev])
+    st = stats_to_numpy(out["stats"])
+    res["factorisation"] = {"all_ok": bool((st["status"] == 0).all()),
+                            "us_p10": float(np.percentile(us, 10)), "us_p50": float(np.percentile(us, 50)),
+                            "us_p90": float(np.percentile(us, 90)), "us_max": float(us.max())}
     return res
 
 

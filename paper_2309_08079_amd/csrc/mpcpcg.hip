@@ -524,7 +524,14 @@ int wide_run(mpcpcg_ctx *c, const std::vector<int64_t> &off, mpc::wide::WArgs &a
   a.nprobs = w->nprobs;
   const bool fac = !form_only && use_factor(c, off, a.warm != 0);
   a.no_dinv = fac ? 1 : 0;
-  hipLaunchKernelGGL((mpc::wide::wide_form<kWNX, kWNU>), dim3(w->nknots), dim3(256), 0, s, a);
+  {
+    namespace mw = mpc::wide;
+    const dim3 blk(mw::kFormWaves * 64);
+    hipLaunchKernelGGL((mw::wide_form_inv<kWNX, kWNU>), dim3((2 * w->nknots + mw::kFormWaves - 1) / mw::kFormWaves),
+                       blk, 0, s, a);
+    hipLaunchKernelGGL((mw::wide_form_theta<kWNX, kWNU>), dim3((w->nknots + mw::kFormWaves - 1) / mw::kFormWaves),
+                       blk, 0, s, a);
+  }
   HIPCHK(c, hipGetLastError());
   if (!fac) {
     hipLaunchKernelGGL((mpc::wide::wide_precond<kWNX, kWNU>), dim3(w->nknots), dim3(256), 0, s, a);

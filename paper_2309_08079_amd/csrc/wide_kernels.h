@@ -3,8 +3,9 @@
 // The 14-state kernel keeps each knot's rows of S and Phi^-1 in registers, one 16-lane
 // DPP row per knot.  A 28-row block does not fit that mapping (a row of S is 84 FP64
 // values), so this path stages the blocks in a device workspace instead:
-//   wide_form    one workgroup per knot: Q^-1, R^-1, the S row blocks, gamma (or the
-//                adjoint right-hand side) and D^-1, in FP64, matrices in LDS;
+//   wide_form_inv, wide_form_theta   one wave per knot (and per control): Q^-1, R^-1, the
+//                S row blocks, gamma (or the adjoint right-hand side) and D^-1, in FP64,
+//                rows in registers;
 //   wide_precond one workgroup per knot: Phi^-1 row blocks -D_b^-1 S_{b,b+-1} D_{b+-1}^-1
 //                (FP32) once every D^-1 exists (the one cross-knot dependency);
 //   wide_pcg     one workgroup per problem: PCG (Algorithm 1) with one matrix row per
@@ -60,41 +61,11 @@ struct WArgs {
   int32_t adjoint;
   int32_t stop_abs;   // 1: eta < eps; 0: sqrt(eta / eta_ref) < eps
   int32_t from_ws;    // 1: wide_pcg skips PCG and takes lambda from lamw (factorisation path)
-  int32_t no_dinv;    // 1: wide_form skips D^-1 (only the preconditioner needs it)
+  int32_t no_dinv;    // 1: wide_form_theta skips D^-1 (only the preconditioner needs it)
   double *lamw;       // [K][NX] lambda of the factorisation path
 };
 
 // ---------------------------------------------------------------- LDS dense helpers
-// In-place Gauss-Jordan inverse of an n x n SPD matrix in LDS (row stride ld); SPD needs
-// no pivoting.  All threads of the block participate.
-// `nonpositive` (optional, shared): set to 1 when a pivot is not > 0, i.e. the matrix is not
-// positive definite.
-template <int NT>
-__device__ void lds_gj_inverse(double *a, int n, int ld, int *nonpositive = nullptr) {
-  __shared__ double piv_row[64];
-  __shared__ double col[64];
-  for (int k = 0; k < n; ++k) {
-    __syncthreads();
-    for (int t = threadIdx.x; t < n; t += NT) {
-      piv_row[t] = a[k * ld + t];
-      col[t] = a[t * ld + k];
-    }
-    __syncthreads();
-    if (nonpositive && threadIdx.x == 0 && !(piv_row[k] > 0.0)) *nonpositive = 1;
-    const double d = 1.0 / piv_row[k];
-    for (int t = threadIdx.x; t < n * n; t += NT) {
-      const int i = t / n, j = t % n;
-      double v;
-      if (i == k)
-        v = (j == k) ? d : piv_row[j] * d;
-      else
-        v = (j == k) ? -col[i] * d : a[i * ld + j] - col[i] * d * piv_row[j];
-      a[i * ld + j] = v;
-    }
-  }
-  __syncthreads();
-}
-
 // C (m x n, ld n) = op(X) (m x k) * op(Y) (k x n); tx/ty transpose the stored operands.
 template <int NT>
 __device__ void lds_gemm(double *C, const double *X, bool tx, int ldx, const double *Y, bool ty,
@@ -113,113 +84,238 @@ __device__ void lds_gemm(double *C, const double *X, bool tx, int ldx, const dou
   __syncthreads();
 }
 
-template <int NT>
-__device__ void lds_load(double *dst, const float *src, int count, bool valid) {
-  for (int t = threadIdx.x; t < count; t += NT) dst[t] = valid ? (double)src[t] : 0.0;
-}
-
-template <int NT>
-__device__ void lds_identity(double *dst, int n) {
-  for (int t = threadIdx.x; t < n * n; t += NT) dst[t] = (t / n == t % n) ? 1.0 : 0.0;
-}
-
 // ---------------------------------------------------------------- formation
-// Knot b of its problem: S row blocks (b,b-1), (b,b), (b,b+1), rhs_b and D_b^-1.
+// Two launches, one wave per task, lane r < n owning row r of an n x n block in registers.
+//   wide_form_inv    task t < K: knot t inverts Q_t (Gauss-Jordan in registers), writes
+//                    Q_t^-1 and S_{t,t+1} = -Q_t^-1 A_t^T, and its transpose as
+//                    S_{t+1,t} (S is symmetric, Section III-B); task K + t: control t of
+//                    knot t inverts R_t and writes (R_t^-1 | R_t^-1 B_t^T);
+//   wide_form_theta  knot b: theta_b = A_{b-1} Q_{b-1}^-1 A_{b-1}^T + B_{b-1} R_{b-1}^-1
+//                    B_{b-1}^T + Q_b^-1 = S_{b,b}, the right-hand side gamma_b (or the
+//                    adjoint's) and, for the preconditioner, D_b^-1 = theta_b^-1.
+// Each Q and R is inverted once (not once per neighbouring knot), and no step needs a
+// workgroup barrier.  Products take the left operand's row from the lane's registers and
+// the right operand's row from the wave's own LDS block, the same address for every lane
+// (a broadcast read).
+constexpr int kFormWaves = 4;
+
+__device__ __forceinline__ double lane_value(double v, int m) {  // v of lane m (m uniform)
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), m);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), m);
+  return __hiloint2double(hi, lo);
+}
+
+// order this wave's LDS accesses: its earlier writes complete before its later reads
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// In-place Gauss-Jordan inverse of an SPD N x N matrix (no pivoting), rows in the lanes'
+// registers: the pivot row k is read from lane k with readlane.  Lanes >= N hold zeros and
+// keep them.  `pd` ends false if a pivot is not > 0.
+template <int N>
+__device__ __forceinline__ void reg_gj_inverse(double (&a)[N], int lane, bool &pd) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    double pk[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) pk[j] = lane_value(a[j], k);
+    const double piv = pk[k];
+    pd = pd && (piv > 0.0);
+    const double d = 1.0 / piv;
+    // pivot row: a_kj d; other rows: a_ij - f a_kj (f = a_ik d); column k: d / -f,
+    // as c a_kj + s a_ij with (s, c) = (0, d) on the pivot lane and (1, -f) elsewhere
+    const bool me = lane == k;
+    const double f = a[k] * d;
+    const double sc = me ? 0.0 : 1.0, c = me ? d : -f;
+#pragma unroll
+    for (int j = 0; j < N; ++j) a[j] = (j == k) ? c : __builtin_fma(c, pk[j], sc * a[j]);
+  }
+}
+
+// acc_j += sum_{m < M} x_m Y[m][j] for j < NX (Y in LDS, rows of NX)
+template <int NX, int M>
+__device__ __forceinline__ void row_times(const double (&x)[M], const double *Y, double (&acc)[NX]) {
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const double *y = Y + m * NX;
+#pragma unroll
+    for (int j = 0; j < NX; ++j) acc[j] = __builtin_fma(x[m], y[j], acc[j]);
+  }
+}
+
 template <int NX, int NU>
-__global__ void __launch_bounds__(256) wide_form(const WArgs a) {
-  constexpr int NT = 256;
+__global__ void __launch_bounds__(kFormWaves * 64) wide_form_inv(const WArgs a) {
   constexpr int MM = NX * NX;
-  __shared__ double Qm[MM], Am[MM], T[MM], Th[MM], Qi[MM], X[MM];
-  __shared__ double Rm[NU * NU], Bm[NX * NU], U[NX * NU];
-  __shared__ double v0[NX], v1[NX], v2[NX];
-  const KnotDesc kd = a.knots[blockIdx.x];
-  const int b = kd.b, N = kd.N;
+  __shared__ __attribute__((aligned(16))) double stage[kFormWaves][MM];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int t = blockIdx.x * kFormWaves + w;
+  if (t >= 2 * a.nknots) return;  // whole waves leave; no workgroup barrier follows
+  const bool ctrl = t >= a.nknots;
+  const KnotDesc kd = a.knots[ctrl ? t - a.nknots : t];
+  const int b = kd.b;
   const int64_t kb = kd.k0 + b;
   const int64_t cb = kd.k0 - kd.id + b;  // packed control row of control b
-  const bool hasPrev = b >= 1, hasNext = b + 1 < N;
+  const bool hasNext = b + 1 < kd.N;
+  double *buf = stage[w];
+  bool pd = true;
+  if (!ctrl) {
+    const bool rowv = lane < NX;
+    const int r = rowv ? lane : 0;
+    double q[NX];
+#pragma unroll
+    for (int j = 0; j < NX; ++j) {
+      const double v = (double)a.Q[kb * MM + r * NX + j];
+      q[j] = rowv ? v : 0.0;
+    }
+    reg_gj_inverse<NX>(q, lane, pd);
+    if (rowv)
+#pragma unroll
+      for (int j = 0; j < NX; ++j) a.Qinv[kb * MM + r * NX + j] = q[j];
+    double *S = a.S + kb * 3 * MM;
+    if (b == 0 && rowv)
+#pragma unroll
+      for (int j = 0; j < NX; ++j) S[r * NX + j] = 0.0;  // no S_{0,-1}
+    double acc[NX];
+#pragma unroll
+    for (int j = 0; j < NX; ++j) acc[j] = 0.0;
+    if (hasNext) {
+      // stage A_b^T: lane j writes row j of A_b as column j
+      if (rowv)
+#pragma unroll
+        for (int m = 0; m < NX; ++m) buf[m * NX + r] = (double)a.A[cb * MM + r * NX + m];
+      wave_lds_order();
+      row_times<NX, NX>(q, buf, acc);  // (Q_b^-1 A_b^T)_r
+    }
+    if (rowv) {
+#pragma unroll
+      for (int j = 0; j < NX; ++j) S[2 * MM + r * NX + j] = -acc[j];
+      if (hasNext)
+#pragma unroll
+        for (int j = 0; j < NX; ++j) S[3 * MM + j * NX + r] = -acc[j];  // S_{b+1,b}, column r
+    }
+  } else {
+    if (!hasNext) return;
+    const bool rowv = lane < NU;
+    const int r = rowv ? lane : 0;
+    double ri[NU];
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+      const double v = (double)a.R[cb * NU * NU + r * NU + j];
+      ri[j] = rowv ? v : 0.0;
+    }
+    reg_gj_inverse<NU>(ri, lane, pd);
+    // stage B_b^T (NU rows of NX): lane j writes row j of B_b as column j
+    if (lane < NX)
+#pragma unroll
+      for (int m = 0; m < NU; ++m) buf[m * NX + lane] = (double)a.B[cb * NX * NU + lane * NU + m];
+    wave_lds_order();
+    double wr[NX];
+#pragma unroll
+    for (int j = 0; j < NX; ++j) wr[j] = 0.0;
+    row_times<NX, NU>(ri, buf, wr);  // (R_b^-1 B_b^T)_r
+    if (rowv) {
+      double *rw = a.RW + cb * NU * (NU + NX) + r * (NU + NX);
+#pragma unroll
+      for (int j = 0; j < NU; ++j) rw[j] = ri[j];
+#pragma unroll
+      for (int j = 0; j < NX; ++j) rw[NU + j] = wr[j];
+    }
+  }
+}
+
+template <int NX, int NU>
+__global__ void __launch_bounds__(kFormWaves * 64) wide_form_theta(const WArgs a) {
+  constexpr int MM = NX * NX;
+  __shared__ __attribute__((aligned(16))) double stage[kFormWaves][2][MM];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int t = blockIdx.x * kFormWaves + w;
+  if (t >= a.nknots) return;
+  const KnotDesc kd = a.knots[t];
+  const int b = kd.b;
+  const int64_t kb = kd.k0 + b;
+  const int64_t cb = kd.k0 - kd.id + b;
+  const bool hasPrev = b >= 1;
   const bool adj = a.adjoint != 0;
   const float *qv = adj ? a.gx : a.q;
   const float *rv = adj ? a.gu : a.r;
-  const int tid = threadIdx.x;
-  double *Sb = a.S + kb * 3 * MM;
-
-  // (1) previous knot: T = A_{b-1} Q_{b-1}^-1, S_{b,b-1} = -T, theta = T A^T + ...
-  if (hasPrev) {
-    lds_load<NT>(Qm, a.Q + (kb - 1) * MM, MM, true);
-    lds_load<NT>(Am, a.A + (cb - 1) * MM, MM, true);
-  } else {
-    lds_identity<NT>(Qm, NX);
-    lds_load<NT>(Am, nullptr, MM, false);
-  }
-  lds_gj_inverse<NT>(Qm, NX, NX);
-  lds_gemm<NT>(T, Am, false, NX, Qm, false, NX, NX, NX, NX, 1.0, false);
-  lds_gemm<NT>(Th, T, false, NX, Am, true, NX, NX, NX, NX, 1.0, false);
-  for (int t = tid; t < MM; t += NT) Sb[t] = -T[t];
-  for (int t = tid; t < NX; t += NT) v0[t] = (hasPrev && qv) ? (double)qv[(kb - 1) * NX + t] : 0.0;
-  __syncthreads();
-  // (2) control b-1: R^-1, U = B R^-1, theta += U B^T, W = R^-1 B^T
-  if (hasPrev) {
-    lds_load<NT>(Rm, a.R + (cb - 1) * NU * NU, NU * NU, true);
-    lds_load<NT>(Bm, a.B + (cb - 1) * NX * NU, NX * NU, true);
-  } else {
-    lds_identity<NT>(Rm, NU);
-    lds_load<NT>(Bm, nullptr, NX * NU, false);
-  }
-  for (int t = tid; t < NU; t += NT) v1[t] = (hasPrev && rv) ? (double)rv[(cb - 1) * NU + t] : 0.0;
-  lds_gj_inverse<NT>(Rm, NU, NU);
-  lds_gemm<NT>(U, Bm, false, NU, Rm, false, NU, NX, NU, NU, 1.0, false);
-  lds_gemm<NT>(Th, U, false, NU, Bm, true, NU, NX, NU, NX, 1.0, true);
-  if (hasPrev) {
-    double *rw = a.RW + (cb - 1) * NU * (NU + NX);
-    for (int t = tid; t < NU * NU; t += NT) rw[(t / NU) * (NU + NX) + t % NU] = Rm[t];
-    for (int t = tid; t < NU * NX; t += NT) {  // W = R^-1 B^T, row i, column j
-      const int i = t / NX, j = t % NX;
-      double s = 0.0;
-      for (int m = 0; m < NU; ++m) s = __builtin_fma(Rm[i * NU + m], Bm[j * NU + m], s);
-      rw[i * (NU + NX) + NU + j] = s;
+  const bool rowv = lane < NX;
+  const int r = rowv ? lane : 0;
+  double *P = stage[w][0], *W = stage[w][1];
+  double th[NX];
+  double g = 0.0;  // gamma_b, row r
+  {
+    double qi[NX];
+#pragma unroll
+    for (int j = 0; j < NX; ++j) {
+      const double v = a.Qinv[kb * MM + r * NX + j];
+      qi[j] = rowv ? v : 0.0;
+      th[j] = qi[j];
     }
+    if (qv)
+#pragma unroll
+      for (int m = 0; m < NX; ++m) g = __builtin_fma(qi[m], (double)qv[kb * NX + m], g);
   }
-  // rhs_b = -T q_{b-1} - U r_{b-1} + Q_b^-1 q_b + add
-  // (3) own knot
-  lds_load<NT>(Qi, a.Q + kb * MM, MM, true);
-  for (int t = tid; t < NX; t += NT) v2[t] = qv ? (double)qv[kb * NX + t] : 0.0;
-  __syncthreads();
-  // keep Q_b itself for D_0^-1 = Q_0
-  for (int t = tid; t < MM; t += NT) X[t] = Qi[t];
-  lds_gj_inverse<NT>(Qi, NX, NX);
-  for (int t = tid; t < MM; t += NT) {
-    a.Qinv[kb * MM + t] = Qi[t];
-    Th[t] += Qi[t];
+  if (hasPrev) {
+    // P = -S_{b-1,b} = Q_{b-1}^-1 A_{b-1}^T; W = R_{b-1}^-1 B_{b-1}^T
+    const double *Sp = a.S + ((kb - 1) * 3 + 2) * MM;
+    const double *rw = a.RW + (cb - 1) * NU * (NU + NX);
+    if (rowv) {
+#pragma unroll
+      for (int m = 0; m < NX; ++m) P[m * NX + r] = -Sp[m * NX + r];
+#pragma unroll
+      for (int m = 0; m < NU; ++m) W[m * NX + r] = rw[m * (NU + NX) + NU + r];
+    }
+    double x[NX], y[NU];
+#pragma unroll
+    for (int j = 0; j < NX; ++j) {
+      const double v = (double)a.A[(cb - 1) * MM + r * NX + j];
+      x[j] = rowv ? v : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+      const double v = (double)a.B[(cb - 1) * NX * NU + r * NU + j];
+      y[j] = rowv ? v : 0.0;
+    }
+    wave_lds_order();
+    // gamma_b -= (A Q^-1)_r q_{b-1} + (B R^-1)_r r_{b-1}; (A Q^-1)_{rm} = P_{mr},
+    // (B R^-1)_{rm} = W_{mr}
+    if (qv)
+#pragma unroll
+      for (int m = 0; m < NX; ++m) g = __builtin_fma(-P[m * NX + r], (double)qv[(kb - 1) * NX + m], g);
+    if (rv)
+#pragma unroll
+      for (int m = 0; m < NU; ++m) g = __builtin_fma(-W[m * NX + r], (double)rv[(cb - 1) * NU + m], g);
+    row_times<NX, NX>(x, P, th);  // + (A Q^-1 A^T)_r
+    row_times<NX, NU>(y, W, th);  // + (B R^-1 B^T)_r
   }
-  __syncthreads();
-  for (int i = tid; i < NX; i += NT) {
-    double s = 0.0;
-    for (int m = 0; m < NX; ++m) s -= T[i * NX + m] * v0[m];
-    for (int m = 0; m < NU; ++m) s -= U[i * NU + m] * v1[m];
-    for (int m = 0; m < NX; ++m) s += Qi[i * NX + m] * v2[m];
+  if (rowv) {
     double add;
-    if (adj) add = (double)a.gl[kb * NX + i];
-    else if (b == 0) add = (double)a.x0[(int64_t)kd.id * NX + i];
-    else add = a.e ? -(double)a.e[(cb - 1) * NX + i] : 0.0;
-    a.rhs[kb * NX + i] = s + add;
+    if (adj) add = (double)a.gl[kb * NX + r];
+    else if (b == 0) add = (double)a.x0[(int64_t)kd.id * NX + r];
+    else add = a.e ? -(double)a.e[(cb - 1) * NX + r] : 0.0;
+    a.rhs[kb * NX + r] = g + add;
+    double *S1 = a.S + (kb * 3 + 1) * MM + r * NX;
+#pragma unroll
+    for (int j = 0; j < NX; ++j) S1[j] = th[j];
   }
-  // (4) S_{b,b+1} = -Q_b^-1 A_b^T
-  if (hasNext) lds_load<NT>(Am, a.A + cb * MM, MM, true);
-  else lds_load<NT>(Am, nullptr, MM, false);
-  lds_gemm<NT>(T, Qi, false, NX, Am, true, NX, NX, NX, NX, -1.0, false);
-  for (int t = tid; t < MM; t += NT) {
-    Sb[2 * MM + t] = T[t];
-    Sb[MM + t] = Th[t];
-  }
-  // (5) D_b^-1 = theta^-1, D_0^-1 = Q_0
+  // D_b^-1 = theta_b^-1 (only the preconditioner needs it); D_0^-1 = Q_0
   if (a.no_dinv) return;
+  double *D = a.Dinv + kb * MM + r * NX;
   if (b == 0) {
-    for (int t = tid; t < MM; t += NT) a.Dinv[kb * MM + t] = X[t];
-  } else {
-    __syncthreads();
-    lds_gj_inverse<NT>(Th, NX, NX);
-    for (int t = tid; t < MM; t += NT) a.Dinv[kb * MM + t] = Th[t];
+    if (rowv)
+#pragma unroll
+      for (int j = 0; j < NX; ++j) D[j] = (double)a.Q[kb * MM + r * NX + j];
+    return;
   }
+  bool pd = true;
+  reg_gj_inverse<NX>(th, lane, pd);
+  if (rowv)
+#pragma unroll
+    for (int j = 0; j < NX; ++j) D[j] = th[j];
 }
 
 // Phi^-1 blocks of knot b (needs D^-1 of b-1, b, b+1) and optional FP32 export of S/gamma.
@@ -280,17 +376,6 @@ __global__ void __launch_bounds__(256) wide_precond(const WArgs a) {
 // (b,b+1) is kept for the primal step; Dinv holds U, rhs holds y then z, lamw the solution.
 constexpr int kCrWaves = 8;
 
-__device__ __forceinline__ double lane_value(double v, int m) {  // v of lane m (m uniform)
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), m);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), m);
-  return __hiloint2double(hi, lo);
-}
-
-// order this wave's LDS accesses: its earlier writes complete before its later reads
-__device__ __forceinline__ void wave_lds_order() {
-  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-}
 
 template <int NX>
 struct WaveBlocks {
