@@ -538,12 +538,9 @@ int wide_run(mpcpcg_ctx *c, const std::vector<int64_t> &off, mpc::wide::WArgs &a
     HIPCHK(c, hipGetLastError());
   }
   if (form_only) return MPCPCG_OK;
-  const size_t lds = wide_lds_bytes(w->maxN, c->nx, c->nu);
-  HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void *>(mpc::wide::wide_pcg<kWNX, kWNU>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   if (fac) {
-    // factorisation path: block LDL^T sweep per problem, then wide_pcg's epilogue only
-    // cyclic reduction: one launch per sub-step of a level over the tasks of every problem
+    // factorisation path: cyclic reduction, one launch per sub-step of a level over the
+    // tasks of every problem, then the primal step (or adjoint gradients) per knot
     namespace mw = mpc::wide;
     const dim3 blk(mw::kCrWaves * 64);
     auto grid = [](int n) { return dim3((n + mw::kCrWaves - 1) / mw::kCrWaves); };
@@ -564,11 +561,14 @@ int wide_run(mpcpcg_ctx *c, const std::vector<int64_t> &off, mpc::wide::WArgs &a
                            w->d_tasks + w->at_odd[l], w->n_odd[l], w->stride[l], c->w_flag);
     hipLaunchKernelGGL(mw::wide_cr_finish<kWNX>, dim3(w->nprobs), dim3(256), 0, s, a, (const int *)c->w_flag);
     HIPCHK(c, hipGetLastError());
-    a.from_ws = 1;
-    hipLaunchKernelGGL((mpc::wide::wide_pcg<kWNX, kWNU>), dim3(w->nprobs), dim3(mpc::wide::kWideThreads), lds, s, a);
+    hipLaunchKernelGGL((mw::wide_epilogue<kWNX, kWNU>), dim3((w->nknots + mw::kFormWaves - 1) / mw::kFormWaves),
+                       dim3(mw::kFormWaves * 64), 0, s, a);
     HIPCHK(c, hipGetLastError());
     return MPCPCG_OK;
   }
+  const size_t lds = wide_lds_bytes(w->maxN, c->nx, c->nu);
+  HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void *>(mpc::wide::wide_pcg<kWNX, kWNU>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL((mpc::wide::wide_pcg<kWNX, kWNU>), dim3(w->nprobs), dim3(mpc::wide::kWideThreads),
                      lds, s, a);
   HIPCHK(c, hipGetLastError());

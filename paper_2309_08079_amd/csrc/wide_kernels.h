@@ -60,7 +60,6 @@ struct WArgs {
   int32_t warm;
   int32_t adjoint;
   int32_t stop_abs;   // 1: eta < eps; 0: sqrt(eta / eta_ref) < eps
-  int32_t from_ws;    // 1: wide_pcg skips PCG and takes lambda from lamw (factorisation path)
   int32_t no_dinv;    // 1: wide_form_theta skips D^-1 (only the preconditioner needs it)
   double *lamw;       // [K][NX] lambda of the factorisation path
 };
@@ -366,12 +365,13 @@ __global__ void __launch_bounds__(256) wide_precond(const WArgs a) {
 // x_j = z_j - V_j x_{j-s} - U_j x_{j+s}.  The reduced systems are Schur complements of S,
 // so a pivot <= 0 means S is not positive definite (BREAKDOWN).
 // Work mapping: one launch per sub-step of a level, over the block tasks of all problems
-// (so a level spreads over the whole device), one wave per task, lane r < NX owns row r;
-// the launches on one stream order the levels.  Matrix products and the
-// Gauss-Jordan inverse read the operands from the wave's own two LDS staging blocks (the
-// row of the right operand is the same address for every lane: a broadcast read), with
-// a loop over the inner index; matrix-vector products broadcast the vector from its owner
-// lanes.  A wave only ever reads LDS it wrote itself, in program order.
+// (so a level spreads over the whole device), one wave per task, lane r < NX owns row r
+// in registers; the launches on one stream order the levels.  The Gauss-Jordan inverse
+// takes the pivot row from its lane with readlane; a matrix product takes the left
+// operand's row from registers and the right operand's rows from the wave's own LDS
+// staging block (the same address for every lane: a broadcast read); matrix-vector
+// products broadcast the vector from its owner lanes.  A wave only ever reads LDS it
+// wrote itself, in program order.
 // Storage: S blocks (b,b-1), (b,b) hold L and D (V once the knot is eliminated), block
 // (b,b+1) is kept for the primal step; Dinv holds U, rhs holds y then z, lamw the solution.
 constexpr int kCrWaves = 8;
@@ -383,21 +383,17 @@ struct WaveBlocks {
   bool rowv;
   int r;  // row of this lane (clamped for lanes >= NX, whose results are never stored)
   __device__ __forceinline__ WaveBlocks(int l) : lane(l), rowv(l < NX), r(l < NX ? l : 0) {}
-  // rows of a global block into a staging block (transposed: columns become rows)
-  __device__ __forceinline__ void rows_to(double *buf, const double *B) const {
+  // a global block into the staging block by rows (lane c copies column c: coalesced)
+  __device__ __forceinline__ void stage_rows(double *buf, const double *B) const {
     if (rowv)
 #pragma unroll 4
-      for (int j = 0; j < NX; ++j) buf[r * NX + j] = B[r * NX + j];
+      for (int m = 0; m < NX; ++m) buf[m * NX + r] = B[m * NX + r];
   }
-  __device__ __forceinline__ void cols_to(double *buf, const double *B) const {
+  // the transpose of a global block into the staging block (lane c writes row c as column c)
+  __device__ __forceinline__ void stage_cols(double *buf, const double *B) const {
     if (rowv)
 #pragma unroll 4
-      for (int c = 0; c < NX; ++c) buf[r * NX + c] = B[c * NX + r];
-  }
-  __device__ __forceinline__ void regs_to(double *buf, const double (&v)[NX]) const {
-    if (rowv)
-#pragma unroll
-      for (int j = 0; j < NX; ++j) buf[r * NX + j] = v[j];
+      for (int m = 0; m < NX; ++m) buf[m * NX + r] = B[r * NX + m];
   }
   // unconditional loads from the clamped row, then masked: straight-line code
   __device__ __forceinline__ void load(const double *B, double (&o)[NX]) const {
@@ -407,62 +403,40 @@ struct WaveBlocks {
       o[j] = rowv ? v : 0.0;
     }
   }
+  // row r of the transpose of a global block (column r of the block)
+  __device__ __forceinline__ void load_t(const double *B, double (&o)[NX]) const {
+#pragma unroll
+    for (int j = 0; j < NX; ++j) {
+      const double v = B[j * NX + r];
+      o[j] = rowv ? v : 0.0;
+    }
+  }
   __device__ __forceinline__ void store(double *B, const double (&v)[NX]) const {
     if (rowv)
 #pragma unroll
       for (int j = 0; j < NX; ++j) B[r * NX + j] = v[j];
   }
-  // C = X Y with X, Y staged
-  __device__ __forceinline__ void mm(const double *X, const double *Y, double (&C)[NX]) const {
+  // C = X Y, rows of X in the lanes' registers, Y staged
+  __device__ __forceinline__ void mm(const double (&X)[NX], const double *Y, double (&C)[NX]) const {
 #pragma unroll
     for (int j = 0; j < NX; ++j) C[j] = 0.0;
-#pragma unroll 1
+    row_times<NX, NX>(X, Y, C);
+  }
+  // C -= X Y
+  __device__ __forceinline__ void mm_sub(const double (&X)[NX], const double *Y, double (&C)[NX]) const {
+#pragma unroll
     for (int m = 0; m < NX; ++m) {
-      const double x = X[r * NX + m];
       const double *y = Y + m * NX;
 #pragma unroll
-      for (int j = 0; j < NX; ++j) C[j] = __builtin_fma(x, y[j], C[j]);
+      for (int j = 0; j < NX; ++j) C[j] = __builtin_fma(-X[m], y[j], C[j]);
     }
   }
-  // (X v)_r with X staged and v distributed over the lanes (lane m holds v_m)
-  __device__ __forceinline__ double mv_staged(const double *X, double v) const {
-    double acc = 0.0;
-#pragma unroll 4
-    for (int m = 0; m < NX; ++m) acc = __builtin_fma(X[r * NX + m], lane_value(v, m), acc);
-    return acc;
-  }
+  // (X v)_r with v distributed over the lanes (lane m holds v_m)
   __device__ __forceinline__ double mv(const double (&X)[NX], double v) const {
     double acc = 0.0;
 #pragma unroll
     for (int m = 0; m < NX; ++m) acc = __builtin_fma(X[m], lane_value(v, m), acc);
     return acc;
-  }
-  // in-place Gauss-Jordan inverse of the SPD matrix whose rows are in `a` (and staged in
-  // buf on return); `pd` ends false on a pivot <= 0
-  __device__ __forceinline__ void gj_inverse(double (&a)[NX], double *buf, bool &pd) const {
-    regs_to(buf, a);
-    wave_lds_order();
-    for (int k = 0; k < NX; ++k) {
-      const double piv = buf[k * NX + k];
-      pd = pd && (piv > 0.0);
-      double d = __builtin_amdgcn_rcp(piv);
-      d = __builtin_fma(d, __builtin_fma(-piv, d, 1.0), d);
-      // pivot row: a_kj d; other rows: a_ij - f a_kj (f = a_ik d); column k: d / -f.
-      // Written as c * a_kj + s * a_ij with (s, c) = (0, d) on the pivot lane and (1, -f)
-      // elsewhere, so every lane runs the same instructions.
-      const bool me = lane == k;
-      const double f = buf[r * NX + k] * d;
-      const double sc = me ? 0.0 : 1.0, c = me ? d : -f;
-      const double *pk = buf + k * NX;
-#pragma unroll
-      for (int j = 0; j < NX; ++j) {
-        const double v = __builtin_fma(c, pk[j], sc * a[j]);
-        a[j] = (j == k) ? c : v;
-      }
-      wave_lds_order();  // every lane has read row k before any lane rewrites its row
-      regs_to(buf, a);
-      wave_lds_order();
-    }
   }
 };
 
@@ -482,7 +456,7 @@ template <int NX, int STEP>
 __global__ void __launch_bounds__(kCrWaves * 64) wide_cr_step(const WArgs a, const CrTask *tasks, int ntasks,
                                                                 int s, int *flag) {
   constexpr int MM = NX * NX;
-  __shared__ __attribute__((aligned(16))) double stage[kCrWaves][2][MM];
+  __shared__ __attribute__((aligned(16))) double stage[kCrWaves][MM];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int t = blockIdx.x * kCrWaves + w;
   if (t >= ntasks) return;  // whole waves leave; no workgroup barrier follows
@@ -491,7 +465,7 @@ __global__ void __launch_bounds__(kCrWaves * 64) wide_cr_step(const WArgs a, con
   const int N = pd.N, j = tk.j;
   const int64_t k0 = pd.k0;
   const WaveBlocks<NX> W(lane);
-  double *bx = stage[w][0], *by = stage[w][1];
+  double *by = stage[w];
   auto blk = [&](int k, int t2) { return a.S + ((k0 + k) * 3 + t2) * MM; };
   auto ublk = [&](int k) { return a.Dinv + (k0 + k) * MM; };
   auto vld = [&](const double *v, int k) {
@@ -502,57 +476,56 @@ __global__ void __launch_bounds__(kCrWaves * 64) wide_cr_step(const WArgs a, con
   if constexpr (STEP == kCrOdd) {  // eliminate j = s(2m+1)
     double D[NX], C[NX];
     W.load(blk(j, 1), D);
-    W.gj_inverse(D, bx, ok);                 // D_j^-1, rows in D and staged in bx
+    reg_gj_inverse<NX>(D, lane, ok);         // D_j^-1, rows in D
     const double z = W.mv(D, vld(a.rhs, j));
-    W.rows_to(by, blk(j, 0));                // L_j
+    W.stage_rows(by, blk(j, 0));             // L_j
     wave_lds_order();
-    W.mm(bx, by, C);                         // V_j
+    W.mm(D, by, C);                          // V_j
     W.store(blk(j, 1), C);                   // over D_j (read above)
     if (j + s < N) {
       wave_lds_order();
-      W.cols_to(by, blk(j + s, 0));          // L_{j+s}^T
+      W.stage_cols(by, blk(j + s, 0));       // L_{j+s}^T
       wave_lds_order();
-      W.mm(bx, by, C);                       // U_j
+      W.mm(D, by, C);                        // U_j
       W.store(ublk(j), C);
     }
     if (W.rowv) a.rhs[(k0 + j) * NX + lane] = z;
   } else if constexpr (STEP == kCrEven) {  // i = 2sm absorbs i - s and i + s
     const int i = j;
-    double D[NX], C[NX];
-    W.load(blk(i, 1), D);
+    double D[NX], X[NX];
     double y = vld(a.rhs, i);
     if (i >= s) {
-      W.rows_to(bx, blk(i, 0));              // L_i
-      W.rows_to(by, ublk(i - s));            // U_{i-s}
+      double C[NX];
+      W.load(blk(i, 0), X);                  // L_i
+      y -= W.mv(X, vld(a.rhs, i - s));
+      W.stage_rows(by, blk(i - s, 1));       // V_{i-s}
       wave_lds_order();
-      W.mm(bx, by, C);
-#pragma unroll
-      for (int c = 0; c < NX; ++c) D[c] -= C[c];
-      y -= W.mv_staged(bx, vld(a.rhs, i - s));
-      wave_lds_order();
-      W.rows_to(by, blk(i - s, 1));          // V_{i-s}
-      wave_lds_order();
-      W.mm(bx, by, C);
+      W.mm(X, by, C);
 #pragma unroll
       for (int c = 0; c < NX; ++c) C[c] = -C[c];
-      W.store(blk(i, 0), C);                 // coupling to i - 2s
+      W.store(blk(i, 0), C);                 // coupling to i - 2s (L_i is in X)
+      wave_lds_order();
+      W.stage_rows(by, ublk(i - s));         // U_{i-s}
+      W.load(blk(i, 1), D);
+      wave_lds_order();
+      W.mm_sub(X, by, D);                    // D_i -= L_i U_{i-s}
+    } else {
+      W.load(blk(i, 1), D);
     }
     if (i + s < N) {
+      W.load_t(blk(i + s, 0), X);            // L_{i+s}^T
+      y -= W.mv(X, vld(a.rhs, i + s));
       wave_lds_order();
-      W.cols_to(bx, blk(i + s, 0));          // L_{i+s}^T
-      W.rows_to(by, blk(i + s, 1));          // V_{i+s}
+      W.stage_rows(by, blk(i + s, 1));       // V_{i+s}
       wave_lds_order();
-      W.mm(bx, by, C);
-#pragma unroll
-      for (int c = 0; c < NX; ++c) D[c] -= C[c];
-      y -= W.mv_staged(bx, vld(a.rhs, i + s));
+      W.mm_sub(X, by, D);                    // D_i -= L_{i+s}^T V_{i+s}
     }
     W.store(blk(i, 1), D);
     if (W.rowv) a.rhs[(k0 + i) * NX + lane] = y;
   } else if constexpr (STEP == kCrRoot) {  // x_0 = D_0^-1 y_0
     double D[NX];
     W.load(blk(0, 1), D);
-    W.gj_inverse(D, bx, ok);
+    reg_gj_inverse<NX>(D, lane, ok);
     const double x = W.mv(D, vld(a.rhs, 0));
     if (W.rowv) a.lamw[k0 * NX + lane] = x;
   } else {  // x_j = z_j - V_j x_{j-s} - U_j x_{j+s}
@@ -595,6 +568,103 @@ __global__ void __launch_bounds__(256) wide_cr_finish(const WArgs a, const int *
   }
 }
 
+
+// ---------------------------------------------------------------- factorisation epilogue
+// The primal step of every knot from the multipliers lamw (dZ = -G^-1 (g - C^T lambda)),
+// or in adjoint mode nu_1 and the block-sparse gradients (the same expressions as the
+// PCG kernel's epilogue).  One wave per knot b; lane r < NX owns row r of the knot's
+// state block and lane r < NU row r of control b, which couples to lambda_{b+1}:
+//   x_b = -Q_b^-1 (q_b - lambda_b) + S_{b,b+1} lambda_{b+1}
+//   u_b = -R_b^-1 r_b - (R_b^-1 B_b^T) lambda_{b+1}
+template <int NX, int NU>
+__global__ void __launch_bounds__(kFormWaves * 64) wide_epilogue(const WArgs a) {
+  constexpr int MM = NX * NX;
+  __shared__ double vx[kFormWaves][NX], vu[kFormWaves][NU];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int t = blockIdx.x * kFormWaves + w;
+  if (t >= a.nknots) return;  // whole waves leave; no workgroup barrier follows
+  const KnotDesc kd = a.knots[t];
+  const int b = kd.b;
+  const int64_t kb = kd.k0 + b;
+  const int64_t cb = kd.k0 - kd.id + b;  // control b
+  const bool hasNext = b + 1 < kd.N;
+  const bool adj = a.adjoint != 0;
+  const float *qv = adj ? a.gx : a.q;
+  const float *rv = adj ? a.gu : a.r;
+  const double *lam = a.lamw;  // lambda, or mu in adjoint mode
+  const bool rowv = lane < NX, urow = lane < NU && hasNext;
+  const int r = rowv ? lane : 0, ru = lane < NU ? lane : 0;
+  double x = 0.0, u = 0.0;
+  {
+    const double *Qi = a.Qinv + kb * MM + r * NX;
+    const double *Sp = a.S + (kb * 3 + 2) * MM + r * NX;
+#pragma unroll 4
+    for (int j = 0; j < NX; ++j) {
+      const double qj = qv ? (double)qv[kb * NX + j] : 0.0;
+      const double ln = hasNext ? lam[(kb + 1) * NX + j] : 0.0;
+      x = __builtin_fma(-Qi[j], qj - lam[kb * NX + j], x);
+      x = __builtin_fma(Sp[j], ln, x);
+    }
+  }
+  if (hasNext) {
+    const double *rw = a.RW + cb * NU * (NU + NX) + ru * (NU + NX);
+#pragma unroll
+    for (int m = 0; m < NU; ++m) u -= rw[m] * (rv ? (double)rv[cb * NU + m] : 0.0);
+#pragma unroll 4
+    for (int j = 0; j < NX; ++j) u -= rw[NU + j] * lam[(kb + 1) * NX + j];
+  }
+  const double mu = rowv ? lam[kb * NX + r] : 0.0;
+  if (!adj) {
+    if (rowv) {
+      a.lam[kb * NX + r] = (float)mu;
+      a.dx[kb * NX + r] = (float)x;
+    }
+    if (urow) a.du[cb * NU + lane] = (float)u;
+    return;
+  }
+  // adjoint: lam holds mu, x = nu_1 of the state rows, u = nu_1 of the control rows
+  if (rowv) {
+    if (a.dgamma) a.dgamma[kb * NX + r] = (float)mu;
+    a.dq[kb * NX + r] = (float)x;
+    if (b == 0) a.dx0[(int64_t)kd.id * NX + r] = (float)mu;
+    if (b >= 1 && a.de) a.de[(cb - 1) * NX + r] = (float)(-mu);
+    vx[w][r] = x;
+  }
+  if (urow) {
+    a.dr[cb * NU + lane] = (float)u;
+    vu[w][lane] = u;
+  }
+  wave_lds_order();
+  // dQ_b = sym(nu1x_b dx_b^T)
+  const float *dxb = a.dx_in + kb * NX;
+  for (int o = lane; o < MM; o += 64) {
+    const int i = o / NX, j = o % NX;
+    const double nx_i = vx[w][i], nx_j = vx[w][j];
+    const double dx_i = (double)dxb[i], dx_j = (double)dxb[j];
+    a.dQ[kb * MM + o] = (float)(0.5 * (nx_i * dx_j + nx_j * dx_i));
+  }
+  if (!hasNext) return;
+  // control b of block row b + 1: dA_b = lambda_{b+1} nu1x_b^T + mu_{b+1} dx_b^T,
+  // dB_b = lambda_{b+1} nu1u_b^T + mu_{b+1} du_b^T, dR_b = sym(nu1u_b du_b^T)
+  const float *lin = a.lam_in + (kb + 1) * NX;
+  const double *mun = lam + (kb + 1) * NX;
+  const float *dub = a.du_in + cb * NU;
+  for (int o = lane; o < MM; o += 64) {
+    const int i = o / NX, j = o % NX;
+    a.dA[cb * MM + o] = (float)((double)lin[i] * vx[w][j] + mun[i] * (double)dxb[j]);
+  }
+  for (int o = lane; o < NX * NU; o += 64) {
+    const int i = o / NU, j = o % NU;
+    a.dB[cb * NX * NU + o] = (float)((double)lin[i] * vu[w][j] + mun[i] * (double)dub[j]);
+  }
+  for (int o = lane; o < NU * NU; o += 64) {
+    const int i = o / NU, j = o % NU;
+    const double ni = vu[w][i], nj = vu[w][j];
+    const double di = (double)dub[i], dj = (double)dub[j];
+    a.dR[cb * NU * NU + o] = (float)(0.5 * (ni * dj + nj * di));
+  }
+}
 
 // ---------------------------------------------------------------- PCG per problem
 constexpr int kWideThreads = 1024;
@@ -682,13 +752,7 @@ __global__ void __launch_bounds__(kWideThreads) wide_pcg(const WArgs a) {
 
   int status = MPCPCG_OK, it = 0;
   double eta_ref = 0.0, eta_new = 0.0;
-  if (a.from_ws) {
-#pragma unroll
-    for (int s = 0; s < kWideRows; ++s) {
-      const int g = tid + s * kWideThreads;
-      lam[s] = g < rows ? a.lamw[k0 * NX + g] : 0.0;
-    }
-  } else {
+  {
   // eta_ref = rhs^T Phi^-1 rhs; r = rhs - S lambda_0
   put_f(g0);
   put_d(lam);
@@ -765,7 +829,7 @@ __global__ void __launch_bounds__(kWideThreads) wide_pcg(const WArgs a) {
     }
     if (it > max_iter) it = max_iter;
   }
-  }  // PCG (not the factorisation path)
+  }
 
   // ---------------------------------------------------------------- epilogue
   // x rows: dZx_b = -Q_b^-1 (q_b - lambda_b) + S_{b,b+1} lambda_{b+1};
@@ -871,7 +935,7 @@ __global__ void __launch_bounds__(kWideThreads) wide_pcg(const WArgs a) {
       a.dR[(c0 + c) * NU * NU + i * NU + j] = (float)(0.5 * (ni * dj + nj * di));
     }
   }
-  if (tid == 0 && !a.from_ws) {
+  if (tid == 0) {
     mpcpcg_stats st;
     st.iters = it;
     st.status = status;

@@ -186,17 +186,23 @@ def test_wide_factor_two_arm_batch_forward_and_adjoint(ctx28):
     gl = 2 * fwd["lam"]
     g = ctx28.mpcpcg_backward(d, off, fwd, gl)
     torch.cuda.synchronize()
-    lam = fwd["lam"].cpu().numpy()
+    fn = {k: fwd[k].cpu().numpy() for k in ("lam", "dx", "du")}
     gln = gl.cpu().numpy().astype(np.float64)
-    dQ, dA = g["dQ"].cpu().numpy(), g["dA"].cpu().numpy()
+    gn = {k: g[k].cpu().numpy() for k in ("dQ", "dR", "dA", "dB", "dq", "dr", "dx0", "de")}
     assert (stats(fwd["stats"])["status"] == 0).all() and (stats(g["stats"])["status"] == 0).all()
     for b in (0, 7, 31):
         k0, k1 = off[b], off[b + 1]
+        c0, c1 = k0 - b, k1 - b - 1
         ex = kkt.kkt_solve(probs[b])
-        assert rel(lam[k0:k1], ex["lam"]) < 1e-6, b
+        assert rel(fn["lam"][k0:k1], ex["lam"]) < 1e-6, b
+        assert rel(fn["dx"][k0:k1], ex["dx"]) < 1e-6, b
+        assert rel(fn["du"][c0:c1], ex["du"]) < 1e-6, b
         ref = kkt.adjoint_dense(probs[b], gln[k0:k1])
-        assert rel(dQ[k0:k1], ref["dQ"]) < 1e-5, b
-        assert rel(dA[k0 - b:k1 - b - 1], ref["dA"]) < 1e-5, b
+        for k in ("dQ", "dq"):
+            assert rel(gn[k][k0:k1], ref[k]) < 1e-5, (b, k)
+        assert rel(gn["dx0"][b], ref["dx0"]) < 1e-5, b
+        for k in ("dR", "dA", "dB", "dr", "de"):
+            assert rel(gn[k][c0:c1], ref[k]) < 1e-5, (b, k)
 
 
 def test_wide_factor_reports_breakdown(ctx28):
