@@ -456,7 +456,11 @@ template <int NX, int STEP>
 __global__ void __launch_bounds__(kCrWaves * 64) wide_cr_step(const WArgs a, const CrTask *tasks, int ntasks,
                                                                 int s, int *flag) {
   constexpr int MM = NX * NX;
-  __shared__ __attribute__((aligned(16))) double stage[kCrWaves][MM];
+  // staged right operands: the elimination loads both of its own before the inverse so
+  // that their global round trips overlap it (at its register count one workgroup fills a
+  // CU, so the LDS is there); the other sub-steps stage one block at a time
+  constexpr int kBufs = STEP == kCrOdd ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) double stage[kCrWaves][kBufs][MM];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int t = blockIdx.x * kCrWaves + w;
   if (t >= ntasks) return;  // whole waves leave; no workgroup barrier follows
@@ -465,7 +469,7 @@ __global__ void __launch_bounds__(kCrWaves * 64) wide_cr_step(const WArgs a, con
   const int N = pd.N, j = tk.j;
   const int64_t k0 = pd.k0;
   const WaveBlocks<NX> W(lane);
-  double *by = stage[w];
+  double *b0 = stage[w][0], *b1 = stage[w][kBufs - 1];
   auto blk = [&](int k, int t2) { return a.S + ((k0 + k) * 3 + t2) * MM; };
   auto ublk = [&](int k) { return a.Dinv + (k0 + k) * MM; };
   auto vld = [&](const double *v, int k) {
@@ -474,19 +478,19 @@ __global__ void __launch_bounds__(kCrWaves * 64) wide_cr_step(const WArgs a, con
   };
   bool ok = true;
   if constexpr (STEP == kCrOdd) {  // eliminate j = s(2m+1)
+    const bool up = j + s < N;
+    W.stage_rows(b0, blk(j, 0));             // L_j
+    if (up) W.stage_cols(b1, blk(j + s, 0)); // L_{j+s}^T
     double D[NX], C[NX];
     W.load(blk(j, 1), D);
+    const double y = vld(a.rhs, j);
     reg_gj_inverse<NX>(D, lane, ok);         // D_j^-1, rows in D
-    const double z = W.mv(D, vld(a.rhs, j));
-    W.stage_rows(by, blk(j, 0));             // L_j
+    const double z = W.mv(D, y);
     wave_lds_order();
-    W.mm(D, by, C);                          // V_j
+    W.mm(D, b0, C);                          // V_j
     W.store(blk(j, 1), C);                   // over D_j (read above)
-    if (j + s < N) {
-      wave_lds_order();
-      W.stage_cols(by, blk(j + s, 0));       // L_{j+s}^T
-      wave_lds_order();
-      W.mm(D, by, C);                        // U_j
+    if (up) {
+      W.mm(D, b1, C);                        // U_j
       W.store(ublk(j), C);
     }
     if (W.rowv) a.rhs[(k0 + j) * NX + lane] = z;
@@ -498,17 +502,17 @@ __global__ void __launch_bounds__(kCrWaves * 64) wide_cr_step(const WArgs a, con
       double C[NX];
       W.load(blk(i, 0), X);                  // L_i
       y -= W.mv(X, vld(a.rhs, i - s));
-      W.stage_rows(by, blk(i - s, 1));       // V_{i-s}
+      W.stage_rows(b0, blk(i - s, 1));       // V_{i-s}
       wave_lds_order();
-      W.mm(X, by, C);
+      W.mm(X, b0, C);
 #pragma unroll
       for (int c = 0; c < NX; ++c) C[c] = -C[c];
       W.store(blk(i, 0), C);                 // coupling to i - 2s (L_i is in X)
       wave_lds_order();
-      W.stage_rows(by, ublk(i - s));         // U_{i-s}
+      W.stage_rows(b0, ublk(i - s));         // U_{i-s}
       W.load(blk(i, 1), D);
       wave_lds_order();
-      W.mm_sub(X, by, D);                    // D_i -= L_i U_{i-s}
+      W.mm_sub(X, b0, D);                    // D_i -= L_i U_{i-s}
     } else {
       W.load(blk(i, 1), D);
     }
@@ -516,9 +520,9 @@ __global__ void __launch_bounds__(kCrWaves * 64) wide_cr_step(const WArgs a, con
       W.load_t(blk(i + s, 0), X);            // L_{i+s}^T
       y -= W.mv(X, vld(a.rhs, i + s));
       wave_lds_order();
-      W.stage_rows(by, blk(i + s, 1));       // V_{i+s}
+      W.stage_rows(b0, blk(i + s, 1));       // V_{i+s}
       wave_lds_order();
-      W.mm_sub(X, by, D);                    // D_i -= L_{i+s}^T V_{i+s}
+      W.mm_sub(X, b0, D);                    // D_i -= L_{i+s}^T V_{i+s}
     }
     W.store(blk(i, 1), D);
     if (W.rowv) a.rhs[(k0 + i) * NX + lane] = y;
