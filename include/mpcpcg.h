@@ -171,11 +171,12 @@ int mpcpcg_set_graph(mpcpcg_ctx *ctx, int32_t enable);
 /* Solution method of mpcpcg_solve, mpcpcg_solve_batched and mpcpcg_backward.
  *   MPCPCG_METHOD_PCG (default): PCG as above (Algorithm 1).
  *   MPCPCG_METHOD_FACTOR: direct solve of the same Schur system, the alternative to the
- *     iterative solve that the paper names as future work (Section VI).  At (14, 7) by
- *     block cyclic reduction of the block-tridiagonal S (log2 N levels of parallel block
- *     eliminations, one workgroup per problem); at (28, 14) by block LDL^T factorisation
- *     (D_0 = S_00, D_k = S_kk - S_{k,k-1} D_{k-1}^-1 S_{k-1,k}, forward and back
- *     substitution, one workgroup per problem).  FP64 throughout, exact up to rounding;
+ *     iterative solve that the paper names as future work (Section VI), by block cyclic
+ *     reduction of the block-tridiagonal S (log2 N levels of parallel block eliminations,
+ *     then back substitution).  At (14, 7) one workgroup per problem, except that a lone
+ *     problem (a single solve or a batch of one) runs its levels with many block tasks
+ *     spread over the device; at (28, 14) every level is spread over the device, one wave
+ *     per block task.  FP64 throughout, exact up to rounding;
  *     eps, max_iter, warm_start and stop_rule are ignored; stats report iters = 0, status
  *     OK or BREAKDOWN (a non-positive pivot, i.e. S not positive definite, or a non-finite
  *     result), final_ratio = 0.  Its cost does not depend on the conditioning of S.  At
@@ -184,9 +185,9 @@ int mpcpcg_set_graph(mpcpcg_ctx *ctx, int32_t enable);
  *   MPCPCG_METHOD_AUTO: per call, at (14, 7) the faster of the two by a cost model
  *     measured on MI355X, which prices PCG at ~100 iterations for cold starts and ~45 for
  *     warm starts (opts->warm_start; the adjoint counts as cold).  On the Kuka-shaped
- *     problems this takes the factorisation for cold solves and batches, and PCG for
- *     warm-started single solves.  At (28, 14) always the factorisation, which is faster
- *     there at every measured size. */
+ *     problems this takes the factorisation for cold solves, lone problems and large
+ *     batches, and PCG for warm-started small batches.  At (28, 14) always the
+ *     factorisation, which is faster there at every measured size. */
 enum { MPCPCG_METHOD_PCG = 0, MPCPCG_METHOD_FACTOR = 1, MPCPCG_METHOD_AUTO = 2 };
 int mpcpcg_set_method(mpcpcg_ctx *ctx, int32_t method);
 

@@ -87,6 +87,7 @@ struct mpcpcg_ctx {
   int method = MPCPCG_METHOD_PCG;
   // factorisation path workspace (allocated on first use): S rows, rhs / y, D^-1, lambda
   double *f_s = nullptr, *f_rhs = nullptr, *f_dinv = nullptr, *f_lam = nullptr;
+  int *f_flag = nullptr;  // breakdown flag of a split single solve (kept at 0 between solves)
   double *qinv_ws = nullptr, *rinv_ws = nullptr;
   void *tws = nullptr;
   Gang *gang = nullptr;
@@ -325,12 +326,16 @@ int ensure_factor_ws(mpcpcg_ctx *c) {
   if (hipMalloc(&c->f_s, K * 3 * kNX * mpc::kGroup * sizeof(double)) != hipSuccess ||
       hipMalloc(&c->f_rhs, K * kNX * sizeof(double)) != hipSuccess ||
       hipMalloc(&c->f_dinv, K * kNX * mpc::kGroup * sizeof(double)) != hipSuccess ||
-      hipMalloc(&c->f_lam, K * kNX * sizeof(double)) != hipSuccess) {
+      hipMalloc(&c->f_lam, K * kNX * sizeof(double)) != hipSuccess ||
+      hipMalloc(&c->f_flag, sizeof(int)) != hipSuccess) {
     (void)hipGetLastError();
     for (double **q : {&c->f_s, &c->f_rhs, &c->f_dinv, &c->f_lam})
       if (*q) { (void)hipFree(*q); *q = nullptr; }
+    if (c->f_flag) { (void)hipFree(c->f_flag); c->f_flag = nullptr; }
     return fail(c, MPCPCG_ENOMEM, "cannot allocate the factorisation workspace (%zu knots)", K);
   }
+  HIPCHK(c, hipMemset(c->f_flag, 0, sizeof(int)));
+  HIPCHK(c, hipDeviceSynchronize());
   return MPCPCG_OK;
 }
 
@@ -341,7 +346,8 @@ int ensure_factor_ws(mpcpcg_ctx *c) {
 //        ~45 for warm-started receding-horizon solves;
 //   factorisation: its two parallel phases, ~25 + 138 per 12,288 knots, plus the cyclic
 //        reduction, one workgroup per problem: ~25 + 0.55 N for the longest horizon alone,
-//        up to 2.2x that when every CU holds a problem.
+//        up to 2.2x that when every CU holds a problem; a lone problem, whose first levels
+//        spread over the device, ~49 + 20.5 (log2 N - 4) in all.
 // The adjoint (warm = false) is priced as a cold solve.
 bool use_factor(mpcpcg_ctx *c, const std::vector<int64_t> &off, bool warm) {
   if (c->method == MPCPCG_METHOD_PCG) return false;
@@ -355,6 +361,7 @@ bool use_factor(mpcpcg_ctx *c, const std::vector<int64_t> &off, bool warm) {
   const double fill = std::min(1.0, knots / per_round);
   const double iters = warm ? 45.0 : 100.0;
   const double t_pcg = rounds * (40.0 + iters * (3.3 + 2.0 * fill));
+  if (B == 1) return 49.0 + 20.5 * std::max(0.0, std::log2((double)nmax) - 4.0) < t_pcg;
   const double load = 1.0 + 1.2 * (double)std::min<int64_t>(B, c->cus) / (double)c->cus;
   const double t_cr = (25.0 + 0.55 * (double)nmax) * load * std::ceil((double)B / (double)c->cus);
   const double t_fac = 25.0 + 138.0 * knots / per_round + t_cr;
@@ -401,13 +408,33 @@ int run_factor(mpcpcg_ctx *c, KArgs a, int mode, Schedule *s, int N, hipStream_t
   std::memset(&t, 0, sizeof t);
   t.s_ws = c->f_s; t.rhs_ws = c->f_rhs; t.dinv_ws = c->f_dinv; t.lam_ws = c->f_lam;
   t.stats = a.stats;
-  if (s) {
+  t.s0 = 1;
+  t.flag = c->f_flag;
+  if (s && s->nprobs > 1) {
     t.probs = s->d_sorted; t.nprobs = s->nprobs;
   } else {
+    // a lone problem (a single solve or a batch of one): the levels with more block tasks
+    // than one workgroup holds run as one launch per sub-step over the device, the rest
+    // in one workgroup
+    const int n1 = s ? (int)(s->off[1] - s->off[0]) : N;
     t.probs = nullptr; t.nprobs = 1;
-    t.single.k0 = 0; t.single.N = N; t.single.t0 = 0; t.single.nparts = 1; t.single.id = 0;
+    t.single.k0 = 0; t.single.N = n1; t.single.t0 = 0; t.single.nparts = 1; t.single.id = 0;
+    while ((n1 - 1) / (2 * t.s0) + 1 > mpc::kCrGroups) t.s0 *= 2;
+  }
+  const int n1 = t.single.N;
+  auto grid = [](int n) { return dim3((n + mpc::kCrGroups - 1) / mpc::kCrGroups); };
+  auto n_odd = [n1](int sl) { return (n1 - sl + 2 * sl - 1) / (2 * sl); };
+  for (int sl = 1; sl < t.s0; sl *= 2) {
+    hipLaunchKernelGGL((mpc::cr_level<kNX, mpc::kLvlOdd>), grid(n_odd(sl)), dim3(mpc::kCrThreads), 0, stream, t, sl);
+    hipLaunchKernelGGL((mpc::cr_level<kNX, mpc::kLvlEven>), grid((n1 - 1) / (2 * sl) + 1), dim3(mpc::kCrThreads), 0,
+                       stream, t, sl);
   }
   hipLaunchKernelGGL(mpc::cr_solve<kNX>, dim3(t.nprobs), dim3(mpc::kCrThreads), 0, stream, t);
+  if (t.s0 > 1) {
+    for (int sl = t.s0 / 2; sl >= 1; sl /= 2)
+      hipLaunchKernelGGL((mpc::cr_level<kNX, mpc::kLvlBack>), grid(n_odd(sl)), dim3(mpc::kCrThreads), 0, stream, t, sl);
+    hipLaunchKernelGGL(mpc::cr_finish<kNX>, dim3(1), dim3(mpc::kCrThreads), 0, stream, t);
+  }
   HIPCHK(c, hipGetLastError());
   return launch_phase(c, a, mode, 2, s, N, stream);
 }
@@ -709,6 +736,7 @@ int mpcpcg_destroy(mpcpcg_ctx *c) {
   for (auto &kv : c->sched) free_schedule(kv.second.get());
   for (double *q : {c->f_s, c->f_rhs, c->f_dinv, c->f_lam})
     if (q) (void)hipFree(q);
+  if (c->f_flag) (void)hipFree(c->f_flag);
   if (c->qinv_ws) (void)hipFree(c->qinv_ws);
   if (c->rinv_ws) (void)hipFree(c->rinv_ws);
   if (c->tws) (void)hipFree(c->tws);

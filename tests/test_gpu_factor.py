@@ -46,7 +46,9 @@ def stats(t):
     return stats_to_numpy(t)
 
 
-@pytest.mark.parametrize("N", [1, 2, 3, 16, 17, 64, 130, 512])
+# N >= 65 runs the first levels as one launch per sub-step over the device (65: one such
+# level; 130, 300, 512: two to three, 300 not a power of two)
+@pytest.mark.parametrize("N", [1, 2, 3, 16, 17, 64, 65, 130, 300, 512])
 def test_factor_single_matches_kkt(ctx, N):
     p = synth.problem(N, seed=9000 + N, defects=(N % 2 == 1))
     out = ctx.mpcpcg_solve(dev(p), eps=1e-6)
@@ -111,9 +113,27 @@ def test_factor_reports_breakdown(ctx):
     assert stats(out["stats"])[0]["status"] == 2
 
 
+@pytest.mark.parametrize("knot", [3, 64])
+def test_factor_split_single_reports_breakdown_then_recovers(ctx, knot):
+    # N = 200 runs strides 1 and 2 over the device and the rest in one workgroup; knot 3 is
+    # eliminated in the first part, knot 64 only at stride 64.  The next (good) solve must
+    # report OK again (the breakdown flag is cleared).
+    p = synth.problem(200, seed=9310)
+    bad = {k: v.copy() for k, v in p.items()}
+    bad["Q"][knot] = -bad["Q"][knot]
+    out = ctx.mpcpcg_solve(dev(bad))
+    torch.cuda.synchronize()
+    assert stats(out["stats"])[0]["status"] == 2
+    out = ctx.mpcpcg_solve(dev(p))
+    torch.cuda.synchronize()
+    assert stats(out["stats"])[0]["status"] == 0
+    assert rel(out["lam"].cpu().numpy(), kkt.kkt_solve(p)["lam"]) < 1e-6
+
+
 def test_auto_selects_by_cost_model():
-    # cold solves price PCG at ~100 iterations (the factorisation wins, one problem or
-    # many); a warm-started single solve at ~45 (PCG wins)
+    # cold solves price PCG at ~100 iterations, warm-started ones at ~45.  A lone problem
+    # (its reduction spread over the device) and a large batch take the factorisation,
+    # cold or warm; a warm-started batch of 8 x N = 512 takes PCG.
     from paper_2309_08079_amd.mpcpcg import Context
     c = Context(14, 7, max_total_knots=256 * 512, max_batch=256)
     try:
@@ -125,12 +145,16 @@ def test_auto_selects_by_cost_model():
         probs = synth.batch([512] * 256, seed0=9401)
         packed, off = synth.pack(probs)
         ob = c.mpcpcg_solve_batched(dev(packed), off)
+        p8, off8 = synth.pack(probs[:8])
+        o8 = c.mpcpcg_solve_batched(dev(p8), off8, lam0=torch.zeros((8 * 512, 14), device="cuda"))
         torch.cuda.synchronize()
         assert stats(o1["stats"])[0]["iters"] == 0         # one cold problem: factorisation
-        assert stats(ow["stats"])[0]["iters"] > 0          # warm-started: PCG
+        assert stats(ow["stats"])[0]["iters"] == 0         # one warm problem: factorisation
         assert (stats(ob["stats"])["iters"] == 0).all()    # many problems: factorisation
+        assert (stats(o8["stats"])["iters"] > 0).all()     # a warm small batch: PCG
         ex = kkt.kkt_solve(probs[5])
         assert rel(ob["lam"].cpu().numpy()[5 * 512:6 * 512], ex["lam"]) < 1e-6
+        assert rel(o8["lam"].cpu().numpy()[5 * 512:6 * 512], ex["lam"]) < 1e-5
         assert rel(o1["lam"].cpu().numpy(), kkt.kkt_solve(one)["lam"]) < 1e-6
     finally:
         c.close()
