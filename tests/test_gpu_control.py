@@ -247,13 +247,14 @@ def run_steps(c, method, graph, trajs, m, steps, iters, warm):
     return outs, off
 
 
-@pytest.mark.parametrize("method", ["pcg", "factor"])
-def test_control_step_graph_replays_match_eager(ctx, method):
+@pytest.mark.parametrize("method,Ns", [("pcg", [24, 64, 9]), ("factor", [24, 64, 9]), ("factor", [200])])
+def test_control_step_graph_replays_match_eager(ctx, method, Ns):
     # calls 1 (direct launches), 2 (capture + launch) and 3..5 (replays) against the same
-    # steps with graphs disabled, every call compared bit for bit
+    # steps with graphs disabled, every call compared bit for bit.  A lone problem of 200
+    # knots runs its factorisation's first levels as separate launches over the device,
+    # with a breakdown flag that the last launch clears.
     from paper_2309_08079_amd.mpcpcg import Context
     m = synth.chain_model(7, seed=10010)
-    Ns = [24, 64, 9]
     trajs = synth.trajectories(Ns, seed0=12800)
     other = Context(14, 7, max_total_knots=1 << 14, max_batch=64)
     try:
