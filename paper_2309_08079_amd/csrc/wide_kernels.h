@@ -111,10 +111,11 @@ __device__ __forceinline__ void wave_lds_order() {
 }
 
 // In-place Gauss-Jordan inverse of an SPD N x N matrix (no pivoting), rows in the lanes'
-// registers: the pivot row k is read from lane k with readlane.  Lanes >= N hold zeros and
-// keep them.  `pd` ends false if a pivot is not > 0.
+// registers: the pivot row k is read from lane k with readlane.  `row` is the row a lane
+// holds (lane k must hold row k; other lanes may hold copies of rows, or zeros under a row
+// id >= N, and keep them consistent).  `pd` ends false if a pivot is not > 0.
 template <int N>
-__device__ __forceinline__ void reg_gj_inverse(double (&a)[N], int lane, bool &pd) {
+__device__ __forceinline__ void reg_gj_inverse(double (&a)[N], int row, bool &pd) {
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     double pk[N];
@@ -125,7 +126,7 @@ __device__ __forceinline__ void reg_gj_inverse(double (&a)[N], int lane, bool &p
     const double d = 1.0 / piv;
     // pivot row: a_kj d; other rows: a_ij - f a_kj (f = a_ik d); column k: d / -f,
     // as c a_kj + s a_ij with (s, c) = (0, d) on the pivot lane and (1, -f) elsewhere
-    const bool me = lane == k;
+    const bool me = row == k;
     const double f = a[k] * d;
     const double sc = me ? 0.0 : 1.0, c = me ? d : -f;
 #pragma unroll
@@ -365,8 +366,9 @@ __global__ void __launch_bounds__(256) wide_precond(const WArgs a) {
 // x_j = z_j - V_j x_{j-s} - U_j x_{j+s}.  The reduced systems are Schur complements of S,
 // so a pivot <= 0 means S is not positive definite (BREAKDOWN).
 // Work mapping: one launch per sub-step of a level, over the block tasks of all problems
-// (so a level spreads over the whole device), one wave per task, lane r < NX owns row r
-// in registers; the launches on one stream order the levels.  The Gauss-Jordan inverse
+// (so a level spreads over the whole device), one wave per task, lanes r and r + 32 own
+// row r < NX in registers (each computing half of the row's product columns); the
+// launches on one stream order the levels.  The Gauss-Jordan inverse
 // takes the pivot row from its lane with readlane; a matrix product takes the left
 // operand's row from registers and the right operand's rows from the wave's own LDS
 // staging block (the same address for every lane: a broadcast read); matrix-vector
@@ -377,23 +379,31 @@ __global__ void __launch_bounds__(256) wide_precond(const WArgs a) {
 constexpr int kCrWaves = 8;
 
 
+// Two lanes per row: lane l holds row l & 31 (valid below NX) and computes the output
+// columns [h H, h H + H) of it, h = l >> 5; both lanes of a row hold the whole left-operand
+// row, so inverses and matrix-vector products run on full rows in both halves.
 template <int NX>
 struct WaveBlocks {
-  int lane;
+  static_assert(NX % 2 == 0 && NX <= 32, "two lanes per row of an even NX <= 32");
+  static constexpr int H = NX / 2;  // output columns per lane
+  int lane, h, row;  // row: this lane's row (>= NX for a lane without one)
   bool rowv;
-  int r;  // row of this lane (clamped for lanes >= NX, whose results are never stored)
-  __device__ __forceinline__ WaveBlocks(int l) : lane(l), rowv(l < NX), r(l < NX ? l : 0) {}
-  // a global block into the staging block by rows (lane c copies column c: coalesced)
+  int r;             // row clamped to 0 for loads (results of such lanes are never stored)
+  __device__ __forceinline__ WaveBlocks(int l)
+      : lane(l), h(l >> 5), row(l & 31), rowv((l & 31) < NX), r((l & 31) < NX ? (l & 31) : 0) {}
+  // a global block into the staging block by rows (lane (h, c) copies column c of its
+  // half of the rows: coalesced)
   __device__ __forceinline__ void stage_rows(double *buf, const double *B) const {
     if (rowv)
-#pragma unroll 4
-      for (int m = 0; m < NX; ++m) buf[m * NX + r] = B[m * NX + r];
+#pragma unroll 2
+      for (int mm = 0; mm < H; ++mm) buf[(h * H + mm) * NX + r] = B[(h * H + mm) * NX + r];
   }
-  // the transpose of a global block into the staging block (lane c writes row c as column c)
+  // the transpose of a global block into the staging block (lane (h, c) writes its half
+  // of row c as its half of column c)
   __device__ __forceinline__ void stage_cols(double *buf, const double *B) const {
     if (rowv)
-#pragma unroll 4
-      for (int m = 0; m < NX; ++m) buf[m * NX + r] = B[r * NX + m];
+#pragma unroll 2
+      for (int mm = 0; mm < H; ++mm) buf[(h * H + mm) * NX + r] = B[r * NX + h * H + mm];
   }
   // unconditional loads from the clamped row, then masked: straight-line code
   __device__ __forceinline__ void load(const double *B, double (&o)[NX]) const {
@@ -411,27 +421,40 @@ struct WaveBlocks {
       o[j] = rowv ? v : 0.0;
     }
   }
-  __device__ __forceinline__ void store(double *B, const double (&v)[NX]) const {
-    if (rowv)
+  // this lane's half of row r
+  __device__ __forceinline__ void load_half(const double *B, double (&o)[H]) const {
 #pragma unroll
-      for (int j = 0; j < NX; ++j) B[r * NX + j] = v[j];
-  }
-  // C = X Y, rows of X in the lanes' registers, Y staged
-  __device__ __forceinline__ void mm(const double (&X)[NX], const double *Y, double (&C)[NX]) const {
-#pragma unroll
-    for (int j = 0; j < NX; ++j) C[j] = 0.0;
-    row_times<NX, NX>(X, Y, C);
-  }
-  // C -= X Y
-  __device__ __forceinline__ void mm_sub(const double (&X)[NX], const double *Y, double (&C)[NX]) const {
-#pragma unroll
-    for (int m = 0; m < NX; ++m) {
-      const double *y = Y + m * NX;
-#pragma unroll
-      for (int j = 0; j < NX; ++j) C[j] = __builtin_fma(-X[m], y[j], C[j]);
+    for (int j = 0; j < H; ++j) {
+      const double v = B[r * NX + h * H + j];
+      o[j] = rowv ? v : 0.0;
     }
   }
-  // (X v)_r with v distributed over the lanes (lane m holds v_m)
+  __device__ __forceinline__ void store_half(double *B, const double (&v)[H]) const {
+    if (rowv)
+#pragma unroll
+      for (int j = 0; j < H; ++j) B[r * NX + h * H + j] = v[j];
+  }
+  // this lane's half of row r of C = X Y (rows of X in registers, Y staged)
+  __device__ __forceinline__ void mm(const double (&X)[NX], const double *Y, double (&C)[H]) const {
+#pragma unroll
+    for (int j = 0; j < H; ++j) C[j] = 0.0;
+    mm_sub_signed<1>(X, Y, C);
+  }
+  // C -= X Y on this lane's half
+  __device__ __forceinline__ void mm_sub(const double (&X)[NX], const double *Y, double (&C)[H]) const {
+    mm_sub_signed<-1>(X, Y, C);
+  }
+  template <int SIGN>
+  __device__ __forceinline__ void mm_sub_signed(const double (&X)[NX], const double *Y, double (&C)[H]) const {
+#pragma unroll
+    for (int m = 0; m < NX; ++m) {
+      const double x = SIGN > 0 ? X[m] : -X[m];
+      const double *y = Y + m * NX + h * H;
+#pragma unroll
+      for (int j = 0; j < H; ++j) C[j] = __builtin_fma(x, y[j], C[j]);
+    }
+  }
+  // (X v)_r with v distributed over the lanes (lane m < NX holds v_m)
   __device__ __forceinline__ double mv(const double (&X)[NX], double v) const {
     double acc = 0.0;
 #pragma unroll
@@ -477,44 +500,46 @@ __global__ void __launch_bounds__(kCrWaves * 64) wide_cr_step(const WArgs a, con
     return W.rowv ? x : 0.0;
   };
   bool ok = true;
+  constexpr int H = WaveBlocks<NX>::H;
+  const bool out = W.rowv && W.h == 0;  // one writer per row of a vector
   if constexpr (STEP == kCrOdd) {  // eliminate j = s(2m+1)
     const bool up = j + s < N;
     W.stage_rows(b0, blk(j, 0));             // L_j
     if (up) W.stage_cols(b1, blk(j + s, 0)); // L_{j+s}^T
-    double D[NX], C[NX];
+    double D[NX], C[H];
     W.load(blk(j, 1), D);
     const double y = vld(a.rhs, j);
-    reg_gj_inverse<NX>(D, lane, ok);         // D_j^-1, rows in D
+    reg_gj_inverse<NX>(D, W.row, ok);        // D_j^-1, rows in D
     const double z = W.mv(D, y);
     wave_lds_order();
     W.mm(D, b0, C);                          // V_j
-    W.store(blk(j, 1), C);                   // over D_j (read above)
+    W.store_half(blk(j, 1), C);              // over D_j (read above)
     if (up) {
       W.mm(D, b1, C);                        // U_j
-      W.store(ublk(j), C);
+      W.store_half(ublk(j), C);
     }
-    if (W.rowv) a.rhs[(k0 + j) * NX + lane] = z;
+    if (out) a.rhs[(k0 + j) * NX + W.r] = z;
   } else if constexpr (STEP == kCrEven) {  // i = 2sm absorbs i - s and i + s
     const int i = j;
-    double D[NX], X[NX];
+    double D[H], X[NX];
     double y = vld(a.rhs, i);
     if (i >= s) {
-      double C[NX];
+      double C[H];
       W.load(blk(i, 0), X);                  // L_i
       y -= W.mv(X, vld(a.rhs, i - s));
       W.stage_rows(b0, blk(i - s, 1));       // V_{i-s}
       wave_lds_order();
       W.mm(X, b0, C);
 #pragma unroll
-      for (int c = 0; c < NX; ++c) C[c] = -C[c];
-      W.store(blk(i, 0), C);                 // coupling to i - 2s (L_i is in X)
+      for (int c = 0; c < H; ++c) C[c] = -C[c];
+      W.store_half(blk(i, 0), C);            // coupling to i - 2s (L_i is in X)
       wave_lds_order();
       W.stage_rows(b0, ublk(i - s));         // U_{i-s}
-      W.load(blk(i, 1), D);
+      W.load_half(blk(i, 1), D);
       wave_lds_order();
       W.mm_sub(X, b0, D);                    // D_i -= L_i U_{i-s}
     } else {
-      W.load(blk(i, 1), D);
+      W.load_half(blk(i, 1), D);
     }
     if (i + s < N) {
       W.load_t(blk(i + s, 0), X);            // L_{i+s}^T
@@ -524,14 +549,14 @@ __global__ void __launch_bounds__(kCrWaves * 64) wide_cr_step(const WArgs a, con
       wave_lds_order();
       W.mm_sub(X, b0, D);                    // D_i -= L_{i+s}^T V_{i+s}
     }
-    W.store(blk(i, 1), D);
-    if (W.rowv) a.rhs[(k0 + i) * NX + lane] = y;
+    W.store_half(blk(i, 1), D);
+    if (out) a.rhs[(k0 + i) * NX + W.r] = y;
   } else if constexpr (STEP == kCrRoot) {  // x_0 = D_0^-1 y_0
     double D[NX];
     W.load(blk(0, 1), D);
-    reg_gj_inverse<NX>(D, lane, ok);
+    reg_gj_inverse<NX>(D, W.row, ok);
     const double x = W.mv(D, vld(a.rhs, 0));
-    if (W.rowv) a.lamw[k0 * NX + lane] = x;
+    if (out) a.lamw[k0 * NX + W.r] = x;
   } else {  // x_j = z_j - V_j x_{j-s} - U_j x_{j+s}
     double T[NX];
     W.load(blk(j, 1), T);
@@ -540,7 +565,7 @@ __global__ void __launch_bounds__(kCrWaves * 64) wide_cr_step(const WArgs a, con
       W.load(ublk(j), T);
       x -= W.mv(T, vld(a.lamw, j + s));
     }
-    if (W.rowv) a.lamw[(k0 + j) * NX + lane] = x;
+    if (out) a.lamw[(k0 + j) * NX + W.r] = x;
   }
   if (!ok && lane == 0) flag[tk.prob] = 1;  // every writer stores the same value
 }
