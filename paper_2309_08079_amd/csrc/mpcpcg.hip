@@ -41,6 +41,12 @@ struct Schedule {
   ProbDesc *d_probs = nullptr;
   ProbDesc *d_sorted = nullptr;  // the same descriptors, longest first (factorisation sweep)
   Task *d_tasks = nullptr;
+  // the same tasks in eight per-XCD lists (batched PCG; nullptr when the batch does not
+  // qualify), with their own problem descriptors (t0 indexes these lists)
+  ProbDesc *d_xprobs = nullptr;
+  Task *d_xtasks = nullptr;
+  int32_t *d_xoff = nullptr;
+  int xgrid = 0;
   hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
   hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
   hipGraphNode_t node[3] = {nullptr, nullptr, nullptr};
@@ -84,6 +90,7 @@ struct mpcpcg_ctx {
   int64_t max_tasks = 0;
   int kpw_override = 0;
   int use_graph = 1;
+  int xcd_pin = 1;  // batched PCG: per-XCD task lists when the batch qualifies
   int method = MPCPCG_METHOD_PCG;
   // factorisation path workspace (allocated on first use): S rows, rhs / y, D^-1, lambda
   double *f_s = nullptr, *f_rhs = nullptr, *f_dinv = nullptr, *f_lam = nullptr;
@@ -304,6 +311,43 @@ int get_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, int kpw, Schedu
   HIPCHK(c, hipMemcpy(s->d_sorted, sorted.data(), sizeof(ProbDesc) * B, hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(s->d_tasks, tasks.data(), sizeof(Task) * tasks.size(), hipMemcpyHostToDevice));
   for (int m = 0; m < 3; ++m) s->grid[m] = std::min(s->ntasks, cap);
+  // Per-XCD lists: workgroups are dispatched to the eight XCDs in turn, so a full
+  // persistent grid puts cap / 8 on each.  When every gang fits in that, each problem (in
+  // longest-first order) goes to the XCD with the least work so far, and all parts of a
+  // gang run on one XCD (each workgroup reads its XCD from the hardware and pops only that
+  // XCD's list).  Its barrier round trips stay device-scope; measured ~8% faster for the
+  // 256 x N = 512 batch than gangs spread over all eight.  Needs a batch that fills all
+  // eight.
+  constexpr int kXcds = 8;
+  int max_parts = 0;
+  for (const auto &d : sorted) max_parts = std::max(max_parts, d.nparts);
+  if (c->xcd_pin && B >= kXcds && cap % kXcds == 0 && max_parts <= cap / kXcds) {
+    std::vector<std::vector<int>> lists(kXcds);
+    std::vector<int64_t> load(kXcds, 0);
+    for (const auto &d : sorted) {
+      const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      lists[x].push_back(d.id);
+      load[x] += d.N;
+    }
+    std::vector<ProbDesc> xprobs(probs);
+    std::vector<Task> xtasks;
+    std::vector<int32_t> xoff(kXcds + 1, 0);
+    for (int x = 0; x < kXcds; ++x) {
+      xoff[x] = (int32_t)xtasks.size();
+      for (int b : lists[x]) {
+        xprobs[b].t0 = (int32_t)xtasks.size();
+        for (int j = 0; j < xprobs[b].nparts; ++j) xtasks.push_back(Task{b, j});
+      }
+    }
+    xoff[kXcds] = (int32_t)xtasks.size();
+    HIPCHK(c, hipMalloc(&s->d_xprobs, sizeof(ProbDesc) * B));
+    HIPCHK(c, hipMalloc(&s->d_xtasks, sizeof(Task) * xtasks.size()));
+    HIPCHK(c, hipMalloc(&s->d_xoff, sizeof(int32_t) * xoff.size()));
+    HIPCHK(c, hipMemcpy(s->d_xprobs, xprobs.data(), sizeof(ProbDesc) * B, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(s->d_xtasks, xtasks.data(), sizeof(Task) * xtasks.size(), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(s->d_xoff, xoff.data(), sizeof(int32_t) * xoff.size(), hipMemcpyHostToDevice));
+    s->xgrid = cap;
+  }
   *out = s.get();
   c->sched.emplace(key, std::move(s));
   return MPCPCG_OK;
@@ -317,6 +361,8 @@ void free_schedule(Schedule *s) {
   if (s->d_probs) (void)hipFree(s->d_probs);
   if (s->d_sorted) (void)hipFree(s->d_sorted);
   if (s->d_tasks) (void)hipFree(s->d_tasks);
+  for (void *q : {(void *)s->d_xprobs, (void *)s->d_xtasks, (void *)s->d_xoff})
+    if (q) (void)hipFree(q);
 }
 
 int ensure_factor_ws(mpcpcg_ctx *c) {
@@ -375,6 +421,7 @@ int launch_phase(mpcpcg_ctx *c, KArgs a, int mode, int phase, Schedule *s, int N
   HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(fn), kpw * mpc::kGroup, 0));
   const int cap = nb * c->cus;
   int grid;
+  a.xoff = nullptr;  // the phases pop the global queue
   if (s) {
     a.probs = s->d_probs; a.tasks = s->d_tasks; a.ntasks = s->ntasks; a.persistent = 1;
     grid = std::min(s->ntasks, cap);
@@ -440,11 +487,13 @@ int run_factor(mpcpcg_ctx *c, KArgs a, int mode, Schedule *s, int N, hipStream_t
 }
 
 int launch_batched(mpcpcg_ctx *c, Schedule *s, KArgs &a, int mode, hipStream_t stream) {
-  a.probs = s->d_probs;
-  a.tasks = s->d_tasks;
+  const bool pin = s->d_xoff != nullptr;
+  a.probs = pin ? s->d_xprobs : s->d_probs;
+  a.tasks = pin ? s->d_xtasks : s->d_tasks;
+  a.xoff = pin ? s->d_xoff : nullptr;
   a.ntasks = s->ntasks;
   a.persistent = 1;
-  const int grid = s->grid[mode];
+  const int grid = pin ? s->xgrid : s->grid[mode];
   const dim3 block(s->kpw * mpc::kGroup);
   if (!c->use_graph) {
     hipLaunchKernelGGL(kernel_for(s->kpw, mode), dim3(grid), block, 0, stream, a);
@@ -717,11 +766,11 @@ int mpcpcg_create(mpcpcg_ctx **out, int32_t nx, int32_t nu, int64_t max_total_kn
   const size_t gb = sizeof(Gang) * (size_t)max_batch;
   if (hipMalloc(&c->qinv_ws, qb) != hipSuccess || hipMalloc(&c->rinv_ws, rb) != hipSuccess ||
       hipMalloc(&c->tws, tb) != hipSuccess || hipMalloc(&c->gang, gb) != hipSuccess ||
-      hipMalloc(&c->queue, 4 * sizeof(int)) != hipSuccess) {
+      hipMalloc(&c->queue, 16 * sizeof(int)) != hipSuccess) {
     mpcpcg_destroy(c.release());
     return MPCPCG_ENOMEM;
   }
-  if (hipMemset(c->gang, 0, gb) != hipSuccess || hipMemset(c->queue, 0, 4 * sizeof(int)) != hipSuccess ||
+  if (hipMemset(c->gang, 0, gb) != hipSuccess || hipMemset(c->queue, 0, 16 * sizeof(int)) != hipSuccess ||
       hipMemset(c->tws, 0, tb) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     mpcpcg_destroy(c.release());
     return MPCPCG_EHIP;

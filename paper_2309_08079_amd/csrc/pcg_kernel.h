@@ -113,11 +113,15 @@ struct KArgs {
   const Task *tasks;
   ProbDesc single;       // used when probs == nullptr (one problem, task = blockIdx.x)
   int32_t ntasks;
-  int32_t persistent;    // 1: workgroups pop tasks from queue[0]
+  int32_t persistent;    // 1: workgroups pop tasks from queue[0] (or their XCD's queue)
+  const int32_t *xoff;   // [9] or nullptr: the tasks of XCD x are [xoff[x], xoff[x+1]), popped
+                         // from queue[4 + x] by the workgroups running on XCD x only, so all
+                         // parts of a gang run on one XCD
   // workspace
   void *tws;             // TaskWS<NX>[ntasks]
   Gang *gang;            // [nprobs]
-  int *queue;            // [0] head, [1] workgroups finished, [2] launch generation
+  int *queue;            // [0] head, [1] workgroups finished, [2] launch generation,
+                         // [4 + x] head of XCD x
   double *qinv_ws;       // [knots][NX][kGroup]   Q_b^-1 by columns (row r at r)
   double *rinv_ws;       // [controls][NU + NX][kURows]  (R^-1 | R^-1 B^T) by columns
   // factorisation path: S rows [knots][NX][3 NX] and rhs [knots][NX] written by phase 1,
@@ -214,7 +218,17 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
     int task;
     if (a.persistent) {
       __syncthreads();
-      if (tid == 0) sh_task = atomicAdd(&a.queue[0], 1);
+      if (tid == 0) {
+        if (a.xoff) {
+          unsigned x;
+          asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+          x &= 7u;
+          const int t = a.xoff[x] + atomicAdd(&a.queue[4 + x], 1);
+          sh_task = t < a.xoff[x + 1] ? t : a.ntasks;  // this XCD's queue is empty
+        } else {
+          sh_task = atomicAdd(&a.queue[0], 1);
+        }
+      }
       __syncthreads();
       task = uni(sh_task);
       if (task >= a.ntasks) break;
@@ -1029,6 +1043,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
     const int d = __hip_atomic_fetch_add(&a.queue[1], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     if (d == (int)gridDim.x - 1) {
       __hip_atomic_store(&a.queue[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int x = 0; x < 8; ++x) __hip_atomic_store(&a.queue[4 + x], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_fetch_add(&a.queue[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&a.queue[1], 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
