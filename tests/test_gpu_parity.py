@@ -307,6 +307,42 @@ def test_backward_with_primal_gradients(ctx):
     check_grads(g, ref, off)
 
 
+def test_batched_gangs_on_one_xcd_match_the_global_queue(ctx):
+    # a batch of >= 8 problems runs each gang on one XCD (per-XCD task lists); smaller
+    # batches use the global queue.  Placement must not change any problem's arithmetic:
+    # the 8-problem batch and the same problems as two 4-problem batches agree bit for bit,
+    # forward and adjoint.  Horizons 96 and 40 (6 and 3 parts of 16 knots), seeds 7001 + b.
+    Ns = [96, 40, 96, 40, 96, 40, 96, 40]
+    probs = [synth.problem(n, seed=7001 + b) for b, n in enumerate(Ns)]
+    ctx.mpcpcg_set_knots_per_group(16)
+    try:
+        def run(group):
+            packed, off = synth.pack(group)
+            d = dev(packed)
+            fwd = ctx.mpcpcg_solve_batched(d, off)
+            g = ctx.mpcpcg_backward(d, off, fwd, 2 * fwd["lam"])
+            torch.cuda.synchronize()
+            return ({k: fwd[k].cpu().numpy() for k in ("lam", "dx", "du")},
+                    {k: g[k].cpu().numpy() for k in ("dQ", "dq")},
+                    stats(fwd["stats"]).copy(), stats(g["stats"]).copy(), off)
+        f8, g8, s8, b8, off8 = run(probs)
+        parts = [run(probs[:4]), run(probs[4:])]
+    finally:
+        ctx.mpcpcg_set_knots_per_group(0)
+    assert (s8["status"] == 0).all() and (b8["status"] == 0).all()
+    for h, (f4, g4, s4, b4, off4) in enumerate(parts):
+        for i in range(4):
+            b = 4 * h + i
+            k8, k4 = slice(off8[b], off8[b + 1]), slice(off4[i], off4[i + 1])
+            c8, c4 = slice(off8[b] - b, off8[b + 1] - b - 1), slice(off4[i] - i, off4[i + 1] - i - 1)
+            assert s8["iters"][b] == s4["iters"][i] and b8["iters"][b] == b4["iters"][i], b
+            for k in ("lam", "dx"):
+                assert np.array_equal(f8[k][k8], f4[k][k4]), (b, k)
+            assert np.array_equal(f8["du"][c8], f4["du"][c4]), b
+            for k in ("dQ", "dq"):
+                assert np.array_equal(g8[k][k8], g4[k][k4]), (b, k)
+
+
 def test_backward_batch64_horizon128(ctx):
     # batch 64, N = 128, L = ||lambda||^2, seeds 4001 + b
     probs, packed, off = _batch_case([128] * 64, 4001)
