@@ -232,7 +232,11 @@ int launch_single(mpcpcg_ctx *c, KArgs &a, int N, int kpw, int mode, hipStream_t
   if (g > c->max_tasks) return fail(c, MPCPCG_EINVAL, "N=%d exceeds the context's task workspace", N);
   a.single.k0 = 0; a.single.N = N; a.single.t0 = 0; a.single.nparts = g; a.single.id = 0;
   a.probs = nullptr; a.tasks = nullptr; a.ntasks = g; a.persistent = 0;
-  hipLaunchKernelGGL(kernel_for(kpw, mode), dim3(g), dim3(kpw * mpc::kGroup), 0, s, a);
+  // a gang of 2..16 parts runs on one XCD: launch 8 workgroups per part, of which the
+  // ones dispatched to the first XCD (blockIdx % 8 == 0) take the parts.  Measured 3-4%
+  // faster at N = 64..256 and 3% slower at 32 parts (N = 512), which stays spread.
+  a.one_xcd = (c->xcd_pin && g > 1 && g <= 16 && 8 * g <= cap) ? 1 : 0;
+  hipLaunchKernelGGL(kernel_for(kpw, mode), dim3(a.one_xcd ? 8 * g : g), dim3(kpw * mpc::kGroup), 0, s, a);
   HIPCHK(c, hipGetLastError());
   return MPCPCG_OK;
 }

@@ -117,6 +117,8 @@ struct KArgs {
   const int32_t *xoff;   // [9] or nullptr: the tasks of XCD x are [xoff[x], xoff[x+1]), popped
                          // from queue[4 + x] by the workgroups running on XCD x only, so all
                          // parts of a gang run on one XCD
+  int32_t one_xcd;       // non-persistent: the grid holds 8 workgroups per part and only those
+                         // with blockIdx % 8 == 0 (dispatched to one XCD) run, part blockIdx / 8
   // workspace
   void *tws;             // TaskWS<NX>[ntasks]
   Gang *gang;            // [nprobs]
@@ -234,7 +236,8 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       if (task >= a.ntasks) break;
     } else {
       if (iter_task > 0) break;
-      task = blockIdx.x;
+      if (a.one_xcd && (blockIdx.x & 7u)) break;
+      task = a.one_xcd ? (int)(blockIdx.x >> 3) : (int)blockIdx.x;
     }
     const Task tk = a.probs ? a.tasks[task] : Task{0, task};
     const ProbDesc pd = a.probs ? a.probs[tk.prob] : a.single;
