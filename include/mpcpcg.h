@@ -165,8 +165,36 @@ int mpcpcg_autotune(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
                     float *dx, float *du, mpcpcg_stats *stats, hipStream_t stream,
                     int32_t *knots_per_group);
 
+/* The schedule the next batched PCG solve of this horizon signature uses: knots per
+ * workgroup and whether each problem's workgroups run on one XCD (per-XCD task lists).
+ * After mpcpcg_autotune this is the tuned choice.  Builds (and caches) the schedule. */
+int mpcpcg_tuned_schedule(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
+                          int32_t *knots_per_group, int32_t *xcd_pinned);
+
+/* Default placement of batched PCG gangs when no tuned choice exists: 1 (default) runs all
+ * workgroups of a problem on one XCD when the device reports eight XCDs and the batch has
+ * at least eight problems that fit; 0 uses one global task queue.  mpcpcg_autotune times
+ * both placements and keeps the faster per signature. */
+int mpcpcg_set_xcd_pinning(mpcpcg_ctx *ctx, int32_t enable);
+
 /* Enable (1, default) or disable (0) hipGraph capture/replay in mpcpcg_solve_batched. */
 int mpcpcg_set_graph(mpcpcg_ctx *ctx, int32_t enable);
+
+/* Per-signature caches (schedules, tuned choices, captured graphs, chunk lists) hold at
+ * most max_signatures entries each (default 32); the least recently used entry is evicted,
+ * its device arrays freed and its graphs destroyed (the device is synchronised first).
+ * mpcpcg_cache_info reports the entries held over all caches and the device bytes of the
+ * cached schedules (either pointer may be NULL). */
+int mpcpcg_set_cache_limit(mpcpcg_ctx *ctx, int32_t max_signatures);
+int mpcpcg_cache_info(const mpcpcg_ctx *ctx, int32_t *entries, int64_t *device_bytes);
+
+/* Failure handling of problems that span several workgroups.  Every wait of one
+ * workgroup for another gives up after limit_us microseconds of wall-clock time (default
+ * 2 s); the problem then reports MPCPCG_TIMEOUT and every workgroup leaves normally.
+ * inject_stall = 1 is a test hook: the first such wait of every launch of the (14, 7)
+ * path waits for a signal that is never sent, so each multi-workgroup problem times out
+ * (on the factorisation path, in its primal-step launch). */
+int mpcpcg_debug_set_wait(mpcpcg_ctx *ctx, int64_t limit_us, int32_t inject_stall);
 
 /* Solution method of mpcpcg_solve, mpcpcg_solve_batched and mpcpcg_backward.
  *   MPCPCG_METHOD_PCG (default): PCG as above (Algorithm 1).

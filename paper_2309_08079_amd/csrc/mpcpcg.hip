@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -30,14 +31,37 @@ constexpr int kNX = 14, kNU = 7;        // register-resident fused path
 constexpr int kWNX = 28, kWNU = 14;     // generic (workspace-staged) path
 constexpr int kKpwChoices[] = {4, 8, 16, 32};
 
+// Device arrays owned by a cached schedule: freed with it.
+struct DevArrays {
+  std::vector<void *> ptrs;
+  int64_t bytes = 0;
+  DevArrays() = default;
+  DevArrays(const DevArrays &) = delete;
+  DevArrays &operator=(const DevArrays &) = delete;
+  ~DevArrays() {
+    for (void *p : ptrs) (void)hipFree(p);
+  }
+  // device copy of n host elements (nullptr on failure)
+  template <class T>
+  T *upload(const T *src, size_t n) {
+    void *p = nullptr;
+    if (hipMalloc(&p, sizeof(T) * (n ? n : 1)) != hipSuccess) return nullptr;
+    ptrs.push_back(p);
+    bytes += (int64_t)(sizeof(T) * (n ? n : 1));
+    if (n && hipMemcpy(p, src, sizeof(T) * n, hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+    return static_cast<T *>(p);
+  }
+};
+
 // One schedule per (horizon signature, knots per workgroup): problem descriptors and the
 // task list in longest-first order, resident on the device, plus the graph execs that
-// replay the persistent launch for it.
+// replay the persistent launch for it ([mode][per-XCD lists used]).
 struct Schedule {
   std::vector<int64_t> off;
   int kpw = 0;
   int ntasks = 0;
   int nprobs = 0;
+  DevArrays mem;
   ProbDesc *d_probs = nullptr;
   ProbDesc *d_sorted = nullptr;  // the same descriptors, longest first (factorisation sweep)
   Task *d_tasks = nullptr;
@@ -47,15 +71,23 @@ struct Schedule {
   Task *d_xtasks = nullptr;
   int32_t *d_xoff = nullptr;
   int xgrid = 0;
-  hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
-  hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
-  hipGraphNode_t node[3] = {nullptr, nullptr, nullptr};
-  KArgs args[3];
+  hipGraph_t graph[3][2] = {};
+  hipGraphExec_t exec[3][2] = {};
+  hipGraphNode_t node[3][2] = {};
+  KArgs args[3][2];
   int grid[3] = {0, 0, 0};
+  ~Schedule() {
+    for (int m = 0; m < 3; ++m)
+      for (int x = 0; x < 2; ++x) {
+        if (exec[m][x]) (void)hipGraphExecDestroy(exec[m][x]);
+        if (graph[m][x]) (void)hipGraphDestroy(graph[m][x]);
+      }
+  }
 };
 
 // chunks of the control-step kernels (linearisation, line search) for one horizon signature
 struct CtrlSchedule {
+  DevArrays mem;
   mpc::ctrl::Chunk *d_chunks = nullptr;
   int nchunks = 0;
 };
@@ -67,9 +99,14 @@ struct CtrlGraph {
   int calls = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  ~CtrlGraph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
 };
 
 struct WideSchedule {
+  DevArrays mem;
   mpc::wide::KnotDesc *d_knots = nullptr;
   mpc::wide::ProbDescW *d_probs = nullptr;
   int nknots = 0, nprobs = 0, maxN = 0;
@@ -81,6 +118,45 @@ struct WideSchedule {
   mpc::wide::CrTask *d_tasks = nullptr;
 };
 
+// Schedule choice of the batched PCG launch for one horizon signature.
+struct Tuned {
+  int kpw = 16;
+  int pin = 1;  // per-XCD task lists when the batch qualifies
+};
+
+// Least-recently-used map of per-signature state.  Values free what they own in their
+// destructors; the context evicts the oldest entry before inserting beyond its limit.
+template <class K, class V>
+struct Lru {
+  struct Ent {
+    std::unique_ptr<V> v;
+    uint64_t used = 0;
+  };
+  std::map<K, Ent> m;
+  uint64_t tick = 0;
+  V *get(const K &k) {
+    auto it = m.find(k);
+    if (it == m.end()) return nullptr;
+    it->second.used = ++tick;
+    return it->second.v.get();
+  }
+  V *put(const K &k, std::unique_ptr<V> v) {
+    Ent &e = m[k];
+    e.v = std::move(v);
+    e.used = ++tick;
+    return e.v.get();
+  }
+  typename std::map<K, Ent>::iterator oldest() {
+    auto best = m.begin();
+    for (auto it = m.begin(); it != m.end(); ++it)
+      if (it->second.used < best->second.used) best = it;
+    return best;
+  }
+  size_t size() const { return m.size(); }
+};
+
+using Sig = std::vector<int64_t>;
+
 }  // namespace
 
 struct mpcpcg_ctx {
@@ -90,8 +166,15 @@ struct mpcpcg_ctx {
   int64_t max_tasks = 0;
   int kpw_override = 0;
   int use_graph = 1;
-  int xcd_pin = 1;  // batched PCG: per-XCD task lists when the batch qualifies
+  // per-XCD task lists: only on a device that reports eight XCDs (one partition spanning
+  // the whole MI355X), where workgroups are dispatched to the XCDs in turn
+  int xcd_ok = 0;
+  int xcd_pin = 1;  // batched PCG default placement when the batch qualifies
   int method = MPCPCG_METHOD_PCG;
+  int64_t spin_ticks = 0;      // bound of every cross-workgroup wait (wall-clock ticks)
+  int64_t clock_khz = 100000;  // wall-clock rate
+  int stall = 0;               // test hook (mpcpcg_debug_set_wait)
+  size_t cache_limit = 32;     // signatures kept per cache
   // factorisation path workspace (allocated on first use): S rows, rhs / y, D^-1, lambda
   double *f_s = nullptr, *f_rhs = nullptr, *f_dinv = nullptr, *f_lam = nullptr;
   int *f_flag = nullptr;  // breakdown flag of a split single solve (kept at 0 between solves)
@@ -99,22 +182,22 @@ struct mpcpcg_ctx {
   void *tws = nullptr;
   Gang *gang = nullptr;
   int *queue = nullptr;
-  std::map<std::pair<std::vector<int64_t>, int>, std::unique_ptr<Schedule>> sched;
-  std::map<std::vector<int64_t>, int> tuned;  // horizon signature -> knots per workgroup
+  Lru<std::pair<Sig, int>, Schedule> sched;
+  Lru<Sig, Tuned> tuned;  // horizon signature -> batched PCG schedule choice
   // generic path (nx = 28)
   bool wide = false;
   double *w_S = nullptr, *w_Dinv = nullptr, *w_rhs = nullptr, *w_Qinv = nullptr, *w_RW = nullptr;
   double *w_lam = nullptr;  // lambda of the factorisation path
   int *w_flag = nullptr;    // per-problem breakdown flags of the factorisation path
   float *w_P = nullptr;
-  std::map<std::vector<int64_t>, std::unique_ptr<WideSchedule>> wsched;
+  Lru<Sig, WideSchedule> wsched;
   // control step: chunk lists and the line search's per-chunk partial sums (on first use)
-  std::map<std::vector<int64_t>, std::unique_ptr<CtrlSchedule>> csched;
+  Lru<Sig, CtrlSchedule> csched;
   double *ls_part = nullptr;
   // control step: the LQ problem and the step between its stages (on first use), graphs
   float *cs_ws = nullptr;
   hipStream_t cap_stream = nullptr;
-  std::map<std::vector<int64_t>, std::unique_ptr<CtrlGraph>> cgraph;
+  Lru<Sig, CtrlGraph> cgraph;
   std::string err;
 };
 
@@ -138,6 +221,27 @@ int fail(mpcpcg_ctx *c, int code, const char *fmt, ...) {
   } while (0)
 
 using KernelFn = void (*)(KArgs);
+
+const Sig &sig_of(const Sig &k) { return k; }
+const Sig &sig_of(const std::pair<Sig, int> &k) { return k.first; }
+
+// Makes room for one more entry in a cache of per-signature state by evicting the least
+// recently used entries.  A captured control step may hold the device arrays of an evicted
+// schedule, so the control-step graph of the same signature goes with it (drop_graphs).
+// The device is synchronised first: a launch still in flight may read what is freed.
+template <class Cache>
+void make_room(mpcpcg_ctx *c, Cache &cache, bool drop_graphs) {
+  if (cache.size() < c->cache_limit) return;
+  (void)hipDeviceSynchronize();
+  while (cache.size() > 0 && cache.size() >= c->cache_limit) {
+    auto it = cache.oldest();
+    if (drop_graphs) {
+      auto g = c->cgraph.m.find(sig_of(it->first));
+      if (g != c->cgraph.m.end()) c->cgraph.m.erase(g);
+    }
+    cache.m.erase(it);
+  }
+}
 
 template <int KPW>
 KernelFn kernel_for(int mode) {
@@ -210,6 +314,8 @@ KArgs base_args(mpcpcg_ctx *c, const mpcpcg_problem *p, const mpcpcg_opts *o) {
   a.tws = c->tws; a.gang = c->gang; a.queue = c->queue;
   a.qinv_ws = c->qinv_ws; a.rinv_ws = c->rinv_ws;
   if (o) { a.eps = o->eps; a.max_iter = o->max_iter; a.warm = o->warm_start; a.stop_abs = o->stop_rule; }
+  a.spin_limit = c->spin_ticks;
+  a.stall = c->stall;
   return a;
 }
 
@@ -235,7 +341,7 @@ int launch_single(mpcpcg_ctx *c, KArgs &a, int N, int kpw, int mode, hipStream_t
   // a gang of 2..16 parts runs on one XCD: launch 8 workgroups per part, of which the
   // ones dispatched to the first XCD (blockIdx % 8 == 0) take the parts.  Measured 3-4%
   // faster at N = 64..256 and 3% slower at 32 parts (N = 512), which stays spread.
-  a.one_xcd = (c->xcd_pin && g > 1 && g <= 16 && 8 * g <= cap) ? 1 : 0;
+  a.one_xcd = (c->xcd_ok && c->xcd_pin && g > 1 && g <= 16 && 8 * g <= cap) ? 1 : 0;
   hipLaunchKernelGGL(kernel_for(kpw, mode), dim3(a.one_xcd ? 8 * g : g), dim3(kpw * mpc::kGroup), 0, s, a);
   HIPCHK(c, hipGetLastError());
   return MPCPCG_OK;
@@ -258,17 +364,24 @@ int validate_batch(mpcpcg_ctx *c, int batch, const int64_t *off, const mpcpcg_pr
   return check_problem_ptrs(c, p, ctrl);
 }
 
-int pick_kpw(mpcpcg_ctx *c, const std::vector<int64_t> &off) {
-  if (c->kpw_override) return c->kpw_override;
-  auto it = c->tuned.find(off);
-  if (it != c->tuned.end()) return it->second;
-  return 16;
+// Schedule of the batched PCG launch for a signature: a fixed shape if one is set, else the
+// autotuned choice, else 16 knots per workgroup with the context's default placement.
+Tuned pick(mpcpcg_ctx *c, const Sig &off) {
+  Tuned t;
+  t.pin = c->xcd_pin;
+  if (c->kpw_override) {
+    t.kpw = c->kpw_override;
+    return t;
+  }
+  if (const Tuned *u = c->tuned.get(off)) return *u;
+  return t;
 }
+
+int pick_kpw(mpcpcg_ctx *c, const Sig &off) { return pick(c, off).kpw; }
 
 int get_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, int kpw, Schedule **out) {
   auto key = std::make_pair(off, kpw);
-  auto it = c->sched.find(key);
-  if (it != c->sched.end()) { *out = it->second.get(); return MPCPCG_OK; }
+  if (Schedule *hit = c->sched.get(key)) { *out = hit; return MPCPCG_OK; }
   const int B = (int)off.size() - 1;
   // longest-processing-time first: every problem runs ~the same number of iterations, so
   // its work is proportional to N; parts of one problem stay adjacent in the queue so a
@@ -308,12 +421,13 @@ int get_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, int kpw, Schedu
   s->kpw = kpw;
   s->ntasks = (int)tasks.size();
   s->nprobs = B;
-  HIPCHK(c, hipMalloc(&s->d_probs, sizeof(ProbDesc) * B));
-  HIPCHK(c, hipMalloc(&s->d_sorted, sizeof(ProbDesc) * B));
-  HIPCHK(c, hipMalloc(&s->d_tasks, sizeof(Task) * tasks.size()));
-  HIPCHK(c, hipMemcpy(s->d_probs, probs.data(), sizeof(ProbDesc) * B, hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(s->d_sorted, sorted.data(), sizeof(ProbDesc) * B, hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(s->d_tasks, tasks.data(), sizeof(Task) * tasks.size(), hipMemcpyHostToDevice));
+  s->d_probs = s->mem.upload(probs.data(), probs.size());
+  s->d_sorted = s->mem.upload(sorted.data(), sorted.size());
+  s->d_tasks = s->mem.upload(tasks.data(), tasks.size());
+  if (!s->d_probs || !s->d_sorted || !s->d_tasks) {
+    (void)hipGetLastError();
+    return fail(c, MPCPCG_ENOMEM, "cannot allocate the schedule of a %d-problem batch", B);
+  }
   for (int m = 0; m < 3; ++m) s->grid[m] = std::min(s->ntasks, cap);
   // Per-XCD lists: workgroups are dispatched to the eight XCDs in turn, so a full
   // persistent grid puts cap / 8 on each.  When every gang fits in that, each problem (in
@@ -325,7 +439,7 @@ int get_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, int kpw, Schedu
   constexpr int kXcds = 8;
   int max_parts = 0;
   for (const auto &d : sorted) max_parts = std::max(max_parts, d.nparts);
-  if (c->xcd_pin && B >= kXcds && cap % kXcds == 0 && max_parts <= cap / kXcds) {
+  if (c->xcd_ok && B >= kXcds && cap % kXcds == 0 && max_parts <= cap / kXcds) {
     std::vector<std::vector<int>> lists(kXcds);
     std::vector<int64_t> load(kXcds, 0);
     for (const auto &d : sorted) {
@@ -344,29 +458,18 @@ int get_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, int kpw, Schedu
       }
     }
     xoff[kXcds] = (int32_t)xtasks.size();
-    HIPCHK(c, hipMalloc(&s->d_xprobs, sizeof(ProbDesc) * B));
-    HIPCHK(c, hipMalloc(&s->d_xtasks, sizeof(Task) * xtasks.size()));
-    HIPCHK(c, hipMalloc(&s->d_xoff, sizeof(int32_t) * xoff.size()));
-    HIPCHK(c, hipMemcpy(s->d_xprobs, xprobs.data(), sizeof(ProbDesc) * B, hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(s->d_xtasks, xtasks.data(), sizeof(Task) * xtasks.size(), hipMemcpyHostToDevice));
-    HIPCHK(c, hipMemcpy(s->d_xoff, xoff.data(), sizeof(int32_t) * xoff.size(), hipMemcpyHostToDevice));
+    s->d_xprobs = s->mem.upload(xprobs.data(), xprobs.size());
+    s->d_xtasks = s->mem.upload(xtasks.data(), xtasks.size());
+    s->d_xoff = s->mem.upload(xoff.data(), xoff.size());
+    if (!s->d_xprobs || !s->d_xtasks || !s->d_xoff) {
+      (void)hipGetLastError();
+      return fail(c, MPCPCG_ENOMEM, "cannot allocate the per-XCD lists of a %d-problem batch", B);
+    }
     s->xgrid = cap;
   }
-  *out = s.get();
-  c->sched.emplace(key, std::move(s));
+  make_room(c, c->sched, true);
+  *out = c->sched.put(key, std::move(s));
   return MPCPCG_OK;
-}
-
-void free_schedule(Schedule *s) {
-  for (int m = 0; m < 3; ++m) {
-    if (s->exec[m]) (void)hipGraphExecDestroy(s->exec[m]);
-    if (s->graph[m]) (void)hipGraphDestroy(s->graph[m]);
-  }
-  if (s->d_probs) (void)hipFree(s->d_probs);
-  if (s->d_sorted) (void)hipFree(s->d_sorted);
-  if (s->d_tasks) (void)hipFree(s->d_tasks);
-  for (void *q : {(void *)s->d_xprobs, (void *)s->d_xtasks, (void *)s->d_xoff})
-    if (q) (void)hipFree(q);
 }
 
 int ensure_factor_ws(mpcpcg_ctx *c) {
@@ -490,8 +593,9 @@ int run_factor(mpcpcg_ctx *c, KArgs a, int mode, Schedule *s, int N, hipStream_t
   return launch_phase(c, a, mode, 2, s, N, stream);
 }
 
-int launch_batched(mpcpcg_ctx *c, Schedule *s, KArgs &a, int mode, hipStream_t stream) {
-  const bool pin = s->d_xoff != nullptr;
+int launch_batched(mpcpcg_ctx *c, Schedule *s, KArgs &a, int mode, int want_pin, hipStream_t stream) {
+  const bool pin = want_pin && s->d_xoff != nullptr;
+  const int x = pin ? 1 : 0;
   a.probs = pin ? s->d_xprobs : s->d_probs;
   a.tasks = pin ? s->d_xtasks : s->d_tasks;
   a.xoff = pin ? s->d_xoff : nullptr;
@@ -504,7 +608,7 @@ int launch_batched(mpcpcg_ctx *c, Schedule *s, KArgs &a, int mode, hipStream_t s
     HIPCHK(c, hipGetLastError());
     return MPCPCG_OK;
   }
-  void *params[] = {&s->args[mode]};
+  void *params[] = {&s->args[mode][x]};
   hipKernelNodeParams kp;
   std::memset(&kp, 0, sizeof kp);
   kp.func = reinterpret_cast<void *>(kernel_for(s->kpw, mode));
@@ -513,16 +617,16 @@ int launch_batched(mpcpcg_ctx *c, Schedule *s, KArgs &a, int mode, hipStream_t s
   kp.sharedMemBytes = 0;
   kp.kernelParams = params;
   kp.extra = nullptr;
-  if (!s->exec[mode]) {
-    s->args[mode] = a;
-    HIPCHK(c, hipGraphCreate(&s->graph[mode], 0));
-    HIPCHK(c, hipGraphAddKernelNode(&s->node[mode], s->graph[mode], nullptr, 0, &kp));
-    HIPCHK(c, hipGraphInstantiate(&s->exec[mode], s->graph[mode], nullptr, nullptr, 0));
-  } else if (std::memcmp(&s->args[mode], &a, sizeof a) != 0) {
-    s->args[mode] = a;
-    HIPCHK(c, hipGraphExecKernelNodeSetParams(s->exec[mode], s->node[mode], &kp));
+  if (!s->exec[mode][x]) {
+    s->args[mode][x] = a;
+    HIPCHK(c, hipGraphCreate(&s->graph[mode][x], 0));
+    HIPCHK(c, hipGraphAddKernelNode(&s->node[mode][x], s->graph[mode][x], nullptr, 0, &kp));
+    HIPCHK(c, hipGraphInstantiate(&s->exec[mode][x], s->graph[mode][x], nullptr, nullptr, 0));
+  } else if (std::memcmp(&s->args[mode][x], &a, sizeof a) != 0) {
+    s->args[mode][x] = a;
+    HIPCHK(c, hipGraphExecKernelNodeSetParams(s->exec[mode][x], s->node[mode][x], &kp));
   }
-  HIPCHK(c, hipGraphLaunch(s->exec[mode], stream));
+  HIPCHK(c, hipGraphLaunch(s->exec[mode][x], stream));
   return MPCPCG_OK;
 }
 
@@ -536,8 +640,7 @@ size_t wide_lds_bytes(int N, int nx, int nu) {
 }
 
 int wide_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, WideSchedule **out) {
-  auto it = c->wsched.find(off);
-  if (it != c->wsched.end()) { *out = it->second.get(); return MPCPCG_OK; }
+  if (WideSchedule *hit = c->wsched.get(off)) { *out = hit; return MPCPCG_OK; }
   const int B = (int)off.size() - 1;
   std::vector<mpc::wide::KnotDesc> kd;
   std::vector<mpc::wide::ProbDescW> pd(B);
@@ -570,14 +673,15 @@ int wide_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, WideSchedule *
   }
   w->at_root = (int64_t)tasks.size();
   for (int b = 0; b < B; ++b) tasks.push_back(mpc::wide::CrTask{b, 0});
-  HIPCHK(c, hipMalloc(&w->d_tasks, sizeof(mpc::wide::CrTask) * tasks.size()));
-  HIPCHK(c, hipMemcpy(w->d_tasks, tasks.data(), sizeof(mpc::wide::CrTask) * tasks.size(), hipMemcpyHostToDevice));
-  HIPCHK(c, hipMalloc(&w->d_knots, sizeof(mpc::wide::KnotDesc) * kd.size()));
-  HIPCHK(c, hipMalloc(&w->d_probs, sizeof(mpc::wide::ProbDescW) * B));
-  HIPCHK(c, hipMemcpy(w->d_knots, kd.data(), sizeof(mpc::wide::KnotDesc) * kd.size(), hipMemcpyHostToDevice));
-  HIPCHK(c, hipMemcpy(w->d_probs, pd.data(), sizeof(mpc::wide::ProbDescW) * B, hipMemcpyHostToDevice));
-  *out = w.get();
-  c->wsched.emplace(off, std::move(w));
+  w->d_tasks = w->mem.upload(tasks.data(), tasks.size());
+  w->d_knots = w->mem.upload(kd.data(), kd.size());
+  w->d_probs = w->mem.upload(pd.data(), pd.size());
+  if (!w->d_tasks || !w->d_knots || !w->d_probs) {
+    (void)hipGetLastError();
+    return fail(c, MPCPCG_ENOMEM, "cannot allocate the schedule of a %d-problem batch", B);
+  }
+  make_room(c, c->wsched, true);
+  *out = c->wsched.put(off, std::move(w));
   return MPCPCG_OK;
 }
 
@@ -665,8 +769,7 @@ constexpr int64_t kCtrlLongFrom = 16384;  // knots in the batch
 int64_t ctrl_max_chunks(const mpcpcg_ctx *c) { return c->max_knots / kCtrlShort + c->max_batch; }
 
 int ctrl_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, CtrlSchedule **out) {
-  auto it = c->csched.find(off);
-  if (it != c->csched.end()) { *out = it->second.get(); return MPCPCG_OK; }
+  if (CtrlSchedule *hit = c->csched.get(off)) { *out = hit; return MPCPCG_OK; }
   const int B = (int)off.size() - 1;
   const int len = off.back() >= kCtrlLongFrom ? kCtrlLong : kCtrlShort;
   std::vector<mpc::ctrl::Chunk> ch;
@@ -684,10 +787,13 @@ int ctrl_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, CtrlSchedule *
   if ((int64_t)ch.size() > ctrl_max_chunks(c)) return fail(c, MPCPCG_EINVAL, "batch exceeds the control-step workspace");
   auto cs = std::make_unique<CtrlSchedule>();
   cs->nchunks = (int)ch.size();
-  HIPCHK(c, hipMalloc(&cs->d_chunks, sizeof(mpc::ctrl::Chunk) * ch.size()));
-  HIPCHK(c, hipMemcpy(cs->d_chunks, ch.data(), sizeof(mpc::ctrl::Chunk) * ch.size(), hipMemcpyHostToDevice));
-  *out = cs.get();
-  c->csched.emplace(off, std::move(cs));
+  cs->d_chunks = cs->mem.upload(ch.data(), ch.size());
+  if (!cs->d_chunks) {
+    (void)hipGetLastError();
+    return fail(c, MPCPCG_ENOMEM, "cannot allocate the control-step chunk list");
+  }
+  make_room(c, c->csched, true);
+  *out = c->csched.put(off, std::move(cs));
   return MPCPCG_OK;
 }
 
@@ -747,6 +853,13 @@ int mpcpcg_create(mpcpcg_ctx **out, int32_t nx, int32_t nu, int64_t max_total_kn
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return MPCPCG_EHIP;
   c->cus = prop.multiProcessorCount;
+  int nxcc = 0, khz = 0;
+  if (hipDeviceGetAttribute(&nxcc, hipDeviceAttributeNumberOfXccs, c->device) != hipSuccess) nxcc = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) != hipSuccess || khz <= 0) khz = 100000;
+  (void)hipGetLastError();
+  c->xcd_ok = (nxcc == 8 && c->cus % 8 == 0) ? 1 : 0;
+  c->clock_khz = khz;
+  c->spin_ticks = (int64_t)2000 * khz;  // 2 s
   const size_t K = (size_t)max_total_knots;
   if (wide) {
     const size_t MM = (size_t)nx * nx;
@@ -786,7 +899,10 @@ int mpcpcg_create(mpcpcg_ctx **out, int32_t nx, int32_t nu, int64_t max_total_kn
 int mpcpcg_destroy(mpcpcg_ctx *c) {
   if (!c) return MPCPCG_OK;
   (void)hipDeviceSynchronize();
-  for (auto &kv : c->sched) free_schedule(kv.second.get());
+  c->cgraph.m.clear();
+  c->sched.m.clear();
+  c->csched.m.clear();
+  c->wsched.m.clear();
   for (double *q : {c->f_s, c->f_rhs, c->f_dinv, c->f_lam})
     if (q) (void)hipFree(q);
   if (c->f_flag) (void)hipFree(c->f_flag);
@@ -795,20 +911,9 @@ int mpcpcg_destroy(mpcpcg_ctx *c) {
   if (c->tws) (void)hipFree(c->tws);
   if (c->gang) (void)hipFree(c->gang);
   if (c->queue) (void)hipFree(c->queue);
-  for (auto &kv : c->csched)
-    if (kv.second->d_chunks) (void)hipFree(kv.second->d_chunks);
   if (c->ls_part) (void)hipFree(c->ls_part);
-  for (auto &kv : c->cgraph) {
-    if (kv.second->exec) (void)hipGraphExecDestroy(kv.second->exec);
-    if (kv.second->graph) (void)hipGraphDestroy(kv.second->graph);
-  }
   if (c->cs_ws) (void)hipFree(c->cs_ws);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-  for (auto &kv : c->wsched) {
-    if (kv.second->d_knots) (void)hipFree(kv.second->d_knots);
-    if (kv.second->d_probs) (void)hipFree(kv.second->d_probs);
-    if (kv.second->d_tasks) (void)hipFree(kv.second->d_tasks);
-  }
   for (void *p : {(void *)c->w_S, (void *)c->w_Dinv, (void *)c->w_P, (void *)c->w_rhs, (void *)c->w_lam, (void *)c->w_Qinv,
                   (void *)c->w_RW, (void *)c->w_flag})
     if (p) (void)hipFree(p);
@@ -877,12 +982,13 @@ int mpcpcg_solve_batched(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const
     return wide_run(c, key, w, false, s);
   }
   const bool fac = use_factor(c, key, o->warm_start != 0);
+  const Tuned tu = pick(c, key);
   Schedule *sc = nullptr;
-  if ((st = get_schedule(c, key, fac ? 16 : pick_kpw(c, key), &sc))) return st;
+  if ((st = get_schedule(c, key, fac ? 16 : tu.kpw, &sc))) return st;
   KArgs a = base_args(c, p, o);
   a.lam = lambda; a.dx = dx; a.du = du; a.stats = stats;
   if (fac) return run_factor(c, a, mpc::kForward, sc, 0, s);
-  return launch_batched(c, sc, a, mpc::kForward, s);
+  return launch_batched(c, sc, a, mpc::kForward, tu.pin, s);
 }
 
 int mpcpcg_backward(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const mpcpcg_problem *p,
@@ -911,8 +1017,9 @@ int mpcpcg_backward(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const mpcp
     return wide_run(c, key, w, false, s);
   }
   const bool fac = use_factor(c, key, false);  // the adjoint solve starts cold
+  const Tuned tu = pick(c, key);
   Schedule *sc = nullptr;
-  if ((st = get_schedule(c, key, fac ? 16 : pick_kpw(c, key), &sc))) return st;
+  if ((st = get_schedule(c, key, fac ? 16 : tu.kpw, &sc))) return st;
   KArgs a = base_args(c, p, o);
   a.warm = 0;
   a.lam_in = lambda; a.dx_in = dx; a.du_in = du;
@@ -920,7 +1027,7 @@ int mpcpcg_backward(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const mpcp
   a.dQ = dQ; a.dR = dR; a.dA = dA; a.dB = dB; a.dq = dq; a.dr = dr; a.dx0 = dx0; a.de = de;
   a.dgamma = dgamma; a.stats = stats;
   if (fac) return run_factor(c, a, mpc::kAdjoint, sc, 0, s);
-  return launch_batched(c, sc, a, mpc::kAdjoint, s);
+  return launch_batched(c, sc, a, mpc::kAdjoint, tu.pin, s);
 }
 
 int mpcpcg_set_knots_per_group(mpcpcg_ctx *c, int32_t k) {
@@ -956,36 +1063,125 @@ int mpcpcg_autotune(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const mpcp
     if (kpw_out) *kpw_out = 0;
     return MPCPCG_OK;
   }
-  std::vector<int64_t> key(off, off + batch + 1);
-  const int saved = c->kpw_override;
-  hipEvent_t e0, e1;
-  HIPCHK(c, hipEventCreate(&e0));
-  HIPCHK(c, hipEventCreate(&e1));
-  int best = 0;
+  const Sig key(off, off + batch + 1);
+  // the trials run PCG with a fixed shape and placement; the context's settings and the
+  // events are restored / released on every exit
+  struct Guard {
+    mpcpcg_ctx *c;
+    int kpw, pin, method;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Guard() {
+      c->kpw_override = kpw;
+      c->xcd_pin = pin;
+      c->method = method;
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } g{c, c->kpw_override, c->xcd_pin, c->method};
+  HIPCHK(c, hipEventCreate(&g.e0));
+  HIPCHK(c, hipEventCreate(&g.e1));
+  c->method = MPCPCG_METHOD_PCG;
+  std::vector<mpcpcg_stats> hst((size_t)batch);
+  Tuned best;
+  best.kpw = 0;
   float best_ms = 0.f;
   for (int k : kKpwChoices) {
-    c->kpw_override = k;
     Schedule *sc = nullptr;
     if (get_schedule(c, key, k, &sc) != MPCPCG_OK) continue;  // shape cannot hold a horizon
-    float ms_min = 0.f;
-    bool okk = true;
-    for (int rep = 0; rep < 4 && okk; ++rep) {
-      HIPCHK(c, hipEventRecord(e0, s));
-      if (mpcpcg_solve_batched(c, batch, off, p, o, lambda, dx, du, stats, s) != MPCPCG_OK) okk = false;
-      HIPCHK(c, hipEventRecord(e1, s));
-      HIPCHK(c, hipEventSynchronize(e1));
-      float ms = 0.f;
-      HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-      if (rep > 0 && (ms_min == 0.f || ms < ms_min)) ms_min = ms;
+    for (int pin = 0; pin < 2; ++pin) {
+      if (pin && !sc->d_xoff) continue;  // the batch does not qualify for per-XCD lists
+      c->kpw_override = k;
+      c->xcd_pin = pin;
+      float ms_min = 0.f;
+      bool ok = true;
+      for (int rep = 0; rep < 4 && ok; ++rep) {
+        HIPCHK(c, hipEventRecord(g.e0, s));
+        if (mpcpcg_solve_batched(c, batch, off, p, o, lambda, dx, du, stats, s) != MPCPCG_OK) ok = false;
+        HIPCHK(c, hipEventRecord(g.e1, s));
+        HIPCHK(c, hipEventSynchronize(g.e1));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, g.e0, g.e1));
+        if (rep > 0 && (ms_min == 0.f || ms < ms_min)) ms_min = ms;
+      }
+      if (!ok) continue;
+      // a shape whose solves broke down or timed out does not qualify
+      HIPCHK(c, hipMemcpy(hst.data(), stats, sizeof(mpcpcg_stats) * (size_t)batch, hipMemcpyDeviceToHost));
+      for (const auto &x : hst)
+        if (x.status == MPCPCG_BREAKDOWN || x.status == MPCPCG_TIMEOUT) ok = false;
+      if (ok && (best.kpw == 0 || ms_min < best_ms)) {
+        best.kpw = k;
+        best.pin = pin;
+        best_ms = ms_min;
+      }
     }
-    if (okk && (best == 0 || ms_min < best_ms)) { best = k; best_ms = ms_min; }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  c->kpw_override = saved;
-  if (!best) return fail(c, MPCPCG_EINVAL, "no workgroup shape can run this batch");
-  c->tuned[key] = best;
-  if (kpw_out) *kpw_out = best;
+  if (!best.kpw) return fail(c, MPCPCG_EINVAL, "no workgroup shape can run this batch");
+  make_room(c, c->tuned, false);
+  c->tuned.put(key, std::make_unique<Tuned>(best));
+  if (kpw_out) *kpw_out = best.kpw;
+  return MPCPCG_OK;
+}
+
+int mpcpcg_tuned_schedule(mpcpcg_ctx *c, int32_t batch, const int64_t *off, int32_t *kpw_out,
+                          int32_t *pinned_out) {
+  if (!c) return MPCPCG_EINVAL;
+  if (batch < 1 || !off || off[0] != 0) return fail(c, MPCPCG_EINVAL, "batch must be >= 1 and knot_off[0] = 0");
+  for (int b = 0; b < batch; ++b)
+    if (off[b + 1] - off[b] < 1) return fail(c, MPCPCG_EINVAL, "problem %d has N < 1", b);
+  if (c->wide) {
+    if (kpw_out) *kpw_out = 0;
+    if (pinned_out) *pinned_out = 0;
+    return MPCPCG_OK;
+  }
+  const Sig key(off, off + batch + 1);
+  const Tuned t = pick(c, key);
+  Schedule *sc = nullptr;
+  int st = get_schedule(c, key, t.kpw, &sc);
+  if (st) return st;
+  if (kpw_out) *kpw_out = t.kpw;
+  if (pinned_out) *pinned_out = (t.pin && sc->d_xoff) ? 1 : 0;
+  return MPCPCG_OK;
+}
+
+int mpcpcg_set_xcd_pinning(mpcpcg_ctx *c, int32_t enable) {
+  if (!c) return MPCPCG_EINVAL;
+  c->xcd_pin = enable ? 1 : 0;
+  return MPCPCG_OK;
+}
+
+int mpcpcg_set_cache_limit(mpcpcg_ctx *c, int32_t max_signatures) {
+  if (!c) return MPCPCG_EINVAL;
+  if (max_signatures < 1) return fail(c, MPCPCG_EINVAL, "the cache limit must be >= 1");
+  c->cache_limit = (size_t)max_signatures;
+  // trim every cache to the new limit (make_room leaves limit - 1 entries)
+  c->cache_limit += 1;
+  make_room(c, c->sched, true);
+  make_room(c, c->wsched, true);
+  make_room(c, c->csched, true);
+  make_room(c, c->cgraph, false);
+  make_room(c, c->tuned, false);
+  c->cache_limit -= 1;
+  return MPCPCG_OK;
+}
+
+int mpcpcg_cache_info(const mpcpcg_ctx *c, int32_t *entries, int64_t *device_bytes) {
+  if (!c) return MPCPCG_EINVAL;
+  int64_t bytes = 0;
+  for (const auto &kv : c->sched.m) bytes += kv.second.v->mem.bytes;
+  for (const auto &kv : c->wsched.m) bytes += kv.second.v->mem.bytes;
+  for (const auto &kv : c->csched.m) bytes += kv.second.v->mem.bytes;
+  if (entries)
+    *entries = (int32_t)(c->sched.size() + c->wsched.size() + c->csched.size() + c->cgraph.size() + c->tuned.size());
+  if (device_bytes) *device_bytes = bytes;
+  return MPCPCG_OK;
+}
+
+int mpcpcg_debug_set_wait(mpcpcg_ctx *c, int64_t limit_us, int32_t inject_stall) {
+  if (!c) return MPCPCG_EINVAL;
+  if (limit_us < 1 || limit_us > (int64_t)600 * 1000000) return fail(c, MPCPCG_EINVAL, "limit_us must be in [1, 6e8]");
+  c->spin_ticks = limit_us * c->clock_khz / 1000;
+  if (c->spin_ticks < 1) c->spin_ticks = 1;
+  c->stall = inject_stall ? 1 : 0;
   return MPCPCG_OK;
 }
 
@@ -1101,9 +1297,11 @@ int mpcpcg_control_step(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const 
       f32(o->eps), (uint64_t)(uint32_t)o->max_iter, (uint64_t)o->warm_start, (uint64_t)o->stop_rule,
       (uint64_t)sqp_iters, f32(mu), u64(lambda), u64(X_out), u64(U_out), u64(merit), u64(choice), u64(stats),
       (uint64_t)c->method, (uint64_t)c->kpw_override, (uint64_t)pick_kpw(c, key)};
-  auto &slot = c->cgraph[key];
-  if (!slot) slot = std::make_unique<CtrlGraph>();
-  CtrlGraph *g = slot.get();
+  CtrlGraph *g = c->cgraph.get(key);
+  if (!g) {
+    make_room(c, c->cgraph, false);
+    g = c->cgraph.put(key, std::make_unique<CtrlGraph>());
+  }
   if (g->sig != sig) {
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
@@ -1115,6 +1313,28 @@ int mpcpcg_control_step(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const 
   }
   if (g->calls++ == 0)  // the first call runs eagerly and creates every schedule and workspace
     return control_body(c, batch, off, m, t, o, sqp_iters, mu, lambda, X_out, U_out, merit, choice, stats, s);
+  // Nothing may be allocated or freed while the launches are captured: make sure every
+  // schedule the step uses is cached (another signature may have evicted one since the
+  // first call).  None of these inserts evicts this signature's graph, which is the newest.
+  {
+    CtrlSchedule *cs = nullptr;
+    if ((st = ctrl_schedule(c, key, &cs))) return st;
+    if (c->wide) {
+      WideSchedule *w = nullptr;
+      if ((st = wide_schedule(c, key, &w))) return st;
+    } else {
+      const bool fac = use_factor(c, key, o->warm_start != 0);
+      Schedule *sc = nullptr;
+      if ((st = get_schedule(c, key, fac ? 16 : pick_kpw(c, key), &sc))) return st;
+    }
+    g = c->cgraph.get(key);
+    if (!g) {  // dropped with an evicted schedule of the same horizons: start it afresh
+      make_room(c, c->cgraph, false);
+      g = c->cgraph.put(key, std::make_unique<CtrlGraph>());
+      g->sig = sig;
+      g->calls = 2;
+    }
+  }
   // the second captures the same launches on the context's own stream and replays them
   if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
   HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));

@@ -48,7 +48,9 @@ struct Task {
 struct alignas(256) Gang {
   int done;        // parts finished with the problem
   int abort;       // set when a part gave up waiting
-  int pad[62];
+  int timed_out;   // factorisation path: set by the formation launch when a part gave up,
+                   // read and cleared by the primal-step launch (reports TIMEOUT)
+  int pad[61];
 };
 
 // Tagged words of the loop barriers, per task: (tag << 32) | 32-bit payload with tag =
@@ -134,9 +136,22 @@ struct KArgs {
   int32_t max_iter;
   int32_t warm;
   int32_t stop_abs;      // 1: eta < eps; 0: sqrt(eta / eta_ref) < eps
+  // every cross-workgroup wait gives up after this many wall-clock ticks (the host sets
+  // 2 s); a part that gives up raises its gang's abort flag and the problem reports TIMEOUT
+  int64_t spin_limit;
+  int32_t stall;         // test hook: the formation barrier waits for a flag never written
+  int32_t pad_opts;
 };
 
-constexpr long long kSpinLimitTicks = 200000000LL;  // 2 s at the 100 MHz wall clock
+// Writes one problem's stats with device-scope stores, so that a later override of the
+// status by another part of the gang (TIMEOUT) is ordered after it through the gang counter.
+__device__ __forceinline__ void put_stats(mpcpcg_stats *s, int iters, int status, float ratio) {
+  int *w = reinterpret_cast<int *>(s);
+  __hip_atomic_store(w + 0, iters, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(w + 1, status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(w + 2, __builtin_bit_cast(int, ratio), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(w + 3, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Wave-uniform copies (kept in SGPRs): values every lane of the workgroup shares.
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -299,7 +314,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       __builtin_amdgcn_s_sleep(1);
       if ((++polls & 63) == 0) {
         if (__hip_atomic_load(&gang->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return 1;
-        if (wall_clock64() - t_start > kSpinLimitTicks) {
+        if (wall_clock64() - t_start > a.spin_limit) {
           __hip_atomic_store(&gang->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           return 1;
         }
@@ -311,10 +326,15 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
     auto sync_point = [&](auto nd_c, auto nr_c, int ph) {
       constexpr int ND = decltype(nd_c)::value, NR = decltype(nr_c)::value;
       __syncthreads();
-      if (multi) {
+      if (multi && aborted) {
+        // the gang has given up: no part waits any more (outputs are undefined)
+        ++nsync;
+      } else if (multi) {
         if (wave == 0) {
           const int par = nsync & 1;
           const uint32_t tag = (uint32_t)nsync + 1u;
+          // test hook: the launch's first wait expects a tag that no part writes
+          const uint32_t want_tag = (a.stall && nsync == 0) ? 0xffffffffu : tag;
           if (NR > 0 && wl < NR) {  // this part's sum of value wl, its waves in order
             double ps = 0.0;
 #pragma unroll
@@ -347,14 +367,14 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
 #pragma unroll
                 for (int v = 0; v < NR; ++v) {
                   rw[v] = load_pair(wsr, ws_off(rsrc->red[par][v]));
-                  ok &= pair_has(rw[v], tag);
+                  ok &= pair_has(rw[v], want_tag);
                 }
               }
               if (halo) {
 #pragma unroll
                 for (int c = 0; c < ND; ++c) {
                   hq[c] = load_pair(wsr, ws_off(hsrc->hv[par][c][srcside][l]));
-                  ok &= pair_has(hq[c], tag);
+                  ok &= pair_has(hq[c], want_tag);
                 }
               }
               if (__ballot(ok) == ~0ull) break;
@@ -381,7 +401,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         }
         __syncthreads();
         ++nsync;
-        aborted = uni(sh_abort) != 0;
+        aborted = aborted || uni(sh_abort) != 0;
       } else {
         if (tid == 0) {
           double s0 = 0.0, s1 = 0.0;
@@ -404,6 +424,8 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       __syncthreads();
       if (multi) {
         const uint64_t epoch = (gen << 32) | 1u;
+        // test hook: wait for an epoch that no part ever writes, so every wait gives up
+        const uint64_t need = a.stall ? ~0ull : epoch;
         if (wave == 0) {
           if (wl == 0) __hip_atomic_store(&tws[my_t].flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           const long long t_start = wall_clock64();
@@ -412,7 +434,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
           const int nb = wl == 0 ? part - 1 : part + 1;
           const bool want = wl < 2 && nb >= 0 && nb < G;
           while (true) {
-            const bool seen = !want || __hip_atomic_load(&tws[pd.t0 + nb].flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+            const bool seen = !want || __hip_atomic_load(&tws[pd.t0 + nb].flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
             if (__ballot(seen) == ~0ull) break;
             if ((ab = poll_spin(polls, t_start))) break;
           }
@@ -430,7 +452,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         }
         __syncthreads();
         ++nsync;
-        aborted = uni(sh_abort) != 0;
+        aborted = aborted || uni(sh_abort) != 0;
       }
     };
 
@@ -442,6 +464,10 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       if (!multi) {
         for (int t = tid; t < 2 * NX * kPRow; t += NT) pl[KPW * NX * kPRow + t] = 0.0f;
         __syncthreads();
+        return;
+      }
+      if (aborted) {  // the gang has given up: no part waits any more
+        ++nsync;
         return;
       }
       const uint64_t epoch = (gen << 32) | 2u;
@@ -481,7 +507,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       }
       __syncthreads();
       ++nsync;
-      aborted = uni(sh_abort) != 0;
+      aborted = aborted || uni(sh_abort) != 0;
     };
 
     // publish this group's value of a double vector channel (LDS + boundary halo)
@@ -1004,14 +1030,9 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
           a.dr[(cb - 1) * NU + lane] = (float)n1u;
         }
       }
-      if (PHASE == 0 && tid == 0 && part == 0) {
-        mpcpcg_stats st;
-        st.iters = it;
-        st.status = status;
-        st.final_ratio = eta_ref > 0.0 ? (float)__builtin_sqrt(eta_new > 0.0 ? eta_new / eta_ref : 0.0) : 0.0f;
-        st.reserved = 0;
-        a.stats[pd.id] = st;
-      }
+      if (PHASE == 0 && tid == 0 && part == 0)
+        put_stats(a.stats + pd.id, it, status,
+                  eta_ref > 0.0 ? (float)__builtin_sqrt(eta_new > 0.0 ? eta_new / eta_ref : 0.0) : 0.0f);
     }
 
     // ------------------------------------------------------------- gang teardown
@@ -1032,6 +1053,21 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
           __hip_atomic_store(w, (uint64_t)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (tid == 0) {
+          // a part that gave up raised the abort flag: the problem reports TIMEOUT (part 0
+          // wrote its stats before its arrival was counted, so this store comes later)
+          const int ab = __hip_atomic_load(&gang->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          int *status_word = a.stats ? reinterpret_cast<int *>(a.stats + pd.id) + 1 : nullptr;
+          if constexpr (PHASE == 1) {
+            if (ab) __hip_atomic_store(&gang->timed_out, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          } else if constexpr (PHASE == 2) {
+            const int t1 = __hip_atomic_load(&gang->timed_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((ab || t1) && status_word)
+              __hip_atomic_store(status_word, (int)MPCPCG_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&gang->timed_out, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          } else if constexpr (MODE != kForm) {
+            if (ab && status_word)
+              __hip_atomic_store(status_word, (int)MPCPCG_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
           __hip_atomic_store(&gang->abort, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           __hip_atomic_store(&gang->done, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -1040,11 +1076,23 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
   }
 
   // ------------------------------------------------------------- launch teardown
-  // The last workgroup out resets the queue and advances the launch generation.
+  // The last workgroup out resets the queue and advances the launch generation.  With
+  // per-XCD lists it first checks that every list was drained: a list whose XCD ran no
+  // workgroup of this launch (a placement the host did not expect) leaves its problems
+  // unsolved, and those report TIMEOUT instead of stale stats.
   __syncthreads();
   if (tid == 0) {
     const int d = __hip_atomic_fetch_add(&a.queue[1], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     if (d == (int)gridDim.x - 1) {
+      if (a.persistent && a.xoff && a.stats) {
+        for (int x = 0; x < 8; ++x) {
+          const int popped = __hip_atomic_load(&a.queue[4 + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          for (int t = a.xoff[x] + max(popped, 0); t < a.xoff[x + 1]; ++t) {
+            const Task tk = a.tasks[t];
+            if (tk.part == 0) put_stats(a.stats + a.probs[tk.prob].id, 0, MPCPCG_TIMEOUT, 0.0f);
+          }
+        }
+      }
       __hip_atomic_store(&a.queue[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       for (int x = 0; x < 8; ++x) __hip_atomic_store(&a.queue[4 + x], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_fetch_add(&a.queue[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

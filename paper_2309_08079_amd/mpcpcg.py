@@ -79,6 +79,11 @@ def load_library(path: str = _LIB_PATH):
     lib.mpcpcg_set_method.argtypes = [vp, i32]
     lib.mpcpcg_set_graph.argtypes = [vp, i32]
     lib.mpcpcg_autotune.argtypes = [vp, i32, i64p, P, O, vp, vp, vp, vp, vp, C.POINTER(i32)]
+    lib.mpcpcg_tuned_schedule.argtypes = [vp, i32, i64p, C.POINTER(i32), C.POINTER(i32)]
+    lib.mpcpcg_set_xcd_pinning.argtypes = [vp, i32]
+    lib.mpcpcg_set_cache_limit.argtypes = [vp, i32]
+    lib.mpcpcg_cache_info.argtypes = [vp, C.POINTER(i32), C.POINTER(C.c_int64)]
+    lib.mpcpcg_debug_set_wait.argtypes = [vp, C.c_int64, i32]
     M, T = C.POINTER(ChainModel), C.POINTER(Trajectory)
     lib.mpcpcg_linearize.argtypes = [vp, i32, i64p, M, T] + [vp] * 6 + [vp]
     lib.mpcpcg_line_search.argtypes = [vp, i32, i64p, M, T, vp, vp, vp, C.c_float] + [vp] * 4 + [vp]
@@ -86,7 +91,9 @@ def load_library(path: str = _LIB_PATH):
     for f in ("mpcpcg_create", "mpcpcg_destroy", "mpcpcg_form_schur", "mpcpcg_solve",
               "mpcpcg_solve_batched", "mpcpcg_backward", "mpcpcg_set_knots_per_group",
               "mpcpcg_set_graph", "mpcpcg_autotune", "mpcpcg_set_method", "mpcpcg_linearize",
-              "mpcpcg_line_search", "mpcpcg_control_step"):
+              "mpcpcg_line_search", "mpcpcg_control_step", "mpcpcg_tuned_schedule",
+              "mpcpcg_set_xcd_pinning", "mpcpcg_set_cache_limit", "mpcpcg_cache_info",
+              "mpcpcg_debug_set_wait"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -275,6 +282,30 @@ class Context:
             _stream(), C.byref(k)), "mpcpcg_autotune")
         return k.value
 
+    def mpcpcg_tuned_schedule(self, knot_off):
+        """(knots per workgroup, gangs pinned to one XCD) of the next batched PCG solve."""
+        off = np.ascontiguousarray(knot_off, dtype=np.int64)
+        k, x = C.c_int32(0), C.c_int32(0)
+        self._check(self.lib.mpcpcg_tuned_schedule(self.h, len(off) - 1, off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                                   C.byref(k), C.byref(x)), "mpcpcg_tuned_schedule")
+        return k.value, bool(x.value)
+
+    def mpcpcg_set_xcd_pinning(self, enable):
+        self._check(self.lib.mpcpcg_set_xcd_pinning(self.h, int(bool(enable))), "mpcpcg_set_xcd_pinning")
+
+    def mpcpcg_set_cache_limit(self, n):
+        self._check(self.lib.mpcpcg_set_cache_limit(self.h, int(n)), "mpcpcg_set_cache_limit")
+
+    def mpcpcg_cache_info(self):
+        """(cached entries over all signature caches, device bytes of cached schedules)."""
+        n, b = C.c_int32(0), C.c_int64(0)
+        self._check(self.lib.mpcpcg_cache_info(self.h, C.byref(n), C.byref(b)), "mpcpcg_cache_info")
+        return n.value, b.value
+
+    def mpcpcg_debug_set_wait(self, limit_us, inject_stall=False):
+        self._check(self.lib.mpcpcg_debug_set_wait(self.h, int(limit_us), int(bool(inject_stall))),
+                    "mpcpcg_debug_set_wait")
+
 
     # ---- control step around the solve ----------------------------------------------------
     def mpcpcg_linearize(self, model, traj, knot_off, out=None):
@@ -344,20 +375,39 @@ def to_device(d, device="cuda"):
     return {k: torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32)).to(device) for k, v in d.items()}
 
 
+STATUS_NAMES = {OK: "OK", NOT_CONVERGED: "NOT_CONVERGED", BREAKDOWN: "BREAKDOWN", TIMEOUT: "TIMEOUT"}
+
+
+def check_stats(stats, what):
+    """Raise MPCPCGError unless every problem of a device stats tensor reports OK (one small
+    device-to-host read, which synchronises the stream)."""
+    st = stats_to_numpy(stats)
+    bad = np.nonzero(st["status"] != OK)[0]
+    if bad.size:
+        b = int(bad[0])
+        raise MPCPCGError("%s: problem %d of %d reports %s after %d iterations (%d problems not OK)"
+                          % (what, b, st.size, STATUS_NAMES.get(int(st["status"][b]), str(st["status"][b])),
+                             int(st["iters"][b]), bad.size))
+
+
 class MPCPCGFunction(torch.autograd.Function):
-    """lambda, dx, du = MPCPCGFunction.apply(ctx, knot_off, eps, Q, R, A, B, q, r, x0, e).
+    """lambda, dx, du = MPCPCGFunction.apply(ctx, knot_off, eps, Q, R, A, B, q, r, x0, e[, max_iter]).
 
     Forward: mpcpcg_solve_batched.  Backward: mpcpcg_backward (adjoint PCG with the same
     stopping rule); returns gradients for Q, R, A, B, q, r, x0, e (symmetric part for Q, R).
+    Both directions read the solver's stats and raise MPCPCGError if any problem did not
+    converge (NOT_CONVERGED, BREAKDOWN or TIMEOUT), so that no unconverged iterate or
+    undefined output flows into autograd.
     """
 
     @staticmethod
-    def forward(fctx, mctx, knot_off, eps, Q, R, A, B, q, r, x0, e):
+    def forward(fctx, mctx, knot_off, eps, Q, R, A, B, q, r, x0, e, max_iter=0):
         packed = dict(Q=Q.contiguous(), R=R.contiguous(), A=A.contiguous(), B=B.contiguous(),
                       q=q.contiguous(), r=r.contiguous(), x0=x0.contiguous(),
                       e=None if e is None else e.contiguous())
-        out = mctx.mpcpcg_solve_batched(packed, knot_off, eps=eps)
-        fctx.mctx, fctx.off, fctx.eps = mctx, np.asarray(knot_off, dtype=np.int64), eps
+        out = mctx.mpcpcg_solve_batched(packed, knot_off, eps=eps, max_iter=max_iter)
+        check_stats(out["stats"], "MPCPCGFunction forward (mpcpcg_solve_batched)")
+        fctx.mctx, fctx.off, fctx.eps, fctx.max_iter = mctx, np.asarray(knot_off, dtype=np.int64), eps, max_iter
         fctx.packed = packed
         fctx.save_for_backward(out["lam"], out["dx"], out["du"])
         fctx.has_e = e is not None
@@ -370,6 +420,8 @@ class MPCPCGFunction(torch.autograd.Function):
         zero_like = lambda t, ref: torch.zeros_like(ref) if t is None else t.contiguous()
         g = fctx.mctx.mpcpcg_backward(fctx.packed, fctx.off, dict(lam=lam, dx=dx, du=du),
                                       zero_like(glam, lam), None if gdx is None else gdx.contiguous(),
-                                      None if gdu is None else gdu.contiguous(), eps=fctx.eps)
+                                      None if gdu is None else gdu.contiguous(), eps=fctx.eps,
+                                      max_iter=fctx.max_iter)
+        check_stats(g["stats"], "MPCPCGFunction backward (mpcpcg_backward)")
         return (None, None, None, g["dQ"], g["dR"], g["dA"], g["dB"], g["dq"], g["dr"], g["dx0"],
-                g["de"] if fctx.has_e else None)
+                g["de"] if fctx.has_e else None, None)

@@ -276,16 +276,24 @@ def check_grads(g, ref, off, tol=1e-4, it_tol=lambda iters: 1):
                 assert rel(out[k][c0:c1], ref[k][c0:c1]) < tol, (k, b)
 
 
+def oracle_saved_forward(packed, off):
+    """The oracle's forward solve, rounded to FP32 as the saved outputs a caller would hold
+    (device tensors for the GPU adjoint, float64 copies of the same values for the oracle's)."""
+    fo = orc.solve_batch(packed, off, eps=EPS, threads=8)
+    f32 = {k: fo[k].astype(np.float32) for k in ("lam", "dx", "du")}
+    return {k: torch.from_numpy(v).cuda() for k, v in f32.items()}, {k: v.astype(np.float64) for k, v in f32.items()}
+
+
 @pytest.mark.parametrize("Ns,seed0", [([8], 4000), ([1, 3, 17, 40], 4100)])
 def test_backward_matches_oracle_adjoint(ctx, Ns, seed0):
+    # the adjoint alone: both sides take the oracle's forward outputs and dL/dlambda = 2 lambda
     probs, packed, off = _batch_case(Ns, seed0)
     d = dev(packed)
-    f = ctx.mpcpcg_solve_batched(d, off, eps=EPS)
-    gl = 2 * f["lam"]
-    g = ctx.mpcpcg_backward(d, off, f, gl, eps=EPS)
+    fdev, fwd = oracle_saved_forward(packed, off)
+    gl = (2 * fwd["lam"]).astype(np.float32)
+    g = ctx.mpcpcg_backward(d, off, fdev, torch.from_numpy(gl).cuda(), eps=EPS)
     torch.cuda.synchronize()
-    fwd = {k: f[k].cpu().numpy().astype(np.float64) for k in ("lam", "dx", "du")}
-    ref = orc.backward_batch(packed, off, fwd, gl.cpu().numpy().astype(np.float64), eps=EPS, threads=8)
+    ref = orc.backward_batch(packed, off, fwd, gl.astype(np.float64), eps=EPS, threads=8)
     check_grads(g, ref, off)
     assert rel(g["dgamma"].cpu().numpy(), ref["mu"]) < 1e-4
 
@@ -293,14 +301,13 @@ def test_backward_matches_oracle_adjoint(ctx, Ns, seed0):
 def test_backward_with_primal_gradients(ctx):
     probs, packed, off = _batch_case([20, 9], 4200)
     d = dev(packed)
-    f = ctx.mpcpcg_solve_batched(d, off, eps=EPS)
+    f, fwd = oracle_saved_forward(packed, off)
     rng = np.random.default_rng(5)
     gl = torch.from_numpy(rng.standard_normal(f["lam"].shape).astype(np.float32)).cuda()
     gx = torch.from_numpy(rng.standard_normal(f["dx"].shape).astype(np.float32)).cuda()
     gu = torch.from_numpy(rng.standard_normal(f["du"].shape).astype(np.float32)).cuda()
     g = ctx.mpcpcg_backward(d, off, f, gl, gx, gu, eps=EPS)
     torch.cuda.synchronize()
-    fwd = {k: f[k].cpu().numpy().astype(np.float64) for k in ("lam", "dx", "du")}
     ref = orc.backward_batch(packed, off, fwd, gl.cpu().numpy().astype(np.float64),
                              gx.cpu().numpy().astype(np.float64), gu.cpu().numpy().astype(np.float64),
                              eps=EPS, threads=8)
@@ -326,6 +333,8 @@ def test_batched_gangs_on_one_xcd_match_the_global_queue(ctx):
                     {k: g[k].cpu().numpy() for k in ("dQ", "dq")},
                     stats(fwd["stats"]).copy(), stats(g["stats"]).copy(), off)
         f8, g8, s8, b8, off8 = run(probs)
+        # the 8-problem batch qualifies for per-XCD lists on the 8-XCD MI355X
+        assert ctx.mpcpcg_tuned_schedule(off8) == (16, True)
         parts = [run(probs[:4]), run(probs[4:])]
     finally:
         ctx.mpcpcg_set_knots_per_group(0)
@@ -344,15 +353,27 @@ def test_batched_gangs_on_one_xcd_match_the_global_queue(ctx):
 
 
 def test_backward_batch64_horizon128(ctx):
-    # batch 64, N = 128, L = ||lambda||^2, seeds 4001 + b
+    # batch 64, N = 128, L = ||lambda||^2, seeds 4001 + b, end to end: the GPU's forward
+    # then its adjoint, against the oracle's forward then the oracle's adjoint (no GPU output
+    # enters the reference), and against the dense KKT adjoint at the exact solution
     probs, packed, off = _batch_case([128] * 64, 4001)
     d = dev(packed)
     f = ctx.mpcpcg_solve_batched(d, off, eps=EPS)
     g = ctx.mpcpcg_backward(d, off, f, 2 * f["lam"], eps=EPS)
     torch.cuda.synchronize()
-    fwd = {k: f[k].cpu().numpy().astype(np.float64) for k in ("lam", "dx", "du")}
-    ref = orc.backward_batch(packed, off, fwd, 2 * fwd["lam"], eps=EPS, threads=8)
+    fo = orc.solve_batch(packed, off, eps=EPS, threads=8)
+    ref = orc.backward_batch(packed, off, fo, 2 * fo["lam"], eps=EPS, threads=8)
     check_grads(g, ref, off)
+    out = {k: g[k].cpu().numpy() for k in GRAD_KEYS}
+    for b in range(3):  # the dense KKT adjoint (dim 4,473) on the first problems
+        k0, k1 = off[b], off[b + 1]
+        c0, c1 = k0 - b, k1 - b - 1
+        dense = kkt.adjoint_dense(probs[b], 2 * kkt.kkt_solve(probs[b])["lam"])
+        for k in ("dQ", "dq"):
+            assert rel(out[k][k0:k1], dense[k]) < 1e-4, (k, b)
+        for k in ("dR", "dA", "dB", "dr"):
+            assert rel(out[k][c0:c1], dense[k]) < 1e-4, (k, b)
+        assert rel(out["dx0"][b], dense["dx0"]) < 1e-4, b
 
 
 def test_autograd_function_matches_dense_gradients(ctx):
@@ -423,10 +444,11 @@ def test_wide_batched_two_arm_workload(ctx28):
     out = ctx28.mpcpcg_solve_batched(dev(packed), off, eps=EPS)
     torch.cuda.synchronize()
     check_batch(out, packed, off, it_tol=wide_it_tol)
+    # end to end: the GPU's forward and adjoint against the oracle's forward and adjoint
     g = ctx28.mpcpcg_backward(dev(packed), off, out, 2 * out["lam"], eps=EPS)
     torch.cuda.synchronize()
-    fwd = {k: out[k].cpu().numpy().astype(np.float64) for k in ("lam", "dx", "du")}
-    ref = orc.backward_batch(packed, off, fwd, 2 * fwd["lam"], eps=EPS, threads=8)
+    fo = orc.solve_batch(packed, off, eps=EPS, threads=8)
+    ref = orc.backward_batch(packed, off, fo, 2 * fo["lam"], eps=EPS, threads=8)
     check_grads(g, ref, off, it_tol=wide_it_tol)
 
 

@@ -46,6 +46,15 @@ MUTANTS = {
                                  "dQ[(size_t)k * bs + i * nx + j] = ax[i] * xk[j];"),
     "adjoint_dx0_sign": ("if (dx0) memcpy(dx0, mu, nx * sizeof(double));",
                          "if (dx0) for (int i = 0; i < nx; ++i) dx0[i] = -mu[i];"),
+    # the batched wrappers: control rows of problem b start at off[b] - b, x0 at row b
+    "batch_control_offset": ("const int64_t k0 = off[b], c0 = off[b] - b;\n    const int N = (int)(off[b + 1] - off[b]);\n    status[b] = orc_solve(",
+                             "const int64_t k0 = off[b], c0 = off[b];\n    const int N = (int)(off[b + 1] - off[b]);\n    status[b] = orc_solve("),
+    "batch_x0_row": ("q + k0 * nx, r + c0 * nu, x0 + (size_t)b * nx, e ? e + c0 * nx : NULL,\n                          eps,",
+                     "q + k0 * nx, r + c0 * nu, x0, e ? e + c0 * nx : NULL,\n                          eps,"),
+    "batch_backward_control_offset": ("const int64_t k0 = off[b], c0 = off[b] - b;\n    const int N = (int)(off[b + 1] - off[b]);\n    status[b] = orc_backward(",
+                                      "const int64_t k0 = off[b], c0 = off[b] - b + 1;\n    const int N = (int)(off[b + 1] - off[b]);\n    status[b] = orc_backward("),
+    "batch_backward_loss_rows": ("du + c0 * nu, gl + k0 * nx, gx ? gx + k0 * nx : NULL,",
+                                 "du + c0 * nu, gl + c0 * nx, gx ? gx + k0 * nx : NULL,"),
 }
 
 
@@ -120,7 +129,39 @@ def battery():
         if rel(b[k], d[k]) > 1e-8:
             failed.append("adjoint_" + k)
             break
+    failed += batch_wrapper_failures()
     return failed
+
+
+def batch_wrapper_failures():
+    """The batched entry points against per-problem solves of the unpacked problems: a
+    ragged batch with a one-knot problem and defects must give the per-problem results bit
+    for bit (forward and adjoint), row for row in the packed layout."""
+    probs = synth.batch([3, 1, 6, 2, 5], seed0=93, defects=True)
+    packed, off = synth.pack(probs)
+    fb = orc.solve_batch(packed, off, eps=1e-8)
+    gl = np.random.default_rng(94).standard_normal(fb["lam"].shape)
+    bb = orc.backward_batch(packed, off, fb, gl, eps=1e-8)
+    for b, p in enumerate(probs):
+        k0, k1 = off[b], off[b + 1]
+        c0, c1 = k0 - b, k1 - b - 1
+        f = orc.solve(p, eps=1e-8)
+        if not (np.array_equal(fb["lam"][k0:k1], f["lam"]) and np.array_equal(fb["dx"][k0:k1], f["dx"])
+                and np.array_equal(fb["du"][c0:c1], f["du"]) and fb["iters"][b] == f["iters"]):
+            return ["batch_forward"]
+        g = orc.backward(p, dict(lam=fb["lam"][k0:k1], dx=fb["dx"][k0:k1], du=fb["du"][c0:c1]),
+                         gl[k0:k1], eps=1e-8)
+        same = all(np.array_equal(bb[k][k0:k1], g[k]) for k in ("dQ", "dq", "mu"))
+        same = same and all(np.array_equal(bb[k][c0:c1], g[k]) for k in ("dR", "dA", "dB", "dr", "de"))
+        if not (same and np.array_equal(bb["dx0"][b], g["dx0"]) and bb["iters"][b] == g["iters"]):
+            return ["batch_backward"]
+    return []
+
+
+def test_batched_wrappers_equal_per_problem_solves():
+    # orc_solve_batch / orc_backward_batch are the reference of every batched GPU parity
+    # test: pinned here against the per-problem entry points, which the other pins fix
+    assert batch_wrapper_failures() == []
 
 
 def _with_library(path):
