@@ -165,3 +165,21 @@ def test_header_is_c_and_the_library_links(tmp_path):
     sizes = [int(v) for v in out[4:]]
     assert sizes == [ctypes.sizeof(mpcpcg.Problem), ctypes.sizeof(mpcpcg.Opts), mpcpcg.STATS_DTYPE.itemsize,
                      ctypes.sizeof(mpcpcg.ChainModel), ctypes.sizeof(mpcpcg.Trajectory)]
+
+
+def test_dpp_asm_header_is_the_generators_output():
+    # csrc/dpp_asm.h is written by csrc/gen_dpp_asm.py; regenerating must reproduce it
+    import importlib.util
+    gen = os.path.join(ROOT, "paper_2309_08079_amd", "csrc", "gen_dpp_asm.py")
+    spec = importlib.util.spec_from_file_location("gen_dpp_asm", gen)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    committed = open(os.path.join(ROOT, "paper_2309_08079_amd", "csrc", "dpp_asm.h")).read()
+    assert mod.render() == committed
+    # every block's operand numbers stay inside its operand list
+    for line in committed.splitlines():
+        if "asm volatile" not in line:
+            continue
+        nops = line.count('"v"(') + line.count('"+&v"(')
+        used = [int(x) for x in re.findall(r"%(\d+)", line)]
+        assert max(used) < nops, line[:120]
