@@ -136,8 +136,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0, help="problems in the CPU sample (0 = auto)")
-    ap.add_argument("--kpw", type=int, default=16,
-                    help="knots per workgroup of the batched kernels (0 = autotune before timing)")
+    ap.add_argument("--kpw", type=int, default=0,
+                    help="knots per workgroup of the batched kernels (0 = autotune shape and XCD "
+                         "placement before timing, the default)")
+    ap.add_argument("--no-floors", action="store_true", help="skip the launch / barrier / LDS / L2 probes")
     ap.add_argument("--step-only", action="store_true",
                     help="time the batched step only (no single-launch comparison, no CPU baseline)")
     ap.add_argument("--ingest-counters", default="", metavar="DIR",
@@ -213,15 +215,18 @@ def _time_ms(fn, stream, reps):
 
 
 def single_sweep(ctx, dev, stream, reps=10):
-    """One launch per solve over horizons (seeds 2000 + N): latency, iterations, latency per
-    iteration, and the formation alone (mpcpcg_form_schur)."""
+    """One launch per solve over horizons (seeds 2000 + N): latency, iterations beside the
+    oracle's iterations on the same problem, latency per iteration, and the formation alone
+    (mpcpcg_form_schur)."""
     import torch
+    from oracle import ref as orc
     from paper_2309_08079_amd import synth
     from paper_2309_08079_amd.mpcpcg import stats_to_numpy, to_device
 
     rows = []
     for N in (16, 32, 64, 128, 256, 512):
-        p = to_device(synth.problem(N, NX, NU, seed=2000 + N), dev)
+        pn = synth.problem(N, NX, NU, seed=2000 + N)
+        p = to_device(pn, dev)
         o = dict(lam=torch.empty((N, NX), device=dev), dx=torch.empty((N, NX), device=dev),
                  du=torch.empty((N - 1, NU), device=dev), stats=torch.zeros((1, 4), dtype=torch.int32, device=dev))
         ms = _time_ms(lambda: ctx.mpcpcg_solve(p, eps=EPS, out=o), stream, reps)
@@ -229,10 +234,45 @@ def single_sweep(ctx, dev, stream, reps=10):
         so = (torch.empty((N, 3, NX, NX), device=dev), torch.empty((N, 3, NX, NX), device=dev),
               torch.empty((N, NX), device=dev))
         fms = _time_ms(lambda: ctx.mpcpcg_form_schur(p, out=so), stream, reps)
-        rows.append({"N": N, "us": round(ms * 1e3, 2), "iters": it,
+        rows.append({"N": N, "us": round(ms * 1e3, 2), "iters": it, "oracle_iters": int(orc.solve(pn, eps=EPS)["iters"]),
                      "us_per_iter": round((ms - fms) * 1e3 / max(it, 1), 3),
-                     "formation_us": round(fms * 1e3, 2)})
+                     "formation_us": round(fms * 1e3, 2), "pcg_us": round((ms - fms) * 1e3, 2)})
     return rows
+
+
+def floors():
+    """Measured floors of this device (libmpcpcg_floors.so): empty-launch latency, one
+    barrier round of the solver's protocol (isolated, and with as many gangs at once as
+    the batched launch keeps), and the LDS, L2 and last-level-cache read bandwidths."""
+    import ctypes as C
+
+    lib = C.CDLL(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2309_08079_amd",
+                              "libmpcpcg_floors.so"))
+    lib.floors_read.argtypes = [C.c_int64, C.c_int, C.c_int, C.POINTER(C.c_double)]
+    v = C.c_double()
+
+    def call(fn, *a):
+        rc = fn(*a, C.byref(v))
+        if rc != 0:
+            raise RuntimeError("floor probe %s failed (%d)" % (fn.__name__, rc))
+        return v.value
+
+    out = {"launch_us": round(call(lib.floors_launch, 2000), 3)}
+    bar = []
+    # (gangs, parts, sleep before the first poll, gangs on one XCD each)
+    for g, n, sl, pin in ((1, 2, 0, 0), (1, 2, 1, 0), (1, 32, 0, 0), (1, 32, 1, 0), (8, 16, 1, 1),
+                          (24, 32, 1, 0), (48, 16, 1, 1)):
+        bar.append({"gangs": g, "parts": n, "sleep_before_poll": bool(sl), "one_xcd_per_gang": bool(pin),
+                    "us_per_round": round(call(lib.floors_barrier, g, n, 400, sl, pin), 3)})
+    out["barrier"] = bar
+    out["lds_read_tbps"] = round(call(lib.floors_lds_read, 2048, 20000) / 1e12, 2)
+    out["l2_read_tbps"] = round(call(lib.floors_read, 2 << 20, 2048, 8) / 1e12, 2)
+    out["llc_read_tbps"] = round(call(lib.floors_read, 64 << 20, 256, 2) / 1e12, 2)
+    out["notes"] = ("launch: back-to-back empty kernels; barrier: one round = publish a tagged 16-byte "
+                    "word, poll every partner's (the solver's PCG sync point), us per round averaged over "
+                    "400 rounds and all gangs; lds: ds_read_b128 conflict free; l2: 2 MiB re-read by 2048 "
+                    "workgroups; llc: 64 MiB re-read by 256 workgroups")
+    return out
 
 
 def mixed_batch(ctx, dev, stream, reps=5):
@@ -478,6 +518,129 @@ def control_step(dev, stream, reps=20):
             "single": rows, "batch_256xN128": batch}
 
 
+def parity_sample(packed_np, off, fout, bout, fst, bst, sample=(0, 85, 170, 255)):
+    """The timed headline batch checked against the oracle on a few of its problems:
+    lambda, dx, du against the oracle's PCG iterate (Algorithm 1 at the same eps) and the
+    gradients against the oracle's forward then adjoint; norm-wise relative errors (the
+    bars are 1e-5 and 1e-4) and iteration counts beside the oracle's."""
+    from oracle import ref as orc
+
+    lam, dx, du = (fout[k].cpu().numpy() for k in ("lam", "dx", "du"))
+    g = {k: bout[k].cpu().numpy() for k in ("dQ", "dR", "dA", "dB", "dq", "dx0")}
+    rel = lambda a, b: float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+    worst = {"lam": 0.0, "dx": 0.0, "du": 0.0, "grad": 0.0}
+    iters = []
+    for b in sample:
+        k0, k1 = int(off[b]), int(off[b + 1])
+        c0, c1 = k0 - b, k1 - b - 1
+        p = {k: packed_np[k][k0:k1] for k in ("Q", "q")}
+        p.update({k: packed_np[k][c0:c1] for k in ("R", "A", "B", "r")})
+        p["x0"] = packed_np["x0"][b]
+        f = orc.solve(p, eps=EPS)
+        gr = orc.backward(p, f, 2 * f["lam"], eps=EPS)
+        worst["lam"] = max(worst["lam"], rel(lam[k0:k1], f["lam"]))
+        worst["dx"] = max(worst["dx"], rel(dx[k0:k1], f["dx"]))
+        worst["du"] = max(worst["du"], rel(du[c0:c1], f["du"]))
+        ge = max(rel(g["dQ"][k0:k1], gr["dQ"]), rel(g["dq"][k0:k1], gr["dq"]), rel(g["dx0"][b], gr["dx0"]),
+                 rel(g["dA"][c0:c1], gr["dA"]), rel(g["dB"][c0:c1], gr["dB"]), rel(g["dR"][c0:c1], gr["dR"]))
+        worst["grad"] = max(worst["grad"], ge)
+        iters.append({"problem": b, "forward": int(fst["iters"][b]), "forward_oracle": int(f["iters"]),
+                      "adjoint": int(bst["iters"][b]), "adjoint_oracle": int(gr["iters"])})
+    return {"problems": list(sample), "max_rel_err": worst, "iters": iters,
+            "within_bar": bool(max(worst["lam"], worst["dx"], worst["du"]) < 1e-5 and worst["grad"] < 1e-4),
+            "reference": "oracle forward (Algorithm 1, FP64) and oracle forward -> oracle adjoint"}
+
+
+def one_round_batch(ctx, d, off, dev, stream, n=24, reps=10):
+    """The first 24 problems of the headline batch alone: as many N = 512 problems as the
+    device keeps resident at once, so the launch is one round and its time per PCG
+    iteration is the per-iteration cost under full load."""
+    import torch
+    from paper_2309_08079_amd.mpcpcg import stats_to_numpy
+
+    sub_off = off[: n + 1]
+    K = int(sub_off[-1])
+    sub = {k: d[k][:K] for k in ("Q", "q")}
+    sub.update({k: d[k][:K - n] for k in ("R", "A", "B", "r", "e")})
+    sub["x0"] = d["x0"][:n]
+    o = ctx.mpcpcg_solve_batched(sub, sub_off, eps=EPS)
+    ms = _time_ms(lambda: ctx.mpcpcg_solve_batched(sub, sub_off, eps=EPS, out=o), stream, reps)
+    it = stats_to_numpy(o["stats"])["iters"]
+    return {"problems": n, "knots": N_KNOTS, "forward_ms": round(ms, 4), "iters_mean": float(it.mean()),
+            "us_per_iter": round(ms * 1e3 / float(it.max()), 3)}
+
+
+def barrier_entry(sweep, one_round, fl):
+    """Microseconds per PCG iteration beside the measured barrier floor (one barrier per
+    iteration in the solver's loop)."""
+    row = {r["N"]: r for r in sweep}
+    out = {"pcg_us_per_iter_one_workgroup_N16": row[16]["us_per_iter"],
+           "pcg_us_per_iter_single_N512": row[512]["us_per_iter"],
+           "pcg_us_per_iter_full_load_24xN512": one_round["us_per_iter"],
+           "barriers_per_iter": 1}
+    if fl:
+        b = {(x["gangs"], x["parts"], x["sleep_before_poll"], x["one_xcd_per_gang"]): x["us_per_round"]
+             for x in fl["barrier"]}
+        out["floor_us_isolated_32_parts"] = b[(1, 32, True, False)]
+        out["floor_us_loaded_24x32_parts"] = b[(24, 32, True, False)]
+        out["single_N512_iter_over_floor"] = round(row[512]["us_per_iter"] / b[(1, 32, True, False)], 2)
+        out["full_load_iter_over_floor"] = round(one_round["us_per_iter"] / b[(24, 32, True, False)], 2)
+    return out
+
+
+PHI_ROW_BYTES = 16 * 3 * NX * 4  # one knot group's LDS reads of its Phi^-1 rows (16 lanes x 42 floats)
+PHI_KNOT_BYTES = NX * 3 * NX * 4  # the knot's 14 rows of Phi^-1 (algorithmic)
+
+
+def lds_entry(fout, off, fwd_ms, kpw, fl):
+    """Phi^-1 bytes the forward launch reads from LDS per second, beside the measured LDS
+    read bandwidth.  Every loop pass (iterations + 1) applies Phi^-1 once per knot slot of a
+    part (slots past the horizon included) and, in a part of a multi-part problem, once
+    more in each of its edge waves for the ghost knots beyond its ends; algorithmic bytes
+    count the problem's own knots only."""
+    from paper_2309_08079_amd.mpcpcg import stats_to_numpy
+
+    passes = stats_to_numpy(fout["stats"])["iters"].astype(np.float64) + 1.0
+    Ns = np.diff(np.asarray(off, dtype=np.int64)).astype(np.float64)
+    parts = np.ceil(Ns / kpw)
+    waves = kpw // 4
+    ghost_groups = np.where(parts > 1, 8.0 if waves >= 2 else 4.0, 0.0)
+    issued = float(np.sum(parts * (kpw + ghost_groups) * passes)) * PHI_ROW_BYTES
+    algorithmic = float(np.sum(Ns * passes)) * PHI_KNOT_BYTES
+    t = fwd_ms * 1e-3
+    out = {"phi_issued_tbps": round(issued / t / 1e12, 3), "phi_algorithmic_tbps": round(algorithmic / t / 1e12, 3),
+           "issued_bytes_per_launch": issued, "algorithmic_bytes_per_launch": algorithmic}
+    if fl:
+        out["lds_floor_tbps"] = fl["lds_read_tbps"]
+        out["frac_issued"] = round(issued / t / 1e12 / fl["lds_read_tbps"], 4)
+    return out
+
+
+def gradient_batch(dev, stream, reps=5):
+    """The differentiated workload: 64 problems of N = 128 (seeds 4001 + b), forward then the
+    adjoint of L = ||lambda||^2, timed one launch each."""
+    import torch
+    from paper_2309_08079_amd import synth
+    from paper_2309_08079_amd.mpcpcg import Context, stats_to_numpy, to_device
+
+    packed_np, off = synth.pack(synth.batch([128] * 64, NX, NU, seed0=4001))
+    d = to_device(packed_np, dev)
+    ctx = Context(NX, NU, max_total_knots=int(off[-1]), max_batch=64)
+    try:
+        fo = ctx.mpcpcg_solve_batched(d, off, eps=EPS)
+        fms = _time_ms(lambda: ctx.mpcpcg_solve_batched(d, off, eps=EPS, out=fo), stream, reps)
+        gl = 2 * fo["lam"]
+        bo = ctx.mpcpcg_backward(d, off, fo, gl, eps=EPS)
+        bms = _time_ms(lambda: ctx.mpcpcg_backward(d, off, fo, gl, eps=EPS, out=bo), stream, reps)
+        ok = bool((stats_to_numpy(fo["stats"])["status"] == 0).all() and (stats_to_numpy(bo["stats"])["status"] == 0).all())
+        return {"problems": 64, "knots": 128, "forward_ms": round(fms, 4), "adjoint_ms": round(bms, 4),
+                "solves_per_s_fwd_adj": 64 / ((fms + bms) * 1e-3),
+                "iters_forward_mean": float(stats_to_numpy(fo["stats"])["iters"].mean()),
+                "iters_adjoint_mean": float(stats_to_numpy(bo["stats"])["iters"].mean()), "all_ok": ok}
+    finally:
+        ctx.close()
+
+
 def main():
     args = parse()
     if args.ingest_counters:
@@ -531,9 +694,11 @@ def main():
     if args.kpw:
         ctx.mpcpcg_set_knots_per_group(args.kpw)
         kpw = args.kpw
+        tuned = False
     else:
         kpw = ctx.mpcpcg_autotune(d, off, eps=EPS)
-        ctx.mpcpcg_set_knots_per_group(kpw)
+        tuned = True
+    kpw, pinned = ctx.mpcpcg_tuned_schedule(off)
 
     def step(evs=None):
         if evs is not None:
@@ -576,12 +741,15 @@ def main():
     achieved = dom_flop / (dom_ms * 1e-3) / 1e12
 
     if args.step_only:
-        print(json.dumps({"ms_per_step": ms_step, "knots_per_group": kpw, "kernel_ms": {"forward": fwd_ms, "adjoint": adj_ms},
+        print(json.dumps({"ms_per_step": ms_step, "knots_per_group": kpw, "xcd_pinned": pinned,
+                          "kernel_ms": {"forward": fwd_ms, "adjoint": adj_ms},
                           "iters_forward_mean": float(it_f.mean()), "iters_adjoint_mean": float(it_b.mean())}))
         return
+    parity = parity_sample(packed_np, off, fout, bout, fst, bst)
+    sched = {"knots_per_group": kpw, "xcd_pinned": pinned, "autotuned": tuned}
 
     # one launch per solve: single problem latency and 256 sequential launches, with the
-    # library's own workgroup shape per horizon (the pin above is for the batched step)
+    # library's own workgroup shape per horizon (the schedule above is for the batched step)
     ctx.mpcpcg_set_knots_per_group(0)
     single = {"Q": d["Q"][:N_KNOTS], "q": d["q"][:N_KNOTS], "x0": d["x0"][0]}
     for k in ("R", "A", "B", "r", "e"):
@@ -613,9 +781,27 @@ def main():
     torch.cuda.synchronize()
     seq_ms = e0.elapsed_time(e1)
     batched_fwd_sps = BATCH / (fwd_ms * 1e-3)
+    # forward + adjoint one problem at a time: the single solve, then the adjoint of a
+    # batch of one (256 problems in turn, and one N = 512 problem alone)
+    one_off = np.array([0, N_KNOTS], dtype=np.int64)
+    gout = {k: v[:N_KNOTS] if k in ("dQ", "dq", "dgamma") else v[:N_KNOTS - 1] for k, v in bout.items()
+            if k not in ("dx0", "stats")}
+    gout["dx0"], gout["stats"] = bout["dx0"][:1], bout["stats"][:1]
+    gl1 = torch.empty((N_KNOTS, NX), device=dev)
+    bviews = [dict(views[b], x0=views[b]["x0"].reshape(1, NX)) for b in range(BATCH)]
+
+    def fwd_adj(b):
+        ctx.mpcpcg_solve(views[b], eps=EPS, out=sout)
+        torch.mul(sout["lam"], 2.0, out=gl1)
+        ctx.mpcpcg_backward(bviews[b], one_off, sout, gl1, eps=EPS, out=gout)
+    single_fa_us = _time_ms(lambda: fwd_adj(0), stream, n_single) * 1e3
+    seq_fa_ms = _time_ms(lambda: [fwd_adj(b) for b in range(BATCH)], stream, 1)
+    one_round = one_round_batch(ctx, d, off, dev, stream)
 
     sweep = single_sweep(ctx, dev, stream)
     mixed = mixed_batch(ctx, dev, stream)
+    grad64 = gradient_batch(dev, stream)
+    fl = None if args.no_floors else floors()
     seqs = warm_sequences(ctx, dev, stream)
     wide = two_arm_batch(dev, stream)
     fac = factor_path(dev, stream)
@@ -647,10 +833,19 @@ def main():
         "single_solve_us_N512": single_us,
         "sequential_256_single_launches_solves_per_s": BATCH / (seq_ms * 1e-3),
         "batched_vs_sequential_speedup": batched_fwd_sps / (BATCH / (seq_ms * 1e-3)),
+        "single_solve_fwd_adj_us_N512": single_fa_us,
+        "sequential_256_fwd_adj_ms": seq_fa_ms,
+        "batched_vs_sequential_fwd_adj_speedup": seq_fa_ms / ms_step,
+        "schedule": sched,
+        "parity_sample": parity,
         "iters_forward_mean": float(it_f.mean()),
         "iters_adjoint_mean": float(it_b.mean()),
         "kernel_ms": {"forward": fwd_ms, "adjoint": adj_ms},
         "single_solve_sweep": sweep,
+        "gradient_batch_64xN128": grad64,
+        "floors": fl,
+        "barrier": barrier_entry(sweep, one_round, fl),
+        "lds": lds_entry(fout, off, fwd_ms, kpw, fl),
         "mixed_batch_256": mixed,
         "warm_sequence": seqs,
         "two_arm_batch_32": wide,

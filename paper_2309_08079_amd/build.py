@@ -24,10 +24,13 @@ def flags():
             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    """Compile every HIP source into libmpcpcg.so (always recompiles)."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC] + flags() + list(extra) + SOURCES + ["-o", tmp]
+FLOORS_LIB = os.path.join(PKG, "libmpcpcg_floors.so")
+FLOORS_SOURCES = [os.path.join(CSRC, "floors.hip")]
+
+
+def _compile(sources, lib, verbose, extra):
+    tmp = lib + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + flags() + list(extra) + sources + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -37,8 +40,15 @@ def build(verbose: bool = False, extra=()) -> str:
         raise RuntimeError("hipcc failed:\n" + err)
     if verbose and err.strip():
         print(err, file=sys.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(verbose: bool = False, extra=()) -> str:
+    """Compile libmpcpcg.so and the benchmark's floor probes, libmpcpcg_floors.so (always
+    recompiles both)."""
+    _compile(FLOORS_SOURCES, FLOORS_LIB, verbose, extra)
+    return _compile(SOURCES, LIB, verbose, extra)
 
 
 if __name__ == "__main__":

@@ -183,3 +183,15 @@ def test_dpp_asm_header_is_the_generators_output():
         nops = line.count('"v"(') + line.count('"+&v"(')
         used = [int(x) for x in re.findall(r"%(\d+)", line)]
         assert max(used) < nops, line[:120]
+
+
+FLOORS_HEADER = os.path.join(ROOT, "include", "mpcpcg_floors.h")
+FLOORS_LIB = os.path.join(ROOT, "paper_2309_08079_amd", "libmpcpcg_floors.so")
+
+
+@pytest.mark.skipif(not os.path.exists(FLOORS_LIB), reason="libmpcpcg_floors.so not built")
+def test_floor_probe_library_exports_every_declared_symbol():
+    syms = sorted(set(re.findall(r"\b(floors_[a-z_0-9]+)\s*\(", open(FLOORS_HEADER).read())))
+    assert len(syms) == 4
+    lib = ctypes.CDLL(FLOORS_LIB)
+    assert not [s for s in syms if not hasattr(lib, s)]
