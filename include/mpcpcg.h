@@ -309,25 +309,6 @@ int mpcpcg_control_step(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
                         float *X_out, float *U_out, double *merit, int32_t *choice,
                         mpcpcg_stats *stats, hipStream_t stream);
 
-/* ---- For callers that cannot allocate device memory ----------------------------------
- * mpcpcg_solve_noalloc is mpcpcg_solve for callers that may not call hipMalloc: code that
- * runs under HIP graph capture, tight serving loops, harnesses that forbid allocation.  It
- * takes no context and allocates nothing (no hipMalloc, hipFree or graph): its scratch
- * (Q^-1 and (R^-1 | R^-1 B^T) per knot, the exchange words of the workgroups, gang and
- * queue counters) lives in one static device array of ~4.4 MB that each GPU the library
- * runs on holds until the process ends.  The first call on a device resolves that device's
- * copy of the array and clears it on `stream`; it must not be captured into a graph (later
- * calls may be).  Every call on one GPU shares the array: calls that overlap on one GPU
- * (other streams, other threads) race and must be serialised by the caller; every
- * finished solve leaves it ready for the next.
- * Problem, options and outputs are those of mpcpcg_solve for (nx, nu) = (14, 7) and
- * 1 <= N <= 4096 (EUNSUPPORTED / EINVAL otherwise), with PCG and the default workgroup
- * shape; results equal mpcpcg_solve's on a context with default settings.
- * mpcpcg_noalloc_last_error() describes this thread's last failed call ("" if none). */
-int mpcpcg_solve_noalloc(const mpcpcg_problem *prob, const mpcpcg_opts *opts, float *lambda,
-                         float *dx, float *du, mpcpcg_stats *stats, hipStream_t stream);
-const char *mpcpcg_noalloc_last_error(void);
-
 #ifdef __cplusplus
 }
 #endif

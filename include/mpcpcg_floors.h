@@ -18,7 +18,7 @@
  *   floors_lds_read  aggregate LDS read bandwidth in bytes/s over `blocks` workgroups of
  *                    256 threads, each reading `iters` conflict-free 16-byte words per thread;
  *   floors_read      aggregate read bandwidth in bytes/s of `blocks` workgroups each reading a
- *                    buffer of buffer_bytes (a multiple of 16, >= 4096) `passes` times: a
+ *                    buffer of buffer_bytes (a multiple of 16384) `passes` times: a
  *                    buffer that fits in the L2 of each XCD measures L2, one beyond the L2s
  *                    but within the last-level cache measures that, a large one HBM.
  * Each call allocates what it needs, runs on the current device, synchronises it, and

@@ -89,6 +89,16 @@ def kkt_matrix(prob, sparse=False):
     return K, np.concatenate([g, c])
 
 
+def primal_step(prob, lam):
+    """The primal step of a given multiplier: dZ = -G^-1 (g - C^T lambda) (Section III-B),
+    by a sparse solve with the block-diagonal G.  Returns (dx [N, nx], du [N-1, nu])."""
+    P, N, nx, nu = _f64(prob)
+    G, g, Cm, _ = assemble(prob, sparse=True)
+    rhs = g - Cm.T @ np.asarray(lam, dtype=np.float64).ravel()
+    dZ = -spla.spsolve(G, rhs)
+    return _split_z(dZ, N, nx, nu)
+
+
 def kkt_solve(prob, sparse=None):
     """Exact (lambda, dx, du) from the KKT system by LU; dense LAPACK for small systems,
     SuperLU on the sparse matrix for large ones."""

@@ -70,16 +70,20 @@ __global__ void __launch_bounds__(64) barrier_probe(BarrierArgs a) {
 
 constexpr int kLdsFloats = 8192;  // 32 KB per workgroup
 
-__global__ void __launch_bounds__(256) lds_probe(int iters, float *sink) {
+// `step` is a kernel argument (256): the compiler cannot see that the read addresses repeat
+// and reuse earlier loads, so every iteration issues its reads.
+__global__ void __launch_bounds__(256) lds_probe(int iters, int step, float *sink) {
   __shared__ float4 buf[kLdsFloats / 4];
   for (int i = threadIdx.x; i < kLdsFloats / 4; i += 256)
     buf[i] = make_float4((float)i, 1.0f, 2.0f, 3.0f);
   __syncthreads();
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
   const int mask = kLdsFloats / 4 - 1;
+  int idx = threadIdx.x;
   for (int i = 0; i < iters; ++i) {
     // consecutive lanes read consecutive 16-byte slots: no bank conflicts
-    const float4 v = buf[(threadIdx.x + i * 256) & mask];
+    const float4 v = buf[idx & mask];
+    idx += step;
     acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
   }
   const float s = acc.x + acc.y + acc.z + acc.w;
@@ -88,14 +92,22 @@ __global__ void __launch_bounds__(256) lds_probe(int iters, float *sink) {
 
 __global__ void __launch_bounds__(256) read_probe(const float4 *buf, int64_t n4, int passes, float *sink) {
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-  // each workgroup sweeps the whole buffer, starting at a different offset
+  // each workgroup sweeps the whole buffer (4 independent loads in flight per thread),
+  // starting at a different offset; n4 is a multiple of 1024
   const int64_t start = ((int64_t)blockIdx.x * 4096) % n4;
   for (int p = 0; p < passes; ++p)
-    for (int64_t i = threadIdx.x; i < n4; i += 256) {
-      int64_t j = start + i;
-      if (j >= n4) j -= n4;
-      const float4 v = buf[j];
-      acc.x += v.x; acc.y += v.y; acc.z += v.z; acc.w += v.w;
+    for (int64_t i = threadIdx.x; i < n4; i += 1024) {
+      float4 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        int64_t j = start + i + u * 256;
+        if (j >= n4) j -= n4;
+        v[u] = buf[j];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        acc.x += v[u].x; acc.y += v[u].y; acc.z += v[u].z; acc.w += v[u].w;
+      }
     }
   const float s = acc.x + acc.y + acc.z + acc.w;
   if (s == -1.0f) sink[blockIdx.x] = s;
@@ -179,10 +191,10 @@ int floors_lds_read(int blocks, int iters, double *bytes_per_s) {
   hipEvent_t e0, e1;
   FCHK(hipEventCreate(&e0));
   FCHK(hipEventCreate(&e1));
-  hipLaunchKernelGGL(lds_probe, dim3(blocks), dim3(256), 0, 0, 16, sink);
+  hipLaunchKernelGGL(lds_probe, dim3(blocks), dim3(256), 0, 0, 16, 256, sink);
   FCHK(hipDeviceSynchronize());
   FCHK(hipEventRecord(e0, 0));
-  hipLaunchKernelGGL(lds_probe, dim3(blocks), dim3(256), 0, 0, iters, sink);
+  hipLaunchKernelGGL(lds_probe, dim3(blocks), dim3(256), 0, 0, iters, 256, sink);
   FCHK(hipEventRecord(e1, 0));
   FCHK(hipEventSynchronize(e1));
   float ms = 0.f;
@@ -195,7 +207,7 @@ int floors_lds_read(int blocks, int iters, double *bytes_per_s) {
 }
 
 int floors_read(int64_t buffer_bytes, int blocks, int passes, double *bytes_per_s) {
-  if (buffer_bytes < 4096 || buffer_bytes % 16 || blocks < 1 || passes < 1 || !bytes_per_s) return -2;
+  if (buffer_bytes < 16384 || buffer_bytes % 16384 || blocks < 1 || passes < 1 || !bytes_per_s) return -2;
   void *buf = nullptr;
   float *sink = nullptr;
   FCHK(hipMalloc(&buf, (size_t)buffer_bytes));

@@ -10,7 +10,6 @@
 #include <cstring>
 #include <map>
 #include <memory>
-#include <mutex>
 #include <string>
 #include <vector>
 
@@ -19,6 +18,7 @@
 #include "ctrl_kernels.h"
 #include "tri_kernel.h"
 #include "wide_kernels.h"
+#include "wide_pcg.h"
 
 namespace {
 
@@ -116,6 +116,10 @@ struct WideSchedule {
   std::vector<int64_t> at_odd, at_even;  // offsets into d_tasks
   int64_t at_root = 0;
   mpc::wide::CrTask *d_tasks = nullptr;
+  // tasks of the gang PCG: (problem, part) longest problem first, KW knots per part
+  ProbDesc *d_gprobs = nullptr;
+  Task *d_gtasks = nullptr;
+  int gntasks = 0, gmax_parts = 0;
 };
 
 // Schedule choice of the batched PCG launch for one horizon signature.
@@ -190,6 +194,9 @@ struct mpcpcg_ctx {
   double *w_lam = nullptr;  // lambda of the factorisation path
   int *w_flag = nullptr;    // per-problem breakdown flags of the factorisation path
   float *w_P = nullptr;
+  void *w_tws = nullptr;  // tagged words of the gang PCG, one per task
+  Gang *w_gang = nullptr;
+  int *w_queue = nullptr;
   Lru<Sig, WideSchedule> wsched;
   // control step: chunk lists and the line search's per-chunk partial sums (on first use)
   Lru<Sig, CtrlSchedule> csched;
@@ -631,13 +638,9 @@ int launch_batched(mpcpcg_ctx *c, Schedule *s, KArgs &a, int mode, int want_pin,
 }
 
 // ---------------------------------------------------------------- generic path (nx = 28)
-constexpr int kWideMaxRows = mpc::wide::kWideThreads * mpc::wide::kWideRows;
+constexpr int kWKnots = mpc::wide::kGangKnots;  // knots per workgroup of the gang PCG
 
-size_t wide_lds_bytes(int N, int nx, int nu) {
-  const size_t vd = sizeof(double) * (size_t)(N + 2) * nx;
-  const size_t vf = sizeof(float) * (((size_t)(N + 2) * nx + 1) / 2 * 2);
-  return vd + vf + sizeof(double) * (size_t)N * nu;
-}
+int64_t wide_max_tasks(const mpcpcg_ctx *c) { return c->max_knots / kWKnots + c->max_batch; }
 
 int wide_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, WideSchedule **out) {
   if (WideSchedule *hit = c->wsched.get(off)) { *out = hit; return MPCPCG_OK; }
@@ -648,9 +651,6 @@ int wide_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, WideSchedule *
   for (int b = 0; b < B; ++b) {
     const int N = (int)(off[b + 1] - off[b]);
     maxN = std::max(maxN, N);
-    if (N * c->nx > kWideMaxRows || wide_lds_bytes(N, c->nx, c->nu) > 150 * 1024)
-      return fail(c, MPCPCG_EINVAL, "horizon N=%d exceeds the %d-row limit of the nx=%d path", N,
-                  kWideMaxRows, c->nx);
     pd[b] = mpc::wide::ProbDescW{off[b], N, b};
     for (int k = 0; k < N; ++k) kd.push_back(mpc::wide::KnotDesc{off[b], N, k, b, 0});
   }
@@ -658,6 +658,34 @@ int wide_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, WideSchedule *
   w->nknots = (int)kd.size();
   w->nprobs = B;
   w->maxN = maxN;
+  // gang PCG: problems longest first, the parts of a problem adjacent (a gang is always
+  // completed by the next free workgroups)
+  {
+    std::vector<int> order(B);
+    for (int b = 0; b < B; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return pd[x].N > pd[y].N; });
+    std::vector<ProbDesc> gp(B);
+    std::vector<Task> gt;
+    for (int b : order) {
+      ProbDesc d;
+      d.k0 = off[b];
+      d.N = pd[b].N;
+      d.nparts = (d.N + kWKnots - 1) / kWKnots;
+      d.t0 = (int32_t)gt.size();
+      d.id = b;
+      gp[b] = d;
+      w->gmax_parts = std::max(w->gmax_parts, d.nparts);
+      for (int j = 0; j < d.nparts; ++j) gt.push_back(Task{b, j});
+    }
+    if ((int64_t)gt.size() > wide_max_tasks(c)) return fail(c, MPCPCG_EINVAL, "batch exceeds the gang workspace");
+    w->gntasks = (int)gt.size();
+    w->d_gprobs = w->mem.upload(gp.data(), gp.size());
+    w->d_gtasks = w->mem.upload(gt.data(), gt.size());
+    if (!w->d_gprobs || !w->d_gtasks) {
+      (void)hipGetLastError();
+      return fail(c, MPCPCG_ENOMEM, "cannot allocate the gang schedule of a %d-problem batch", B);
+    }
+  }
   std::vector<mpc::wide::CrTask> tasks;
   for (int s = 1; s < maxN; s *= 2) {
     w->stride.push_back(s);
@@ -750,12 +778,26 @@ int wide_run(mpcpcg_ctx *c, const std::vector<int64_t> &off, mpc::wide::WArgs &a
     HIPCHK(c, hipGetLastError());
     return MPCPCG_OK;
   }
-  const size_t lds = wide_lds_bytes(w->maxN, c->nx, c->nu);
-  HIPCHK(c, hipFuncSetAttribute(reinterpret_cast<const void *>(mpc::wide::wide_pcg<kWNX, kWNU>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL((mpc::wide::wide_pcg<kWNX, kWNU>), dim3(w->nprobs), dim3(mpc::wide::kWideThreads),
-                     lds, s, a);
-  HIPCHK(c, hipGetLastError());
+  // PCG on gangs of workgroups (every gang co-resident), then the primal step or gradients
+  {
+    namespace mw = mpc::wide;
+    auto fn = mw::wide_pcg_gang<kWNX, kWKnots>;
+    int nb = 0;
+    HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(fn), kWKnots * 64, 0));
+    const int cap = nb * c->cus;
+    if (w->gmax_parts > cap)
+      return fail(c, MPCPCG_EINVAL, "a horizon needs %d co-resident workgroups; the device holds %d", w->gmax_parts, cap);
+    mw::GangArgs ga;
+    std::memset(&ga, 0, sizeof ga);
+    ga.tws = c->w_tws; ga.gang = c->w_gang; ga.queue = c->w_queue;
+    ga.probs = w->d_gprobs; ga.tasks = w->d_gtasks; ga.ntasks = w->gntasks;
+    ga.spin_limit = c->spin_ticks;
+    hipLaunchKernelGGL(fn, dim3(std::min(w->gntasks, cap)), dim3(kWKnots * 64), 0, s, a, ga);
+    HIPCHK(c, hipGetLastError());
+    hipLaunchKernelGGL((mw::wide_epilogue<kWNX, kWNU>), dim3((w->nknots + mw::kFormWaves - 1) / mw::kFormWaves),
+                       dim3(mw::kFormWaves * 64), 0, s, a);
+    HIPCHK(c, hipGetLastError());
+  }
   return MPCPCG_OK;
 }
 
@@ -832,89 +874,6 @@ mpc::ctrl::CtrlArgs ctrl_args(const mpcpcg_chain_model *m, const mpcpcg_trajecto
   return a;
 }
 
-// ---- allocation-free single solve (mpcpcg_solve_noalloc) -----------------------------
-// The scratch of one single-problem solve: Q^-1 and (R^-1 | R^-1 B^T) by columns, the
-// per-part exchange words, one gang and the launch queue, for horizons up to kNaMaxKnots.
-constexpr int64_t kNaMaxKnots = 4096;
-constexpr int kNaMaxParts = (int)(kNaMaxKnots / 16);  // horizons beyond 32 knots use 16 per part
-constexpr size_t na_round(size_t n) { return (n + 255) / 256 * 256; }
-constexpr size_t kNaQinv = na_round((size_t)kNaMaxKnots * kNX * mpc::kGroup * sizeof(double));
-constexpr size_t kNaRinv = na_round((size_t)kNaMaxKnots * (kNU + kNX) * mpc::kURows * sizeof(double));
-constexpr size_t kNaTws = na_round((size_t)kNaMaxParts * sizeof(mpc::TaskWS<kNX>));
-constexpr size_t kNaGang = na_round(sizeof(Gang));
-constexpr size_t kNaQueue = 256;
-constexpr size_t kNaZeroBytes = kNaTws + kNaGang + kNaQueue;  // must start at zero
-constexpr size_t kNaBytes = kNaQinv + kNaRinv + kNaZeroBytes;
-
-// Per device: the device address of `scratch` (each device holds its own copy of the
-// array), resolved once with that device current, plus launch limits.
-struct NaDevice {
-  std::once_flag once;
-  int rc = MPCPCG_OK;
-  unsigned char *ptr = nullptr;
-  int cap[4] = {0, 0, 0, 0};  // co-resident workgroups per shape of kKpwChoices
-  int xcd_ok = 0;
-  int64_t spin = 0;
-  bool cleared = false;
-};
-constexpr int kNaDevices = 64;
-NaDevice g_na[kNaDevices];
-std::mutex g_na_mu;
-thread_local std::string g_na_err;
-
-int na_fail(int code, const char *fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
-  va_end(ap);
-  g_na_err = buf;
-  return code;
-}
-
-__global__ void na_clear(uint4 *p, size_t n16) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
-    p[i] = make_uint4(0u, 0u, 0u, 0u);
-}
-
-}  // namespace
-
-static __device__ __align__(256) unsigned char scratch[kNaBytes];
-
-namespace {
-
-// Resolves this device's copy of `scratch` and the launch limits (once per device).
-void na_setup(NaDevice &d, int dev) {
-  void *ptr = nullptr;
-  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
-  if (e != hipSuccess || !ptr) {
-    d.rc = na_fail(MPCPCG_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
-    return;
-  }
-  d.ptr = static_cast<unsigned char *>(ptr);
-  hipDeviceProp_t prop;
-  int nxcc = 0, khz = 0;
-  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
-    d.rc = na_fail(MPCPCG_EHIP, "hipGetDeviceProperties failed on device %d", dev);
-    return;
-  }
-  if (hipDeviceGetAttribute(&nxcc, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess) nxcc = 0;
-  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
-  (void)hipGetLastError();
-  d.xcd_ok = (nxcc == 8 && prop.multiProcessorCount % 8 == 0) ? 1 : 0;
-  d.spin = (int64_t)2000 * khz;  // 2 s
-  for (int i = 0; i < 4; ++i) {
-    const int k = kKpwChoices[i];
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(kernel_for(k, mpc::kForward)),
-                                                     k * mpc::kGroup, 0) != hipSuccess) {
-      d.rc = na_fail(MPCPCG_EHIP, "occupancy query failed on device %d", dev);
-      return;
-    }
-    d.cap[i] = nb * prop.multiProcessorCount;
-  }
-}
-
 }  // namespace
 
 extern "C" {
@@ -953,9 +912,18 @@ int mpcpcg_create(mpcpcg_ctx **out, int32_t nx, int32_t nu, int64_t max_total_kn
         hipMalloc(&c->w_lam, sizeof(double) * K * nx) != hipSuccess ||
         hipMalloc(&c->w_flag, sizeof(int) * (size_t)max_batch) != hipSuccess ||
         hipMalloc(&c->w_Qinv, sizeof(double) * K * MM) != hipSuccess ||
-        hipMalloc(&c->w_RW, sizeof(double) * K * nu * (nu + nx)) != hipSuccess) {
+        hipMalloc(&c->w_RW, sizeof(double) * K * nu * (nu + nx)) != hipSuccess ||
+        hipMalloc(&c->w_tws, sizeof(mpc::wide::WTag) * (size_t)wide_max_tasks(c.get())) != hipSuccess ||
+        hipMalloc(&c->w_gang, sizeof(Gang) * (size_t)max_batch) != hipSuccess ||
+        hipMalloc(&c->w_queue, 16 * sizeof(int)) != hipSuccess) {
       mpcpcg_destroy(c.release());
       return MPCPCG_ENOMEM;
+    }
+    if (hipMemset(c->w_tws, 0, sizeof(mpc::wide::WTag) * (size_t)wide_max_tasks(c.get())) != hipSuccess ||
+        hipMemset(c->w_gang, 0, sizeof(Gang) * (size_t)max_batch) != hipSuccess ||
+        hipMemset(c->w_queue, 0, 16 * sizeof(int)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+      mpcpcg_destroy(c.release());
+      return MPCPCG_EHIP;
     }
     *out = c.release();
     return MPCPCG_OK;
@@ -998,7 +966,7 @@ int mpcpcg_destroy(mpcpcg_ctx *c) {
   if (c->cs_ws) (void)hipFree(c->cs_ws);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (void *p : {(void *)c->w_S, (void *)c->w_Dinv, (void *)c->w_P, (void *)c->w_rhs, (void *)c->w_lam, (void *)c->w_Qinv,
-                  (void *)c->w_RW, (void *)c->w_flag})
+                  (void *)c->w_RW, (void *)c->w_flag, c->w_tws, (void *)c->w_gang, (void *)c->w_queue})
     if (p) (void)hipFree(p);
   delete c;
   return MPCPCG_OK;
@@ -1438,69 +1406,5 @@ int mpcpcg_control_step(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const 
   return MPCPCG_OK;
 }
 
-const char *mpcpcg_noalloc_last_error(void) { return g_na_err.c_str(); }
-
-int mpcpcg_solve_noalloc(const mpcpcg_problem *p, const mpcpcg_opts *o, float *lambda, float *dx, float *du,
-                         mpcpcg_stats *stats, hipStream_t s) {
-  if (!p) return na_fail(MPCPCG_EINVAL, "problem is NULL");
-  if (p->nx != kNX || p->nu != kNU) return na_fail(MPCPCG_EUNSUPPORTED, "only (nx, nu) = (14, 7) is supported");
-  if (p->N < 1 || p->N > kNaMaxKnots) return na_fail(MPCPCG_EINVAL, "N = %d outside [1, %lld]", p->N, (long long)kNaMaxKnots);
-  if (!p->Q || !p->q || !p->x0) return na_fail(MPCPCG_EINVAL, "Q, q and x0 must be non-NULL");
-  if (p->N > 1 && (!p->R || !p->A || !p->B || !p->r))
-    return na_fail(MPCPCG_EINVAL, "R, A, B and r must be non-NULL when N > 1");
-  if (!o) return na_fail(MPCPCG_EINVAL, "opts is NULL");
-  if (!(o->eps >= 0.0f) || o->max_iter < 0) return na_fail(MPCPCG_EINVAL, "eps must be >= 0 and max_iter >= 0");
-  if (o->stop_rule != MPCPCG_STOP_RELATIVE && o->stop_rule != MPCPCG_STOP_ABSOLUTE)
-    return na_fail(MPCPCG_EINVAL, "stop_rule must be MPCPCG_STOP_RELATIVE or MPCPCG_STOP_ABSOLUTE");
-  if (!lambda || !dx || !stats || (p->N > 1 && !du)) return na_fail(MPCPCG_EINVAL, "lambda, dx, du and stats must be non-NULL");
-  int dev = -1;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNaDevices)
-    return na_fail(MPCPCG_EHIP, "no current device (or device index >= %d)", kNaDevices);
-  NaDevice &d = g_na[dev];
-  std::call_once(d.once, [&] { na_setup(d, dev); });
-  if (d.rc) return d.rc;
-  {
-    // the exchange words, gang and queue start at zero (every solve leaves them so)
-    std::lock_guard<std::mutex> lock(g_na_mu);
-    if (!d.cleared) {
-      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-      if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
-        return na_fail(MPCPCG_EINVAL, "the first call on a device clears its scratch and must not be captured");
-      const size_t n16 = kNaZeroBytes / 16;
-      hipLaunchKernelGGL(na_clear, dim3((unsigned)std::min<size_t>((n16 + 255) / 256, 1024)), dim3(256), 0, s,
-                         reinterpret_cast<uint4 *>(d.ptr + kNaQinv + kNaRinv), n16);
-      const hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return na_fail(MPCPCG_EHIP, "clearing the scratch failed: %s", hipGetErrorString(e));
-      d.cleared = true;
-    }
-  }
-  const int N = p->N;
-  int kpw = 16, ki = 2;
-  for (int i = 0; i < 4; ++i)
-    if (N <= kKpwChoices[i]) { kpw = kKpwChoices[i]; ki = i; break; }
-  const int g = (N + kpw - 1) / kpw;
-  if (g > kNaMaxParts || g > d.cap[ki])
-    return na_fail(MPCPCG_EINVAL, "horizon N=%d needs %d co-resident workgroups; the device holds %d", N, g, d.cap[ki]);
-  KArgs a;
-  std::memset(&a, 0, sizeof a);
-  a.Q = p->Q; a.R = p->R; a.A = p->A; a.B = p->B;
-  a.q = p->q; a.r = p->r; a.x0 = p->x0; a.e = p->e;
-  a.qinv_ws = reinterpret_cast<double *>(d.ptr);
-  a.rinv_ws = reinterpret_cast<double *>(d.ptr + kNaQinv);
-  a.tws = d.ptr + kNaQinv + kNaRinv;
-  a.gang = reinterpret_cast<Gang *>(d.ptr + kNaQinv + kNaRinv + kNaTws);
-  a.queue = reinterpret_cast<int *>(d.ptr + kNaQinv + kNaRinv + kNaTws + kNaGang);
-  a.eps = o->eps; a.max_iter = o->max_iter; a.warm = o->warm_start; a.stop_abs = o->stop_rule;
-  a.spin_limit = d.spin;
-  a.lam = lambda; a.dx = dx; a.du = du; a.stats = stats;
-  a.single.k0 = 0; a.single.N = N; a.single.t0 = 0; a.single.nparts = g; a.single.id = 0;
-  a.ntasks = g;
-  // the placement rule of mpcpcg_solve: a gang of 2..16 parts on one XCD
-  a.one_xcd = (d.xcd_ok && g > 1 && g <= 16 && 8 * g <= d.cap[ki]) ? 1 : 0;
-  hipLaunchKernelGGL(kernel_for(kpw, mpc::kForward), dim3(a.one_xcd ? 8 * g : g), dim3(kpw * mpc::kGroup), 0, s, a);
-  const hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return na_fail(MPCPCG_EHIP, "launch failed: %s", hipGetErrorString(e));
-  return MPCPCG_OK;
-}
 
 }  // extern "C"

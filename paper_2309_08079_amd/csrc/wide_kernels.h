@@ -8,10 +8,9 @@
 //                rows in registers;
 //   wide_precond one workgroup per knot: Phi^-1 row blocks -D_b^-1 S_{b,b+-1} D_{b+-1}^-1
 //                (FP32) once every D^-1 exists (the one cross-knot dependency);
-//   wide_pcg     one workgroup per problem: PCG (Algorithm 1) with one matrix row per
-//                thread, S and Phi^-1 streamed from the workspace every iteration and
-//                the vectors broadcast from LDS; then the primal step, or in adjoint mode
-//                nu_1 and the block-sparse gradients.
+//   wide_pcg_gang (wide_pcg.h) PCG (Algorithm 1) on gangs of workgroups, rows of S and
+//                Phi^-1 in registers; then wide_epilogue: the primal step, or in adjoint
+//                mode nu_1 and the block-sparse gradients.
 // Precision matches the 14-state kernel: FP64 formation, S, vectors and reductions; FP32
 // Phi^-1.  Method references: S, gamma (Section III-B, sign-flipped so S is positive
 // definite), Phi^-1 (Section IV-A), PCG (Algorithm 1), dZ = -G^-1 (g - C^T lambda).
@@ -692,285 +691,6 @@ __global__ void __launch_bounds__(kFormWaves * 64) wide_epilogue(const WArgs a) 
     const double ni = vu[w][i], nj = vu[w][j];
     const double di = (double)dub[i], dj = (double)dub[j];
     a.dR[cb * NU * NU + o] = (float)(0.5 * (ni * dj + nj * di));
-  }
-}
-
-// ---------------------------------------------------------------- PCG per problem
-constexpr int kWideThreads = 1024;
-constexpr int kWideRows = 8;  // rows per thread: N * NX <= 8192
-
-__device__ __forceinline__ double block_sum(double v, double *red) {
-  // fixed-shape reduction: butterfly within each wave, then waves in order
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[w] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
-  return s;
-}
-
-// Dynamic LDS: vd [N+2][NX] FP64, vf [N+2][NX] FP32, vu [N][NU] FP64 (row 0 and N+1 of the
-// vectors are zero halos).
-template <int NX, int NU>
-__global__ void __launch_bounds__(kWideThreads) wide_pcg(const WArgs a) {
-  extern __shared__ double lds[];
-  __shared__ double red[kWideThreads / 64];
-  constexpr int MM = NX * NX;
-  const ProbDescW pd = a.probs[blockIdx.x];
-  const int N = pd.N;
-  const int64_t k0 = pd.k0, c0 = pd.k0 - pd.id;
-  const int rows = N * NX;
-  double *vd = lds;                                   // [N+2][NX]
-  float *vf = reinterpret_cast<float *>(vd + (N + 2) * NX);  // [N+2][NX]
-  double *vu = reinterpret_cast<double *>(vf + ((N + 2) * NX + 1) / 2 * 2);  // [N][NU]
-  const int tid = threadIdx.x;
-  const bool adj = a.adjoint != 0;
-  for (int t = tid; t < NX; t += kWideThreads) {
-    vd[t] = 0.0; vd[(N + 1) * NX + t] = 0.0;
-    vf[t] = 0.0f; vf[(N + 1) * NX + t] = 0.0f;
-  }
-  // row ownership: thread t owns rows g = t + s * kWideThreads
-  double lam[kWideRows], r[kWideRows], p[kWideRows], Y[kWideRows], g0[kWideRows];
-  float rt[kWideRows];
-#pragma unroll
-  for (int s = 0; s < kWideRows; ++s) {
-    const int g = tid + s * kWideThreads;
-    const bool ok = g < rows;
-    lam[s] = (ok && a.warm && !adj) ? (double)a.lam[k0 * NX + g] : 0.0;
-    g0[s] = ok ? a.rhs[k0 * NX + g] : 0.0;
-  }
-  // matvec with the S (FP64) or Phi^-1 (FP32) row of global row g against an LDS vector
-  auto s_row = [&](int g, const double *v) {
-    const int b = g / NX, i = g % NX;
-    const double *Srow = a.S + (k0 + b) * 3 * MM + i * NX;
-    double acc = 0.0;
-    for (int slot = 0; slot < 3; ++slot) {
-      const double *x = v + (b + slot) * NX;  // halo-shifted: row b-1 of the vector is b
-      const double *m = Srow + slot * MM;
-      for (int j = 0; j < NX; ++j) acc = __builtin_fma(m[j], x[j], acc);
-    }
-    return acc;
-  };
-  auto p_row = [&](int g, const float *v) {
-    const int b = g / NX, i = g % NX;
-    const float *Prow = a.P + (k0 + b) * 3 * MM + i * NX;
-    float acc = 0.0f;
-    for (int slot = 0; slot < 3; ++slot) {
-      const float *x = v + (b + slot) * NX;
-      const float *m = Prow + slot * MM;
-      for (int j = 0; j < NX; ++j) acc = __builtin_fmaf(m[j], x[j], acc);
-    }
-    return acc;
-  };
-  auto put_d = [&](const double *src) {
-#pragma unroll
-    for (int s = 0; s < kWideRows; ++s) {
-      const int g = tid + s * kWideThreads;
-      if (g < rows) vd[NX + g] = src[s];
-    }
-  };
-  auto put_f = [&](const double *src) {
-#pragma unroll
-    for (int s = 0; s < kWideRows; ++s) {
-      const int g = tid + s * kWideThreads;
-      if (g < rows) vf[NX + g] = (float)src[s];
-    }
-  };
-
-  int status = MPCPCG_OK, it = 0;
-  double eta_ref = 0.0, eta_new = 0.0;
-  {
-  // eta_ref = rhs^T Phi^-1 rhs; r = rhs - S lambda_0
-  put_f(g0);
-  put_d(lam);
-  __syncthreads();
-  double pr = 0.0, pe = 0.0;
-  float gt[kWideRows];
-#pragma unroll
-  for (int s = 0; s < kWideRows; ++s) {
-    const int g = tid + s * kWideThreads;
-    gt[s] = 0.0f;
-    r[s] = g0[s];
-    if (g < rows) {
-      gt[s] = p_row(g, vf);
-      if (a.warm && !adj) r[s] = g0[s] - s_row(g, vd);
-    }
-  }
-  __syncthreads();
-  put_f(r);
-  __syncthreads();
-#pragma unroll
-  for (int s = 0; s < kWideRows; ++s) {
-    const int g = tid + s * kWideThreads;
-    rt[s] = g < rows ? p_row(g, vf) : 0.0f;
-    pr += r[s] * (double)rt[s];
-    pe += g0[s] * (double)gt[s];
-    p[s] = (double)rt[s];
-  }
-  double eta = block_sum(pr, red);
-  eta_ref = block_sum(pe, red);
-  const double tau = a.stop_abs ? (double)a.eps : (double)a.eps * (double)a.eps * eta_ref;
-  const int max_iter = a.max_iter > 0 ? a.max_iter : N * NX;
-  status = MPCPCG_NOT_CONVERGED;
-  eta_new = eta;
-  if (!(eta == eta) || !(eta_ref == eta_ref) || __builtin_isinf(eta) || __builtin_isinf(eta_ref)) {
-    status = MPCPCG_BREAKDOWN;
-  } else if (eta <= tau) {
-    status = MPCPCG_OK;
-  } else {
-    for (it = 1; it <= max_iter; ++it) {
-      __syncthreads();
-      put_d(p);
-      __syncthreads();
-      double pu = 0.0;
-#pragma unroll
-      for (int s = 0; s < kWideRows; ++s) {
-        const int g = tid + s * kWideThreads;
-        Y[s] = g < rows ? s_row(g, vd) : 0.0;
-        pu += p[s] * Y[s];
-      }
-      const double ups = block_sum(pu, red);
-      if (!(ups > 0.0) || __builtin_isinf(ups)) { status = MPCPCG_BREAKDOWN; break; }
-      const double alpha = eta / ups;
-#pragma unroll
-      for (int s = 0; s < kWideRows; ++s) {
-        lam[s] = __builtin_fma(alpha, p[s], lam[s]);
-        r[s] = __builtin_fma(-alpha, Y[s], r[s]);
-      }
-      put_f(r);
-      __syncthreads();
-      double pn = 0.0;
-#pragma unroll
-      for (int s = 0; s < kWideRows; ++s) {
-        const int g = tid + s * kWideThreads;
-        rt[s] = g < rows ? p_row(g, vf) : 0.0f;
-        pn += r[s] * (double)rt[s];
-      }
-      eta_new = block_sum(pn, red);
-      if (!(eta_new == eta_new) || __builtin_isinf(eta_new)) { status = MPCPCG_BREAKDOWN; break; }
-      if (eta_new < tau) { status = MPCPCG_OK; break; }
-      const double beta = eta_new / eta;
-#pragma unroll
-      for (int s = 0; s < kWideRows; ++s) p[s] = __builtin_fma(beta, p[s], (double)rt[s]);
-      eta = eta_new;
-    }
-    if (it > max_iter) it = max_iter;
-  }
-  }
-
-  // ---------------------------------------------------------------- epilogue
-  // x rows: dZx_b = -Q_b^-1 (q_b - lambda_b) + S_{b,b+1} lambda_{b+1};
-  // u rows of control b-1: -R^-1 r_{b-1} - (R^-1 B^T) lambda_b  (mu and gradients in adjoint)
-  const float *qv = adj ? a.gx : a.q;
-  const float *rv = adj ? a.gu : a.r;
-  __syncthreads();
-  put_d(lam);
-  __syncthreads();
-  double xrow[kWideRows];
-#pragma unroll
-  for (int s = 0; s < kWideRows; ++s) {
-    const int g = tid + s * kWideThreads;
-    xrow[s] = 0.0;
-    if (g < rows) {
-      const int b = g / NX, i = g % NX;
-      const double *Qi = a.Qinv + (k0 + b) * MM + i * NX;
-      const double *Sp = a.S + (k0 + b) * 3 * MM + 2 * MM + i * NX;
-      const double *lb = vd + (b + 1) * NX, *ln = vd + (b + 2) * NX;
-      double acc = 0.0;
-      for (int j = 0; j < NX; ++j) {
-        const double qj = qv ? (double)qv[(k0 + b) * NX + j] : 0.0;
-        acc = __builtin_fma(-Qi[j], qj - lb[j], acc);
-        acc = __builtin_fma(Sp[j], ln[j], acc);
-      }
-      xrow[s] = acc;
-    }
-  }
-  // u rows: thread t handles (control c = b-1 for b = 1..N-1, row i < NU)
-  for (int g = tid; g < (N - 1) * NU; g += kWideThreads) {
-    const int c = g / NU, i = g % NU;  // control c belongs to block row b = c + 1
-    const double *rw = a.RW + (c0 + c) * NU * (NU + NX) + i * (NU + NX);
-    const double *lb = vd + (c + 2) * NX;  // lambda_{c+1}
-    double acc = 0.0;
-    for (int m = 0; m < NU; ++m) acc -= rw[m] * (rv ? (double)rv[(c0 + c) * NU + m] : 0.0);
-    for (int j = 0; j < NX; ++j) acc -= rw[NU + j] * lb[j];
-    vu[c * NU + i] = acc;
-  }
-  if (!adj) {
-#pragma unroll
-    for (int s = 0; s < kWideRows; ++s) {
-      const int g = tid + s * kWideThreads;
-      if (g < rows) {
-        a.lam[k0 * NX + g] = (float)lam[s];
-        a.dx[k0 * NX + g] = (float)xrow[s];
-      }
-    }
-    __syncthreads();
-    for (int g = tid; g < (N - 1) * NU; g += kWideThreads) a.du[c0 * NU + g] = (float)vu[g];
-  } else {
-    // lam holds mu; xrow = nu1x; vu = nu1u.  vd (mu) is reused for nu1x after a barrier.
-#pragma unroll
-    for (int s = 0; s < kWideRows; ++s) {
-      const int g = tid + s * kWideThreads;
-      if (g < rows) {
-        if (a.dgamma) a.dgamma[k0 * NX + g] = (float)lam[s];
-        a.dq[k0 * NX + g] = (float)xrow[s];
-        const int b = g / NX, i = g % NX;
-        if (b == 0) a.dx0[(int64_t)pd.id * NX + i] = (float)lam[s];
-        if (b >= 1 && a.de) a.de[(c0 + b - 1) * NX + i] = (float)(-lam[s]);
-      }
-    }
-    // nu1x replaces mu in the LDS vector; mu (FP64) is staged in the right-hand-side
-    // workspace, which PCG no longer needs
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < kWideRows; ++s) {
-      const int g = tid + s * kWideThreads;
-      if (g < rows) a.rhs[k0 * NX + g] = lam[s];
-    }
-    put_d(xrow);
-    __syncthreads();
-    for (int g = tid; g < (N - 1) * NU; g += kWideThreads) a.dr[c0 * NU + g] = (float)vu[g];
-    // dQ_b = sym(nu1x_b dx_b^T)
-    for (int t = tid; t < N * MM; t += kWideThreads) {
-      const int b = t / MM, i = (t / NX) % NX, j = t % NX;
-      const double nx_i = vd[(b + 1) * NX + i], nx_j = vd[(b + 1) * NX + j];
-      const double dx_i = (double)a.dx_in[(k0 + b) * NX + i], dx_j = (double)a.dx_in[(k0 + b) * NX + j];
-      a.dQ[(k0 + b) * MM + i * NX + j] = (float)(0.5 * (nx_i * dx_j + nx_j * dx_i));
-    }
-    // control c of block row b = c + 1: dA_c = lambda_b nu1x_c^T + mu_b dx_c^T,
-    // dB_c = lambda_b nu1u_c^T + mu_b du_c^T, dR_c = sym(nu1u_c du_c^T)
-    for (int t = tid; t < (N - 1) * MM; t += kWideThreads) {
-      const int c = t / MM, i = (t / NX) % NX, j = t % NX;
-      const double lb_i = (double)a.lam_in[(k0 + c + 1) * NX + i];
-      const double mu_i = a.rhs[(k0 + c + 1) * NX + i];
-      const double n1x_j = vd[(c + 1) * NX + j];
-      const double dx_j = (double)a.dx_in[(k0 + c) * NX + j];
-      a.dA[(c0 + c) * MM + i * NX + j] = (float)(lb_i * n1x_j + mu_i * dx_j);
-    }
-    for (int t = tid; t < (N - 1) * NX * NU; t += kWideThreads) {
-      const int c = t / (NX * NU), i = (t / NU) % NX, j = t % NU;
-      const double lb_i = (double)a.lam_in[(k0 + c + 1) * NX + i];
-      const double mu_i = a.rhs[(k0 + c + 1) * NX + i];
-      const double n1u_j = vu[c * NU + j];
-      const double du_j = (double)a.du_in[(c0 + c) * NU + j];
-      a.dB[(c0 + c) * NX * NU + i * NU + j] = (float)(lb_i * n1u_j + mu_i * du_j);
-    }
-    for (int t = tid; t < (N - 1) * NU * NU; t += kWideThreads) {
-      const int c = t / (NU * NU), i = (t / NU) % NU, j = t % NU;
-      const double ni = vu[c * NU + i], nj = vu[c * NU + j];
-      const double di = (double)a.du_in[(c0 + c) * NU + i], dj = (double)a.du_in[(c0 + c) * NU + j];
-      a.dR[(c0 + c) * NU * NU + i * NU + j] = (float)(0.5 * (ni * dj + nj * di));
-    }
-  }
-  if (tid == 0) {
-    mpcpcg_stats st;
-    st.iters = it;
-    st.status = status;
-    st.final_ratio = eta_ref > 0.0 ? (float)__builtin_sqrt(eta_new > 0.0 ? eta_new / eta_ref : 0.0) : 0.0f;
-    st.reserved = 0;
-    a.stats[pd.id] = st;
   }
 }
 

@@ -359,3 +359,21 @@ def test_adjoint_matches_central_finite_differences(h, tol):
             want.append((L(bump(1)) - L(bump(-1))) / (2 * h))
             got.append(b[gkey][ix])
         assert relerr(np.array(got), np.array(want)) < tol, gkey
+
+
+@pytest.mark.parametrize("N,nx,nu", [(1, 14, 7), (2, 14, 7), (9, 14, 7), (6, 28, 14)])
+def test_primal_step_of_exact_multipliers_is_exact_primal(N, nx, nu):
+    # dZ = -G^-1 (g - C^T lambda) at the exact lambda gives the exact dZ of the KKT solve, and
+    # a perturbation of lambda moves dZ by G^-1 C^T times it (linear in lambda)
+    p = synth.problem(N, nx, nu, seed=300 + N, defects=True)
+    ex = kkt.kkt_solve(p)
+    dx, du = kkt.primal_step(p, ex["lam"])
+    assert relerr(dx, ex["dx"]) < 1e-11 and (N == 1 or relerr(du, ex["du"]) < 1e-11)
+    d = np.random.default_rng(7).standard_normal(ex["lam"].shape)
+    dx2, du2 = kkt.primal_step(p, ex["lam"] + d)
+    G, g, Cm, _ = kkt.assemble(p)
+    dz = np.linalg.solve(G, Cm.T @ d.ravel())
+    lin = np.concatenate([dx2.ravel() - dx.ravel(), (du2 - du).ravel()]) if N > 1 else dx2.ravel() - dx.ravel()
+    ref = np.concatenate([dz[k * (nx + nu):k * (nx + nu) + nx] for k in range(N)] +
+                         [dz[k * (nx + nu) + nx:(k + 1) * (nx + nu)] for k in range(N - 1)])
+    assert relerr(lin, ref) < 1e-10
