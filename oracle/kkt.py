@@ -3,11 +3,11 @@
 Everything here is a plain definition written out with library primitives, so that it
 can be checked against MPCGPU Section III by eye:
 
-* ``assemble``      -- G, g, C, c of the KKT system (Section III-A, eq. "KKT").
+* ``assemble``      -- G, g, C, c of the KKT system (Section III-A, eq. (4)).
 * ``kkt_solve``     -- [G C^T; C 0][-dZ; lambda] = [g; c] solved by LU (O1): the exact
                        solution the iterative method approximates.
 * ``schur_dense``   -- S = C G^-1 C^T and gamma = C G^-1 g - c as sparse/dense products
-                       (eq. "schur", both sides negated so that S is positive definite).
+                       (eq. (5), both sides negated so that S is positive definite).
 * ``riccati``       -- textbook discrete-time LQR recursion (cost-to-go V_k(x) =
                        1/2 x^T P_k x + p_k^T x); its costate P_k x_k + p_k is lambda_k.
 * ``banded_solve``  -- lambda from a banded Cholesky solve of S (scipy.linalg.solveh_banded).

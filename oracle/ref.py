@@ -4,7 +4,7 @@ Test infrastructure only (see the package docstring).  ``build()`` compiles the 
 with gcc; every function takes numpy arrays (any float dtype, upcast to float64) and
 returns float64 results.
 
-Follows MPCGPU Section III-B (Schur complement, eq. "schur", "trajoptSchur_1/2"),
+Follows MPCGPU Section III-B (Schur complement, eqs. (5)-(7)),
 Section IV-A (symmetric stair preconditioner) and Algorithm 1 (PCG), with the stopping
 rule sqrt(eta'/eta_ref) < eps, eta_ref = gamma^T Phi^-1 gamma (stop="relative"), or the
 absolute test eta' < eps printed in Algorithm 1 (stop="absolute").

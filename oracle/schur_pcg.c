@@ -14,11 +14,11 @@
  *     G = blockdiag(Q_0, R_0, Q_1, ..., R_{N-2}, Q_{N-1}),  g = [q_0, r_0, ..., q_{N-1}],
  *     C block row 0 = [I 0 ...], block row k+1 = [.. -A_k -B_k I ..],
  *     c = [-x0, e_0, ..., e_{N-2}]   (the input x0 is the required value of dx_0).
- *   Schur complement (Section III-B, eq. "schur"): the paper writes S = -C G^-1 C^T and
+ *   Schur complement (Section III-B, eq. (5)): the paper writes S = -C G^-1 C^T and
  *   gamma = c - C G^-1 g; the same equation S lambda = gamma is solved here with both
  *   sides negated, S = C G^-1 C^T (positive definite) and gamma = C G^-1 g - c, which
  *   leaves lambda unchanged and matches the positive preconditioner the paper prints.
- *   Blocks (eq. "trajoptSchur_1/2"):
+ *   Blocks (eqs. (6) and (7)):
  *     S_00 = Q_0^-1, S_{k+1,k+1} = theta_k = A_k Q_k^-1 A_k^T + B_k R_k^-1 B_k^T + Q_{k+1}^-1,
  *     S_{k+1,k} = phi_k = -A_k Q_k^-1, S_{k,k+1} = phi_k^T,
  *     gamma_0 = Q_0^-1 q_0 + x0,
@@ -35,7 +35,7 @@
  *   rule; bit 1 (ORC_MODE_PHI_FP32) rounds every Phi^-1 entry to the nearest float before
  *   PCG uses it, for comparing unconverged iterates with a solver that stores Phi^-1 in
  *   single precision (the preconditioner changes the Krylov path, never the solution).
- *   Primal step (eq. "schur"): dZ = -G^-1 (g - C^T lambda).
+ *   Primal step (eq. (5)): dZ = -G^-1 (g - C^T lambda).
  *
  * Storage: row-major, S and Phi^-1 as [N][3][nx][nx] with slot 0 = (b,b-1),
  * slot 1 = (b,b), slot 2 = (b,b+1); slots outside the matrix are zero.

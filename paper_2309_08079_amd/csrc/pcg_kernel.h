@@ -681,7 +681,8 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
     float Pm[NX], Pd[NX], Pp[NX];
     if constexpr (PHASE == 0) {
     // (6) exchange D^-1 rows with the neighbouring knots (the one cross-knot dependency of
-    //     the formation: "only theta_k^-1 needs to be shared")
+    //     the formation; section IV-A, Symmetric Stair preconditioner: of the whole
+    //     preconditioner, only the neighbours' inverted diagonal blocks cross knots)
     if (rowv) {
 #pragma unroll
       for (int j = 0; j < NX; ++j) ex_m[slot + 1][lane][j] = Dd[j];
