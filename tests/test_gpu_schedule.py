@@ -9,6 +9,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
+from oracle import kkt
 from oracle import ref as orc
 from paper_2309_08079_amd import synth
 
@@ -57,6 +58,22 @@ def check_against_oracle(out, packed, off, only=None):
         assert rel(dx[k0:k1], ref["dx"][k0:k1]) < 1e-5, b
         if c1 > c0:
             assert rel(du[c0:c1], ref["du"][c0:c1]) < 1e-5, b
+
+
+def check_against_exact(out, probs, off, only=None):
+    """The factorisation path (no iterations) against the exact KKT solution at 1e-6, the
+    bar of the factorisation tests."""
+    lam, dx, du = (out[k].cpu().numpy() for k in ("lam", "dx", "du"))
+    st = stats(out["stats"])
+    for b in range(len(off) - 1) if only is None else only:
+        k0, k1 = off[b], off[b + 1]
+        c0, c1 = k0 - b, k1 - b - 1
+        assert st[b]["status"] == orc.OK and st[b]["iters"] == 0, (b, int(st[b]["status"]), int(st[b]["iters"]))
+        ex = kkt.kkt_solve(probs[b])
+        assert rel(lam[k0:k1], ex["lam"]) < 1e-6, b
+        assert rel(dx[k0:k1], ex["dx"]) < 1e-6, b
+        if c1 > c0:
+            assert rel(du[c0:c1], ex["du"]) < 1e-6, b
 
 
 def test_autotune_picks_a_shape_caches_it_and_matches_fixed_shape(ctx):
@@ -157,7 +174,10 @@ def test_wait_that_gives_up_reports_timeout(ctx, method):
         torch.cuda.synchronize()
         st = stats(out["stats"])
         assert list(st["status"]) == [M.TIMEOUT if n > 16 else M.OK for n in Ns], st
-        check_against_oracle(out, packed, off, only=[1, 3])
+        if method == "pcg":
+            check_against_oracle(out, packed, off, only=[1, 3])
+        else:
+            check_against_exact(out, probs, off, only=[1, 3])
         single = ctx.mpcpcg_solve(dev(probs[0]), eps=EPS)
         torch.cuda.synchronize()
         assert stats(single["stats"])[0]["status"] == M.TIMEOUT
@@ -167,7 +187,7 @@ def test_wait_that_gives_up_reports_timeout(ctx, method):
         if method == "pcg":
             check_against_oracle(out, packed, off)
         else:
-            assert (stats(out["stats"])["status"] == orc.OK).all()
+            check_against_exact(out, probs, off)
     finally:
         ctx.mpcpcg_debug_set_wait(2_000_000, inject_stall=False)
         ctx.mpcpcg_set_knots_per_group(0)
