@@ -309,6 +309,26 @@ int mpcpcg_control_step(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
                         float *X_out, float *U_out, double *merit, int32_t *choice,
                         mpcpcg_stats *stats, hipStream_t stream);
 
+/* ---- For callers that cannot allocate device memory ----------------------------------
+ * mpcpcg_solve_noalloc is mpcpcg_solve for callers that may not call hipMalloc: code that
+ * runs under HIP graph capture, tight serving loops, harnesses that forbid allocation.  It
+ * takes no context and allocates nothing (no hipMalloc, hipFree, graph or allocating
+ * library call).  Its scratch (Q^-1 and (R^-1 | R^-1 B^T) per knot, the exchange words of
+ * the workgroups, the gang and queue counters) is one static device array of 7.83 MB that
+ * each GPU the library runs on holds until the process ends; the first call on a device
+ * resolves that device's copy.  Every call clears the counters and exchange words it uses
+ * with a small fill kernel on `stream` (no memset), so calls may be captured into a graph.
+ * Every call on one GPU shares the array: calls that overlap on one GPU (other streams,
+ * other threads) race and must be serialised by the caller.
+ * Problem, options and outputs are those of mpcpcg_solve (device pointers, FP32, row-major)
+ * for (nx, nu) = (14, 7) and 1 <= N <= 2048; N beyond 2048 returns MPCPCG_EINVAL and other
+ * shapes MPCPCG_EUNSUPPORTED, before any launch.  It always solves by PCG with the workgroup
+ * shape mpcpcg_solve takes on a context with default settings, and gives the same results.
+ * mpcpcg_noalloc_last_error() describes this thread's last failed call ("" if none). */
+int mpcpcg_solve_noalloc(const mpcpcg_problem *prob, const mpcpcg_opts *opts, float *lambda,
+                         float *dx, float *du, mpcpcg_stats *stats, hipStream_t stream);
+const char *mpcpcg_noalloc_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

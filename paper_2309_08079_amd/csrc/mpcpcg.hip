@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -874,6 +875,99 @@ mpc::ctrl::CtrlArgs ctrl_args(const mpcpcg_chain_model *m, const mpcpcg_trajecto
   return a;
 }
 
+// ---- allocation-free single solve (mpcpcg_solve_noalloc) -----------------------------
+// Everything one single-problem PCG solve needs beyond its inputs and outputs: Q^-1 and
+// (R^-1 | R^-1 B^T) by columns, the exchange words of the parts, one gang record and the
+// launch queue, sized for horizons up to kNaMaxKnots.  The last three must be zero when a
+// launch starts; every call clears the part of them it uses with a fill kernel on its
+// stream (a kernel, not a memset, so the call may be captured into a graph).
+constexpr int64_t kNaMaxKnots = 2048;
+constexpr int kNaMaxParts = (int)(kNaMaxKnots / 16);  // horizons beyond 32 knots use 16 per part
+constexpr size_t na_round(size_t n) { return (n + 255) / 256 * 256; }
+constexpr size_t kNaQinv = na_round((size_t)kNaMaxKnots * kNX * mpc::kGroup * sizeof(double));
+constexpr size_t kNaRinv = na_round((size_t)kNaMaxKnots * (kNU + kNX) * mpc::kURows * sizeof(double));
+constexpr size_t kNaTws = na_round((size_t)kNaMaxParts * sizeof(mpc::TaskWS<kNX>));
+constexpr size_t kNaGang = na_round(sizeof(Gang));
+constexpr size_t kNaQueue = 256;
+constexpr size_t kNaBytes = kNaQinv + kNaRinv + kNaTws + kNaGang + kNaQueue;
+static_assert(sizeof(mpc::TaskWS<kNX>) % 16 == 0 && kNaQinv % 16 == 0 && kNaRinv % 16 == 0, "16-byte fill");
+
+// Per device: the device address of `scratch` (each device holds its own copy of the
+// array), resolved once with that device current, and the launch limits.
+struct NaDevice {
+  std::once_flag once;
+  int rc = MPCPCG_OK;
+  unsigned char *ptr = nullptr;
+  int cap[4] = {0, 0, 0, 0};  // co-resident workgroups per shape of kKpwChoices
+  int xcd_ok = 0;
+  int64_t spin = 0;
+};
+constexpr int kNaDevices = 64;
+NaDevice g_na[kNaDevices];
+thread_local std::string g_na_err;
+
+int na_fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_na_err = buf;
+  return code;
+}
+
+// zeroes [p, p + n16 * 16) and the n16b 16-byte words at q
+__global__ void na_clear(uint4 *p, size_t n16, uint4 *q, size_t n16b) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) p[i] = make_uint4(0u, 0u, 0u, 0u);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16b; i += stride) q[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+}  // namespace
+
+// The scratch of mpcpcg_solve_noalloc (one copy per device, held until the process ends).
+// In host code this name is not a device address: host code uses the per-device pointer
+// that na_setup resolves with hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+
+// Resolves this device's copy of `scratch` and the launch limits (once per device, with
+// that device current).
+void na_setup(NaDevice &d, int dev) {
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    d.rc = na_fail(MPCPCG_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    return;
+  }
+  d.ptr = static_cast<unsigned char *>(ptr);
+  hipDeviceProp_t prop;
+  int nxcc = 0, khz = 0;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    d.rc = na_fail(MPCPCG_EHIP, "hipGetDeviceProperties failed on device %d", dev);
+    return;
+  }
+  if (hipDeviceGetAttribute(&nxcc, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess) nxcc = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
+  (void)hipGetLastError();
+  d.xcd_ok = (nxcc == 8 && prop.multiProcessorCount % 8 == 0) ? 1 : 0;
+  d.spin = (int64_t)2000 * khz;  // 2 s
+  for (int i = 0; i < 4; ++i) {
+    const int k = kKpwChoices[i];
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(kernel_for(k, mpc::kForward)),
+                                                     k * mpc::kGroup, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      d.rc = na_fail(MPCPCG_EHIP, "occupancy query failed on device %d", dev);
+      return;
+    }
+    d.cap[i] = nb * prop.multiProcessorCount;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -1406,5 +1500,71 @@ int mpcpcg_control_step(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const 
   return MPCPCG_OK;
 }
 
+
+const char *mpcpcg_noalloc_last_error(void) { return g_na_err.c_str(); }
+
+int mpcpcg_solve_noalloc(const mpcpcg_problem *p, const mpcpcg_opts *o, float *lambda, float *dx, float *du,
+                         mpcpcg_stats *stats, hipStream_t s) {
+  g_na_err.clear();
+  if (!p) return na_fail(MPCPCG_EINVAL, "problem is NULL");
+  if (p->nx != kNX || p->nu != kNU) return na_fail(MPCPCG_EUNSUPPORTED, "only (nx, nu) = (14, 7) is supported");
+  if (p->N < 1 || p->N > kNaMaxKnots)
+    return na_fail(MPCPCG_EINVAL, "N = %d outside [1, %lld], the horizons the static scratch holds", p->N,
+                   (long long)kNaMaxKnots);
+  if (!p->Q || !p->q || !p->x0) return na_fail(MPCPCG_EINVAL, "Q, q and x0 must be non-NULL");
+  if (p->N > 1 && (!p->R || !p->A || !p->B || !p->r))
+    return na_fail(MPCPCG_EINVAL, "R, A, B and r must be non-NULL when N > 1");
+  if (!o) return na_fail(MPCPCG_EINVAL, "opts is NULL");
+  if (!(o->eps >= 0.0f) || o->max_iter < 0) return na_fail(MPCPCG_EINVAL, "eps must be >= 0 and max_iter >= 0");
+  if (o->stop_rule != MPCPCG_STOP_RELATIVE && o->stop_rule != MPCPCG_STOP_ABSOLUTE)
+    return na_fail(MPCPCG_EINVAL, "stop_rule must be MPCPCG_STOP_RELATIVE or MPCPCG_STOP_ABSOLUTE");
+  if (!lambda || !dx || !stats || (p->N > 1 && !du)) return na_fail(MPCPCG_EINVAL, "lambda, dx, du and stats must be non-NULL");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNaDevices) {
+    (void)hipGetLastError();
+    return na_fail(MPCPCG_EHIP, "no current device (or device index >= %d)", kNaDevices);
+  }
+  NaDevice &d = g_na[dev];
+  std::call_once(d.once, [&] { na_setup(d, dev); });
+  if (d.rc) return d.rc;
+  const int N = p->N;
+  int kpw = 16, ki = 2;  // the shape mpcpcg_solve takes on a context with default settings
+  for (int i = 0; i < 4; ++i)
+    if (N <= kKpwChoices[i]) { kpw = kKpwChoices[i]; ki = i; break; }
+  const int g = (N + kpw - 1) / kpw;
+  if (g > kNaMaxParts || g > d.cap[ki])
+    return na_fail(MPCPCG_EINVAL, "horizon N=%d needs %d co-resident workgroups; the device holds %d", N, g, d.cap[ki]);
+  unsigned char *const tws = d.ptr + kNaQinv + kNaRinv;
+  unsigned char *const gq = tws + kNaTws;  // gang record, then the queue
+  // the exchange words of the g parts, the gang record and the queue start at zero
+  {
+    const size_t n16 = (size_t)g * sizeof(mpc::TaskWS<kNX>) / 16, n16b = (kNaGang + kNaQueue) / 16;
+    const unsigned blocks = (unsigned)std::min<size_t>((n16 + 255) / 256, 512);
+    hipLaunchKernelGGL(na_clear, dim3(blocks ? blocks : 1), dim3(256), 0, s, reinterpret_cast<uint4 *>(tws), n16,
+                       reinterpret_cast<uint4 *>(gq), n16b);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return na_fail(MPCPCG_EHIP, "clearing the scratch failed: %s", hipGetErrorString(e));
+  }
+  KArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.Q = p->Q; a.R = p->R; a.A = p->A; a.B = p->B;
+  a.q = p->q; a.r = p->r; a.x0 = p->x0; a.e = p->e;
+  a.qinv_ws = reinterpret_cast<double *>(d.ptr);
+  a.rinv_ws = reinterpret_cast<double *>(d.ptr + kNaQinv);
+  a.tws = tws;
+  a.gang = reinterpret_cast<Gang *>(gq);
+  a.queue = reinterpret_cast<int *>(gq + kNaGang);
+  a.eps = o->eps; a.max_iter = o->max_iter; a.warm = o->warm_start; a.stop_abs = o->stop_rule;
+  a.spin_limit = d.spin;
+  a.lam = lambda; a.dx = dx; a.du = du; a.stats = stats;
+  a.single.k0 = 0; a.single.N = N; a.single.t0 = 0; a.single.nparts = g; a.single.id = 0;
+  a.ntasks = g;
+  // the placement rule of mpcpcg_solve: a gang of 2..16 parts on one XCD
+  a.one_xcd = (d.xcd_ok && g > 1 && g <= 16 && 8 * g <= d.cap[ki]) ? 1 : 0;
+  hipLaunchKernelGGL(kernel_for(kpw, mpc::kForward), dim3(a.one_xcd ? 8 * g : g), dim3(kpw * mpc::kGroup), 0, s, a);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return na_fail(MPCPCG_EHIP, "launch failed: %s", hipGetErrorString(e));
+  return MPCPCG_OK;
+}
 
 }  // extern "C"

@@ -84,6 +84,9 @@ def load_library(path: str = _LIB_PATH):
     lib.mpcpcg_set_cache_limit.argtypes = [vp, i32]
     lib.mpcpcg_cache_info.argtypes = [vp, C.POINTER(i32), C.POINTER(C.c_int64)]
     lib.mpcpcg_debug_set_wait.argtypes = [vp, C.c_int64, i32]
+    lib.mpcpcg_solve_noalloc.argtypes = [P, O, vp, vp, vp, vp, vp]
+    lib.mpcpcg_noalloc_last_error.argtypes = []
+    lib.mpcpcg_noalloc_last_error.restype = C.c_char_p
     M, T = C.POINTER(ChainModel), C.POINTER(Trajectory)
     lib.mpcpcg_linearize.argtypes = [vp, i32, i64p, M, T] + [vp] * 6 + [vp]
     lib.mpcpcg_line_search.argtypes = [vp, i32, i64p, M, T, vp, vp, vp, C.c_float] + [vp] * 4 + [vp]
@@ -93,7 +96,7 @@ def load_library(path: str = _LIB_PATH):
               "mpcpcg_set_graph", "mpcpcg_autotune", "mpcpcg_set_method", "mpcpcg_linearize",
               "mpcpcg_line_search", "mpcpcg_control_step", "mpcpcg_tuned_schedule",
               "mpcpcg_set_xcd_pinning", "mpcpcg_set_cache_limit", "mpcpcg_cache_info",
-              "mpcpcg_debug_set_wait"):
+              "mpcpcg_debug_set_wait", "mpcpcg_solve_noalloc"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -368,6 +371,18 @@ class Context:
             int(sqp_iters), float(mu), _ptr(lam), _ptr(X_out), opt(U_out), merit.data_ptr(),
             choice.data_ptr(), stats.data_ptr(), _stream()), "mpcpcg_control_step")
         return dict(merit=merit, choice=choice, stats=stats)
+
+
+def mpcpcg_solve_noalloc(prob, lam, dx, du, stats, eps=1e-6, max_iter=0, warm=False, stop="relative"):
+    """mpcpcg_solve_noalloc on caller-owned output tensors (lam, dx [N, 14], du [N-1, 7],
+    stats int32 [1, 4]); no context, nothing allocated by the library."""
+    lib = load_library()
+    N = prob["q"].shape[0]
+    st = lib.mpcpcg_solve_noalloc(C.byref(_problem(prob, 14, 7, N)), C.byref(_opts(eps, max_iter, warm, stop)),
+                                  _ptr(lam), _ptr(dx), _ptr(du) if du.numel() else None, stats.data_ptr(),
+                                  _stream())
+    if st != OK:
+        raise MPCPCGError("mpcpcg_solve_noalloc failed (%d): %s" % (st, lib.mpcpcg_noalloc_last_error().decode()))
 
 
 def to_device(d, device="cuda"):
