@@ -154,8 +154,8 @@ int mpcpcg_backward(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
                     mpcpcg_stats *stats, hipStream_t stream);
 
 /* Schedule control for the batched calls.
- * mpcpcg_set_knots_per_group fixes the knots handled by one workgroup (a multiple of 4
- * from 4 to 32; 0 restores the automatic choice).  mpcpcg_autotune times every
+ * mpcpcg_set_knots_per_group fixes the knots handled by one workgroup (one of 4, 8, 16,
+ * 24, 32, 48; 0 restores the automatic choice).  mpcpcg_autotune times every
  * candidate shape on the given batch (running real solves, outputs overwritten) and
  * caches the fastest for that batch signature; it synchronises the stream.  The chosen
  * value is returned in *knots_per_group (may be NULL). */

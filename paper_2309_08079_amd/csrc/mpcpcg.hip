@@ -30,7 +30,8 @@ using mpc::Task;
 
 constexpr int kNX = 14, kNU = 7;        // register-resident fused path
 constexpr int kWNX = 28, kWNU = 14;     // generic (workspace-staged) path
-constexpr int kKpwChoices[] = {4, 8, 16, 32};
+constexpr int kKpwChoices[] = {4, 8, 16, 24, 32, 48};
+constexpr int kNumKpw = (int)(sizeof(kKpwChoices) / sizeof(kKpwChoices[0]));
 
 // Device arrays owned by a cached schedule: freed with it.
 struct DevArrays {
@@ -273,6 +274,8 @@ KernelFn kernel_for(int kpw, int mode) {
     case 4: return kernel_for<4>(mode);
     case 8: return kernel_for<8>(mode);
     case 16: return kernel_for<16>(mode);
+    case 24: return kernel_for<24>(mode);
+    case 48: return kernel_for<48>(mode);
     default: return kernel_for<32>(mode);
   }
 }
@@ -882,7 +885,7 @@ mpc::ctrl::CtrlArgs ctrl_args(const mpcpcg_chain_model *m, const mpcpcg_trajecto
 // launch starts; every call clears the part of them it uses with a fill kernel on its
 // stream (a kernel, not a memset, so the call may be captured into a graph).
 constexpr int64_t kNaMaxKnots = 2048;
-constexpr int kNaMaxParts = (int)(kNaMaxKnots / 16);  // horizons beyond 32 knots use 16 per part
+constexpr int kNaMaxParts = (int)(kNaMaxKnots / 16);  // horizons beyond 48 knots use 16 per part
 constexpr size_t na_round(size_t n) { return (n + 255) / 256 * 256; }
 constexpr size_t kNaQinv = na_round((size_t)kNaMaxKnots * kNX * mpc::kGroup * sizeof(double));
 constexpr size_t kNaRinv = na_round((size_t)kNaMaxKnots * (kNU + kNX) * mpc::kURows * sizeof(double));
@@ -898,7 +901,7 @@ struct NaDevice {
   std::once_flag once;
   int rc = MPCPCG_OK;
   unsigned char *ptr = nullptr;
-  int cap[4] = {0, 0, 0, 0};  // co-resident workgroups per shape of kKpwChoices
+  int cap[kNumKpw] = {};  // co-resident workgroups per shape of kKpwChoices
   int xcd_ok = 0;
   int64_t spin = 0;
 };
@@ -955,7 +958,7 @@ void na_setup(NaDevice &d, int dev) {
   (void)hipGetLastError();
   d.xcd_ok = (nxcc == 8 && prop.multiProcessorCount % 8 == 0) ? 1 : 0;
   d.spin = (int64_t)2000 * khz;  // 2 s
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < kNumKpw; ++i) {
     const int k = kKpwChoices[i];
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(kernel_for(k, mpc::kForward)),
@@ -1529,7 +1532,7 @@ int mpcpcg_solve_noalloc(const mpcpcg_problem *p, const mpcpcg_opts *o, float *l
   if (d.rc) return d.rc;
   const int N = p->N;
   int kpw = 16, ki = 2;  // the shape mpcpcg_solve takes on a context with default settings
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < kNumKpw; ++i)
     if (N <= kKpwChoices[i]) { kpw = kKpwChoices[i]; ki = i; break; }
   const int g = (N + kpw - 1) / kpw;
   if (g > kNaMaxParts || g > d.cap[ki])

@@ -28,7 +28,7 @@ namespace mpc {
 
 enum Mode : int { kForm = 0, kForward = 1, kAdjoint = 2 };
 
-constexpr int kMaxWaves = 8;    // waves per workgroup (32 knots x 16 lanes / 64)
+constexpr int kMaxWaves = 12;   // waves per workgroup (48 knots x 16 lanes / 64)
 
 struct ProbDesc {
   int64_t k0;       // first knot row of the problem in the packed arrays
@@ -166,9 +166,10 @@ __device__ __forceinline__ double uni(double v) {
 // Register budget: the FP64 S row (84 VGPRs) stays resident for the whole solve and the
 // FP32 Phi^-1 row lives in LDS; the occupancy target sets how many knots stay resident.
 // A 32-knot workgroup (8 waves) fits only two waves per SIMD anyway, so it keeps the full
-// 256-VGPR budget; smaller shapes target three.
+// 256-VGPR budget; the other shapes target three (a 24-knot workgroup has 6 waves, two
+// per compute unit; a 48-knot one has 12 waves, one per compute unit).
 template <int KPW>
-constexpr int waves_per_eu() { return KPW >= 32 ? 2 : 3; }
+constexpr int waves_per_eu() { return KPW == 32 ? 2 : 3; }
 // The formation-only and epilogue-only kernels of the factorisation path hold no PCG state:
 // two waves per SIMD give them the registers of the formation without spills.
 template <int KPW, int PHASE>
@@ -210,7 +211,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
   float *const pl = reinterpret_cast<float *>(big);
   __shared__ double red_w[2][2][NW];           // [phase][value][wave]
   __shared__ double tot[2];
-  __shared__ double d2[2][2][kGroup];  // [side][r, s][lane] two knots beyond each end
+  __shared__ double rcp_sh[2];  // 1 / gamma_prev, 1 / alpha_prev of the PCG loop
   __shared__ int sh_task;
   __shared__ int sh_abort;
 
@@ -823,9 +824,11 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       ex_d[1][slot + 1][lane] = warm ? lam : 0.0;
       sync_setup();
       double r = rhs, rm = ex_d[0][slot][lane], rp = ex_d[0][slot + 2][lane];
-      // r and s of the knots two beyond each end live in d2, touched only by the edge slots
-      if (slot == 0) { d2[0][0][lane] = ex_d[1][0][lane]; d2[0][1][lane] = 0.0; }
-      if (slot == KPW - 1) { d2[1][0][lane] = ex_d[1][KPW + 1][lane]; d2[1][1][lane] = 0.0; }
+      // r and s of the knot two beyond this part's end, kept in the registers of the edge
+      // slots' lanes (the only lanes that use them)
+      double r2 = 0.0, s2 = 0.0;
+      if (slot == 0) r2 = ex_d[1][0][lane];
+      if (slot == KPW - 1) r2 = ex_d[1][KPW + 1][lane];
       if (warm) {
         // r = gamma - S lambda_0; eta_ref = gamma^T Phi^-1 gamma; then r's halos two deep
         const double lm = ex_d[1][slot][lane], lp = ex_d[1][slot + 2][lane];
@@ -842,8 +845,8 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         eta_ref = uni(tot[0]);
         rm = ex_d[0][slot][lane];
         rp = ex_d[0][slot + 2][lane];
-        if (slot == 0) d2[0][0][lane] = ex_d[1][0][lane];
-        if (slot == KPW - 1) d2[1][0][lane] = ex_d[1][KPW + 1][lane];
+        if (slot == 0) r2 = ex_d[1][0][lane];
+        if (slot == KPW - 1) r2 = ex_d[1][KPW + 1][lane];
       }
       // Algorithm 1 with its two inner products gathered at one barrier per iteration
       // (Chronopoulos-Gear form): u = Phi^-1 r and w = S u, then gam = r^T u (= eta') and
@@ -856,6 +859,10 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       double p = 0.0, sv = 0.0, sm = 0.0, sp = 0.0;
       double gam_prev = 1.0, alpha_prev = 1.0, tau = 0.0;
       const bool edge_wave = multi && (wave == 0 || wave == NW - 1);
+      // the reciprocals of the previous iteration's gamma and alpha are formed before the
+      // iteration's first workgroup barrier by a wave that does no ghost product (it waits
+      // there anyway), so only one division remains after the gang barrier
+      const int rcp_wave = NW > 2 ? 1 : 0;
       for (it = 0;; ++it) {
         if (aborted) break;
         // (1) u = Phi^-1 r on this knot, and on the ghost knot beyond each end
@@ -863,13 +870,20 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         ex_f[slot + 1][lane] = u;
         if (edge_wave) {
           const bool left = slot == 0;
-          const double r2 = d2[left ? 0 : 1][0][lane];
           const float ug = precond_row(left ? KPW : KPW + 1, (float)(left ? r2 : r), (float)(left ? rm : rp),
                                        (float)(left ? r : r2));
           if (slot == 0) ex_f[0][lane] = ug;
           if (slot == KPW - 1) ex_f[KPW + 1][lane] = ug;
         }
+        if (wave == rcp_wave) {
+          const double rg = 1.0 / gam_prev, ra = 1.0 / alpha_prev;
+          if (wl == 0) {
+            rcp_sh[0] = rg;
+            rcp_sh[1] = ra;
+          }
+        }
         __syncthreads();
+        const double rg = uni(rcp_sh[0]), ra = uni(rcp_sh[1]);
         // (2) w = S u
         const double um = (double)ex_f[slot][lane], up = (double)ex_f[slot + 2][lane];
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
@@ -901,8 +915,8 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
           break;
         }
         if (it >= max_iter) break;
-        const double beta = it == 0 ? 0.0 : gam / gam_prev;
-        const double pSp = it == 0 ? del : del - beta * gam / alpha_prev;
+        const double beta = it == 0 ? 0.0 : gam * rg;
+        const double pSp = it == 0 ? del : del - beta * gam * ra;
         if (!(pSp > 0.0) || __builtin_isinf(pSp)) {
           status = MPCPCG_BREAKDOWN;
           break;
@@ -921,9 +935,8 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         rp = __builtin_fma(-alpha, sp, rp);
         if (multi && (slot == 0 || slot == KPW - 1)) {
           const int side = slot == 0 ? 0 : 1;
-          const double s2 = __builtin_fma(beta, d2[side][1][lane], ex_d[1][side ? KPW + 1 : 0][lane]);
-          d2[side][1][lane] = s2;
-          d2[side][0][lane] = __builtin_fma(-alpha, s2, d2[side][0][lane]);
+          s2 = __builtin_fma(beta, s2, ex_d[1][side ? KPW + 1 : 0][lane]);
+          r2 = __builtin_fma(-alpha, s2, r2);
         }
         gam_prev = gam;
         alpha_prev = alpha;

@@ -106,7 +106,7 @@ def test_solve_single_problem_matches_kkt_and_oracle_pcg(ctx):
 
 
 @pytest.mark.parametrize("N", [1, 2, 3, 15, 16, 17, 31, 33, 64, 100, 128, 256, 512])
-@pytest.mark.parametrize("kpw", [0, 4, 16])
+@pytest.mark.parametrize("kpw", [0, 4, 16, 24, 48])
 def test_solve_horizons_and_shapes(ctx, N, kpw):
     ctx.mpcpcg_set_knots_per_group(kpw)
     try:
@@ -214,7 +214,7 @@ def check_batch(out, packed, off, eps=EPS, tol=1e-5, it_tol=lambda iters: 1, pro
     return ref
 
 
-@pytest.mark.parametrize("kpw", [4, 8, 16, 32])
+@pytest.mark.parametrize("kpw", [4, 8, 16, 24, 32, 48])
 def test_batched_ragged_horizons(ctx, kpw):
     Ns = [1, 5, 32, 33, 64, 100, 2, 17, 47, 129]
     probs, packed, off = _batch_case(Ns, 300)
