@@ -10,9 +10,11 @@
  *                    on the null stream;
  *   floors_barrier   microseconds per barrier round of `gangs` independent gangs of `parts`
  *                    workgroups (2..64) using the solver's protocol (each part publishes a
- *                    tagged 16-byte word with device-scope stores, then polls its partners';
- *                    sleep != 0 waits ~1,500 cycles before the first poll as the solver
- *                    does; pin = 1 runs each gang on one XCD and needs gangs % 8 == 0);
+ *                    tagged 16-byte word, then polls its partners'; sleep != 0 waits ~1,500
+ *                    cycles before the first poll as the solver's device-scope barrier
+ *                    does; pin = 1 runs each gang on one XCD and needs gangs % 8 == 0;
+ *                    l2 = 0 exchanges device-scope words, l2 = 1 (needs pin = 1) exchanges
+ *                    through the XCD's L2 as the solver does for gangs on one XCD);
  *                    gangs * parts must not exceed 8 per compute unit.  *us_per_round is
  *                    negative if a wait gave up (2 s);
  *   floors_lds_read  aggregate LDS read bandwidth in bytes/s over `blocks` workgroups of
@@ -34,7 +36,7 @@ extern "C" {
 #endif
 
 int floors_launch(int launches, double *us_per_launch);
-int floors_barrier(int gangs, int parts, int rounds, int sleep, int pin, double *us_per_round);
+int floors_barrier(int gangs, int parts, int rounds, int sleep, int pin, int l2, double *us_per_round);
 int floors_lds_read(int blocks, int iters, double *bytes_per_s);
 int floors_read(int64_t buffer_bytes, int blocks, int passes, double *bytes_per_s);
 

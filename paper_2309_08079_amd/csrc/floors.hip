@@ -2,9 +2,10 @@
 // bench.py; not part of the solve path):
 //   floors_launch      latency of back-to-back empty kernel launches on one stream;
 //   floors_barrier     one cross-workgroup barrier round with the solver's protocol (the
-//                      sync points of PCG: every part publishes a tagged 16-byte word with
-//                      device-scope stores and polls its partners' words), isolated or with
-//                      many gangs at once, gangs spread over the XCDs or each on one XCD;
+//                      sync points of PCG: every part publishes a tagged 16-byte word and
+//                      polls its partners' words), isolated or with many gangs at once, gangs
+//                      spread over the XCDs or each on one XCD, through device-scope words or
+//                      (gangs on one XCD) through that XCD's L2;
 //   floors_lds_read    aggregate LDS read bandwidth (ds_read_b128, conflict free);
 //   floors_read        aggregate read bandwidth of a buffer of a given size, re-read by
 //                      every workgroup (sizes that stay in L2, in the last-level cache, or
@@ -31,6 +32,7 @@ struct BarrierArgs {
   int64_t *ticks;  // [gangs] wall-clock ticks of all rounds (part 0), -1 if a wait gave up
 };
 
+template <int L2X>
 __global__ void __launch_bounds__(64) barrier_probe(BarrierArgs a) {
   const int b = blockIdx.x, lane = threadIdx.x;
   int gang, part;
@@ -48,14 +50,19 @@ __global__ void __launch_bounds__(64) barrier_probe(BarrierArgs a) {
   for (int r = 0; r < a.rounds && !gave_up; ++r) {
     const int par = r & 1;
     const uint32_t tag = (uint32_t)r + 1u;
-    if (lane == 0) mpc::store_pair(rs, off(par, part), tag, (double)r);
+    if (lane == 0) {
+      if (L2X)
+        mpc::store_pair_l2(rs, off(par, part), tag, (double)r);
+      else
+        mpc::store_pair(rs, off(par, part), tag, (double)r);
+    }
     if (a.sleep > 0) __builtin_amdgcn_s_sleep(24);
     const bool mine = lane < a.parts;
     const long long ts = wall_clock64();
     int polls = 0;
     while (true) {
       bool ok = true;
-      if (mine) ok = mpc::pair_has(mpc::load_pair(rs, off(par, lane)), tag);
+      if (mine) ok = mpc::pair_has(L2X ? mpc::load_pair_l2(rs, off(par, lane)) : mpc::load_pair(rs, off(par, lane)), tag);
       if (__ballot(ok) == ~0ull) break;
       __builtin_amdgcn_s_sleep(1);
       if ((++polls & 63) == 0 && wall_clock64() - ts > a.spin) {
@@ -149,9 +156,10 @@ int floors_launch(int launches, double *us_per_launch) {
   return 0;
 }
 
-int floors_barrier(int gangs, int parts, int rounds, int sleep, int pin, double *us_per_round) {
+int floors_barrier(int gangs, int parts, int rounds, int sleep, int pin, int l2, double *us_per_round) {
   if (gangs < 1 || parts < 2 || parts > 64 || rounds < 1 || !us_per_round) return -2;
   if (pin && gangs % 8) return -2;
+  if (l2 && !pin) return -2;  // the XCD-local exchange needs every gang on one XCD
   int dev = 0, cus = 0;
   FCHK(hipGetDevice(&dev));
   FCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -166,7 +174,10 @@ int floors_barrier(int gangs, int parts, int rounds, int sleep, int pin, double 
   a.words = words; a.parts = parts; a.rounds = rounds; a.sleep = sleep; a.pin = pin;
   a.spin = 2000 * clock_khz();  // 2 s
   a.ticks = ticks;
-  hipLaunchKernelGGL(barrier_probe, dim3(gangs * parts), dim3(64), 0, 0, a);
+  if (l2)
+    hipLaunchKernelGGL(barrier_probe<1>, dim3(gangs * parts), dim3(64), 0, 0, a);
+  else
+    hipLaunchKernelGGL(barrier_probe<0>, dim3(gangs * parts), dim3(64), 0, 0, a);
   FCHK(hipGetLastError());
   FCHK(hipDeviceSynchronize());
   int64_t *h = new int64_t[gangs];

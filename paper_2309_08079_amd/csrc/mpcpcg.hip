@@ -349,10 +349,11 @@ int launch_single(mpcpcg_ctx *c, KArgs &a, int N, int kpw, int mode, hipStream_t
   if (g > c->max_tasks) return fail(c, MPCPCG_EINVAL, "N=%d exceeds the context's task workspace", N);
   a.single.k0 = 0; a.single.N = N; a.single.t0 = 0; a.single.nparts = g; a.single.id = 0;
   a.probs = nullptr; a.tasks = nullptr; a.ntasks = g; a.persistent = 0;
-  // a gang of 2..16 parts runs on one XCD: launch 8 workgroups per part, of which the
-  // ones dispatched to the first XCD (blockIdx % 8 == 0) take the parts.  Measured 3-4%
-  // faster at N = 64..256 and 3% slower at 32 parts (N = 512), which stays spread.
-  a.one_xcd = (c->xcd_ok && c->xcd_pin && g > 1 && g <= 16 && 8 * g <= cap) ? 1 : 0;
+  // a gang that fits one XCD's share of the device runs there: launch 8 workgroups per
+  // part; the ones running on XCD 0 take the parts and the loop barriers exchange through
+  // that XCD's L2
+  a.one_xcd = (c->xcd_ok && c->xcd_pin && g > 1 && 8 * g <= cap) ? 1 : 0;
+  a.l2x = a.one_xcd;
   hipLaunchKernelGGL(kernel_for(kpw, mode), dim3(a.one_xcd ? 8 * g : g), dim3(kpw * mpc::kGroup), 0, s, a);
   HIPCHK(c, hipGetLastError());
   return MPCPCG_OK;
@@ -610,6 +611,7 @@ int launch_batched(mpcpcg_ctx *c, Schedule *s, KArgs &a, int mode, int want_pin,
   a.probs = pin ? s->d_xprobs : s->d_probs;
   a.tasks = pin ? s->d_xtasks : s->d_tasks;
   a.xoff = pin ? s->d_xoff : nullptr;
+  a.l2x = pin ? 1 : 0;  // a gang's workgroups all pop their XCD's list
   a.ntasks = s->ntasks;
   a.persistent = 1;
   const int grid = pin ? s->xgrid : s->grid[mode];
@@ -1562,8 +1564,9 @@ int mpcpcg_solve_noalloc(const mpcpcg_problem *p, const mpcpcg_opts *o, float *l
   a.lam = lambda; a.dx = dx; a.du = du; a.stats = stats;
   a.single.k0 = 0; a.single.N = N; a.single.t0 = 0; a.single.nparts = g; a.single.id = 0;
   a.ntasks = g;
-  // the placement rule of mpcpcg_solve: a gang of 2..16 parts on one XCD
-  a.one_xcd = (d.xcd_ok && g > 1 && g <= 16 && 8 * g <= d.cap[ki]) ? 1 : 0;
+  // the placement rule of mpcpcg_solve: a gang that fits one XCD's share runs there
+  a.one_xcd = (d.xcd_ok && g > 1 && 8 * g <= d.cap[ki]) ? 1 : 0;
+  a.l2x = a.one_xcd;
   hipLaunchKernelGGL(kernel_for(kpw, mpc::kForward), dim3(a.one_xcd ? 8 * g : g), dim3(kpw * mpc::kGroup), 0, s, a);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return na_fail(MPCPCG_EHIP, "launch failed: %s", hipGetErrorString(e));

@@ -96,6 +96,25 @@ __device__ __forceinline__ u32x4 load_pair(__amdgpu_buffer_rsrc_t rs, uint32_t o
   return __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kDeviceScope);
 }
 __device__ __forceinline__ bool pair_has(u32x4 w, uint32_t tag) { return w.y == tag && w.w == tag; }
+// The same exchange inside one XCD, for a gang whose parts all run on it: stores go to the
+// XCD's L2 (the per-CU L1 is write-through) and loads carry the non-temporal bit, which
+// makes them miss the CU's L1 and read the L2 (a load with only sc0 set is served from the
+// CU's L1 and would keep returning a stale line).  Measured on MI355X: ~0.4 us per
+// barrier round of 32 parts, against ~1.0 us for the device-scope words.
+constexpr int kL2Load = 2;  // cache-policy bit nt
+__device__ __forceinline__ void store_pair_l2(__amdgpu_buffer_rsrc_t rs, uint32_t off, uint32_t tag, double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const u32x4 d = {(uint32_t)u, tag, (uint32_t)(u >> 32), tag};
+  __builtin_amdgcn_raw_buffer_store_b128(d, rs, off, 0, 0);
+}
+__device__ __forceinline__ u32x4 load_pair_l2(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kL2Load);
+}
+// Tag of loop barrier n of a launch: (launch generation mod 256) << 24 | (n + 1), so that a
+// word left by an earlier launch never carries a live tag, whichever cache still holds it.
+__device__ __forceinline__ uint32_t loop_tag(uint64_t gen, int n) {
+  return ((uint32_t)(gen & 0xffu) << 24) | ((uint32_t)(n + 1) & 0xffffffu);
+}
 __device__ __forceinline__ double pair_value(u32x4 w) {
   return __builtin_bit_cast(double, ((uint64_t)w.z << 32) | w.x);
 }
@@ -119,8 +138,10 @@ struct KArgs {
   const int32_t *xoff;   // [9] or nullptr: the tasks of XCD x are [xoff[x], xoff[x+1]), popped
                          // from queue[4 + x] by the workgroups running on XCD x only, so all
                          // parts of a gang run on one XCD
-  int32_t one_xcd;       // non-persistent: the grid holds 8 workgroups per part and only those
-                         // with blockIdx % 8 == 0 (dispatched to one XCD) run, part blockIdx / 8
+  int32_t one_xcd;       // non-persistent: the grid holds 8 workgroups per part; those running
+                         // on XCD 0 (HW_REG_XCC_ID) take the parts from queue[4], the rest exit
+  int32_t l2x;           // 1: every gang's parts run on one XCD (per-XCD lists or one_xcd), so
+                         // the loop barriers exchange through that XCD's L2
   // workspace
   void *tws;             // TaskWS<NX>[ntasks]
   Gang *gang;            // [nprobs]
@@ -252,8 +273,18 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       if (task >= a.ntasks) break;
     } else {
       if (iter_task > 0) break;
-      if (a.one_xcd && (blockIdx.x & 7u)) break;
-      task = a.one_xcd ? (int)(blockIdx.x >> 3) : (int)blockIdx.x;
+      if (a.one_xcd) {
+        if (tid == 0) {
+          unsigned x;
+          asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+          sh_task = (x & 7u) ? a.ntasks : atomicAdd(&a.queue[4], 1);
+        }
+        __syncthreads();
+        task = uni(sh_task);
+        if (task >= a.ntasks) break;
+      } else {
+        task = (int)blockIdx.x;
+      }
     }
     const Task tk = a.probs ? a.tasks[task] : Task{0, task};
     const ProbDesc pd = a.probs ? a.probs[tk.prob] : a.single;
@@ -322,6 +353,22 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       }
       return 0;
     };
+    // the tagged words of the loop barriers: through one XCD's L2 when the gang runs there
+    const bool l2x = a.l2x != 0;
+    auto put_pair = [&](uint32_t off, uint32_t tag, double v) {
+      if (l2x)
+        store_pair_l2(wsr, off, tag, v);
+      else
+        store_pair(wsr, off, tag, v);
+    };
+    auto get_pair = [&](uint32_t off) -> u32x4 {
+      u32x4 w;
+      if (l2x)
+        w = load_pair_l2(wsr, off);
+      else
+        w = load_pair(wsr, off);
+      return w;
+    };
     // Loop barrier: ND double channels of halos, NR partial sums
     // (read from red_w[ph] when the problem has one part); totals land in tot[].
     auto sync_point = [&](auto nd_c, auto nr_c, int ph) {
@@ -333,14 +380,14 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       } else if (multi) {
         if (wave == 0) {
           const int par = nsync & 1;
-          const uint32_t tag = (uint32_t)nsync + 1u;
+          const uint32_t tag = loop_tag(gen, nsync);
           // test hook: the launch's first wait expects a tag that no part writes
           const uint32_t want_tag = (a.stall && nsync == 0) ? 0xffffffffu : tag;
           if (NR > 0 && wl < NR) {  // this part's sum of value wl, its waves in order
             double ps = 0.0;
 #pragma unroll
             for (int w = 0; w < NW; ++w) ps += red_w[ph][wl][w];
-            store_pair(wsr, ws_off(tws[my_t].tg.red[par][wl]), tag, ps);
+            put_pair(ws_off(tws[my_t].tg.red[par][wl]), tag, ps);
           }
           const int side = wl >> 4, l = wl & 15;
           const int nb = side == 0 ? part - 1 : part + 1;
@@ -351,11 +398,12 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
           double v0 = 0.0, v1 = 0.0;
           int ab = 0, polls = 0;
           const long long t_start = wall_clock64();
-          // The last part's words land ~1 us after the first part arrives, so an immediate
-          // poll almost always fails and only adds traffic at the coherence point, which
-          // every other gang's polls share: waiting ~1,500 cycles first measured 10% faster
-          // on 256 x N=512 (and no slower for one problem).
-          __builtin_amdgcn_s_sleep(24);
+          // Device scope: the last part's words land ~1 us after the first part arrives, so
+          // an immediate poll almost always fails and only adds traffic at the coherence
+          // point, which every other gang's polls share: waiting ~1,500 cycles first
+          // measured 10% faster on 256 x N=512 (and no slower for one problem).  Through
+          // one XCD's L2 a round takes ~0.4 us, and polling at once measured fastest.
+          if (!l2x) __builtin_amdgcn_s_sleep(24);
           for (int g0 = 0; g0 < G && !ab; g0 += 64) {
             const int g = g0 + wl;
             const bool mine = NR > 0 && g < G;
@@ -367,14 +415,14 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
               if (mine) {
 #pragma unroll
                 for (int v = 0; v < NR; ++v) {
-                  rw[v] = load_pair(wsr, ws_off(rsrc->red[par][v]));
+                  rw[v] = get_pair(ws_off(rsrc->red[par][v]));
                   ok &= pair_has(rw[v], want_tag);
                 }
               }
               if (halo) {
 #pragma unroll
                 for (int c = 0; c < ND; ++c) {
-                  hq[c] = load_pair(wsr, ws_off(hsrc->hv[par][c][srcside][l]));
+                  hq[c] = get_pair(ws_off(hsrc->hv[par][c][srcside][l]));
                   ok &= pair_has(hq[c], want_tag);
                 }
               }
@@ -515,7 +563,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
     auto put_d = [&](int c, double v) {
       ex_d[c][slot + 1][lane] = v;
       if (multi && (slot == 0 || slot == KPW - 1)) {
-        store_pair(wsr, ws_off(tws[my_t].tg.hv[nsync & 1][c][slot == 0 ? 0 : 1][lane]), (uint32_t)nsync + 1u, v);
+        put_pair(ws_off(tws[my_t].tg.hv[nsync & 1][c][slot == 0 ? 0 : 1][lane]), loop_tag(gen, nsync), v);
       }
     };
     // publish a double vector whose neighbours need two knots deep: LDS channel 0, and to the
@@ -525,7 +573,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       if (multi && (slot <= 1 || slot >= KPW - 2)) {
         const int side = slot <= 1 ? 0 : 1;
         const int c = (slot == 0 || slot == KPW - 1) ? 0 : 1;
-        store_pair(wsr, ws_off(tws[my_t].tg.hv[nsync & 1][c][side][lane]), (uint32_t)nsync + 1u, v);
+        put_pair(ws_off(tws[my_t].tg.hv[nsync & 1][c][side][lane]), loop_tag(gen, nsync), v);
       }
     };
     // per-wave partial of a lane value (deterministic order), written to red_w[ph][v]
@@ -796,8 +844,8 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         row_fma14_f32(acc2, xp, m);
         return rowv ? (acc0 + acc1) + acc2 : 0.0f;
       };
-      // one barrier per iteration; the cap keeps barrier tags far from 32-bit wrap-around
-      const int max_iter = (int)min((int64_t)(a.max_iter > 0 ? a.max_iter : (int64_t)N * NX), (int64_t)1 << 29);
+      // one barrier per iteration; the cap keeps barrier indices within the 24 bits the tags give them
+      const int max_iter = (int)min((int64_t)(a.max_iter > 0 ? a.max_iter : (int64_t)N * NX), (int64_t)1 << 23);
       const bool warm = (MODE == kForward) && a.warm;
       if (warm && act && rowv) lam = (double)a.lam[kb * NX + lane];
       // setup exchange: boundary Phi^-1 rows; gamma at depths 1 and 2 (cold) or gamma and

@@ -125,6 +125,29 @@ def test_placements_agree_bit_for_bit(ctx):
     check_against_oracle(outs[0], packed, off)
 
 
+@pytest.mark.parametrize("N", [40, 100, 512])
+def test_single_solve_on_one_xcd_agrees_with_spread_gang(ctx, N):
+    # a single solve whose gang runs on one XCD exchanges its loop barriers through that
+    # XCD's L2; spread over the device it uses device-scope words: same arithmetic, same bits
+    from paper_2309_08079_amd.mpcpcg import to_device
+    p = synth.problem(N, seed=7300 + N)
+    d = to_device(p)
+    outs = []
+    for pin in (True, False):
+        ctx.mpcpcg_set_xcd_pinning(pin)
+        o = ctx.mpcpcg_solve(d, eps=EPS)
+        torch.cuda.synchronize()
+        outs.append({k: v.clone() for k, v in o.items()})
+    ctx.mpcpcg_set_xcd_pinning(True)
+    for k in ("lam", "dx", "du", "stats"):
+        assert torch.equal(outs[0][k], outs[1][k]), k
+    ref = orc.solve(p, eps=EPS)
+    st = stats(outs[0]["stats"])[0]
+    assert st["status"] == orc.OK and abs(int(st["iters"]) - int(ref["iters"])) <= 1
+    assert rel(outs[0]["lam"].cpu().numpy(), ref["lam"]) < 1e-5
+    assert rel(outs[0]["dx"].cpu().numpy(), ref["dx"]) < 1e-5
+
+
 def test_cache_is_bounded_over_many_signatures(ctx):
     # 100 distinct horizon signatures through a context limited to 6 per cache: the
     # entries and their device memory stay bounded and every solve still matches the oracle
