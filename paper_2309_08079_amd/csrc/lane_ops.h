@@ -58,6 +58,30 @@ __device__ __forceinline__ double group_sum_to_last(double v) {
   return v;
 }
 
+// 64-bit DPP move with a row mask: lanes of rows outside ROWS get 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64_rows(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROWS, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROWS, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+constexpr int kRowBcast15 = 0x142;  // DPP row_bcast:15 (lane 15 of a row to the next row)
+constexpr int kRowBcast31 = 0x143;  // DPP row_bcast:31 (lane 31 to rows 2 and 3)
+
+// Sum over the 64 lanes of the wave with a fixed reduction shape, (g0 + g1) + (g2 + g3) of
+// the four 16-lane row sums (identical rounding in every wave that calls it), carried
+// across rows by DPP row broadcasts; the result is uniform (read from lane 63).
+__device__ __forceinline__ double wave_sum_fast(double v) {
+  double g = group_sum_to_last(v);
+  g += dpp_f64_rows<kRowBcast15, 0xA>(g);  // rows 1, 3: + lane 15 of rows 0, 2
+  g += dpp_f64_rows<kRowBcast31, 0xC>(g);  // rows 2, 3: + lane 31 (g0 + g1)
+  const uint64_t u = __builtin_bit_cast(uint64_t, g);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, 63);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), 63);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // Sum over the 64 lanes of the wave with a fixed reduction shape (identical rounding in
 // every wave that calls it); the result is returned in every lane.
 __device__ __forceinline__ double wave_sum(double v) {

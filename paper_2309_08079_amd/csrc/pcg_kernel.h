@@ -441,7 +441,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
 #pragma unroll
             for (int c = 0; c < ND; ++c) ex_d[c][dst][l] = has ? pair_value(hq[c]) : 0.0;
           }
-          const double w0 = wave_sum(v0), w1 = wave_sum(v1);
+          const double w0 = wave_sum_fast(v0), w1 = wave_sum_fast(v1);
           if (wl == 0) {
             tot[0] = w0;
             tot[1] = w1;
@@ -578,16 +578,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
     };
     // per-wave partial of a lane value (deterministic order), written to red_w[ph][v]
     auto put_red = [&](int ph, int v, double x) {
-      const double g = group_sum_to_last(x);
-      const uint64_t u = __builtin_bit_cast(uint64_t, g);
-      const uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
-      double s = 0.0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t l2 = __builtin_amdgcn_readlane(lo, 16 * q + 15);
-        const uint32_t h2 = __builtin_amdgcn_readlane(hi, 16 * q + 15);
-        s += __builtin_bit_cast(double, ((uint64_t)h2 << 32) | l2);
-      }
+      const double s = wave_sum_fast(x);
       if (wl == 0) red_w[ph][v][wave] = s;
     };
 
@@ -827,21 +818,23 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       // ================================================================== PCG
       refresh();
       // r~ row = Phi^-1 row . [x(b-1), x(b), x(b+1)] for the rows of knot slot ps (a ghost
-      // slot for the recomputed neighbour knots), read back one block at a time so that
-      // only 14 of its values occupy registers
+      // slot for the recomputed neighbour knots): two blocks are read from LDS up front and
+      // the third while the first product runs, so that at most 28 of its values occupy
+      // registers and only two LDS round trips are exposed
       auto precond_row = [&](int ps, float xm, float x0v, float xp) {
         const float *row = pl + (ps * NX + (rowv ? lane : 0)) * kPRow;
         float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
-        float m[NX];
+        float m0[NX], m1[NX], m2[NX];
 #pragma unroll
-        for (int j = 0; j < NX; ++j) m[j] = row[j];
-        row_fma14_f32(acc0, xm, m);
+        for (int j = 0; j < NX; ++j) {
+          m0[j] = row[j];
+          m1[j] = row[NX + j];
+        }
+        row_fma14_f32(acc0, xm, m0);
 #pragma unroll
-        for (int j = 0; j < NX; ++j) m[j] = row[NX + j];
-        row_fma14_f32(acc1, x0v, m);
-#pragma unroll
-        for (int j = 0; j < NX; ++j) m[j] = row[2 * NX + j];
-        row_fma14_f32(acc2, xp, m);
+        for (int j = 0; j < NX; ++j) m2[j] = row[2 * NX + j];
+        row_fma14_f32(acc1, x0v, m1);
+        row_fma14_f32(acc2, xp, m2);
         return rowv ? (acc0 + acc1) + acc2 : 0.0f;
       };
       // one barrier per iteration; the cap keeps barrier indices within the 24 bits the tags give them
