@@ -42,7 +42,8 @@ def kernel_sources():
     import glob
 
     root = os.path.dirname(os.path.abspath(__file__))
-    srcs = sorted(glob.glob(os.path.join(root, "paper_2309_08079_amd", "csrc", "*")))
+    srcs = sorted(p for p in glob.glob(os.path.join(root, "paper_2309_08079_amd", "csrc", "*"))
+                  if os.path.isfile(p) and not p.endswith(".pyc"))
     return [os.path.relpath(p, root) for p in srcs] + ["include/mpcpcg.h"]
 
 
@@ -106,6 +107,13 @@ def ingest_counters(prof_dir):
             if not m or m.group(2) not in MODE_OF_TEMPLATE:
                 continue
             acc.setdefault((MODE_OF_TEMPLATE[m.group(2)], m.group(1)), []).append(float(r["Counter_Value"]))
+        shapes = {}
+        for mode, kpw in acc:
+            shapes.setdefault(mode, set()).add(kpw)
+        for mode, ks in shapes.items():
+            if len(ks) > 1:
+                raise SystemExit("the %s pass holds %s launches of several workgroup shapes (%s): take the "
+                                 "counter passes with a fixed --kpw" % (name, mode, sorted(ks)))
         for (mode, kpw), v in acc.items():
             d = per_launch.setdefault(mode, {"knots_per_group": int(kpw)})
             d[key + "_kib_raw"] = float(np.mean(v))
