@@ -122,6 +122,10 @@ struct WideSchedule {
   ProbDesc *d_gprobs = nullptr;
   Task *d_gtasks = nullptr;
   int gntasks = 0, gmax_parts = 0;
+  // the same tasks in eight per-XCD lists (nullptr when a gang does not fit one XCD's share)
+  ProbDesc *d_gxprobs = nullptr;
+  Task *d_gxtasks = nullptr;
+  int32_t *d_gxoff = nullptr;
 };
 
 // Schedule choice of the batched PCG launch for one horizon signature.
@@ -445,9 +449,8 @@ int get_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, int kpw, Schedu
   // persistent grid puts cap / 8 on each.  When every gang fits in that, each problem (in
   // longest-first order) goes to the XCD with the least work so far, and all parts of a
   // gang run on one XCD (each workgroup reads its XCD from the hardware and pops only that
-  // XCD's list).  Its barrier round trips stay device-scope; measured ~8% faster for the
-  // 256 x N = 512 batch than gangs spread over all eight.  Needs a batch that fills all
-  // eight.
+  // XCD's list).  Its loop barriers then exchange through that XCD's L2.  Needs a batch
+  // that fills all eight.
   constexpr int kXcds = 8;
   int max_parts = 0;
   for (const auto &d : sorted) max_parts = std::max(max_parts, d.nparts);
@@ -691,6 +694,42 @@ int wide_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, WideSchedule *
       (void)hipGetLastError();
       return fail(c, MPCPCG_ENOMEM, "cannot allocate the gang schedule of a %d-problem batch", B);
     }
+    // Per-XCD lists (as for the 14-state batches): each problem, longest first, goes to the
+    // XCD with the least work, and a workgroup pops only the list of the XCD it runs on, so
+    // a gang's parts share that XCD's L2 for their barriers.  Needs every gang to fit the
+    // cap / 8 workgroups of one XCD; XCDs left without problems just exit.
+    int nb = 0;
+    HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                  &nb, reinterpret_cast<const void *>(mpc::wide::wide_pcg_gang<kWNX, kWKnots>), kWKnots * 64, 0));
+    const int cap = nb * c->cus;
+    constexpr int kXcds = 8;
+    if (c->xcd_ok && cap % kXcds == 0 && w->gmax_parts <= cap / kXcds) {
+      std::vector<std::vector<int>> lists(kXcds);
+      std::vector<int64_t> load(kXcds, 0);
+      for (int b : order) {
+        const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        lists[x].push_back(b);
+        load[x] += pd[b].N;
+      }
+      std::vector<ProbDesc> xp(gp);
+      std::vector<Task> xt;
+      std::vector<int32_t> xoff(kXcds + 1, 0);
+      for (int x = 0; x < kXcds; ++x) {
+        xoff[x] = (int32_t)xt.size();
+        for (int b : lists[x]) {
+          xp[b].t0 = (int32_t)xt.size();
+          for (int j = 0; j < xp[b].nparts; ++j) xt.push_back(Task{b, j});
+        }
+      }
+      xoff[kXcds] = (int32_t)xt.size();
+      w->d_gxprobs = w->mem.upload(xp.data(), xp.size());
+      w->d_gxtasks = w->mem.upload(xt.data(), xt.size());
+      w->d_gxoff = w->mem.upload(xoff.data(), xoff.size());
+      if (!w->d_gxprobs || !w->d_gxtasks || !w->d_gxoff) {
+        (void)hipGetLastError();
+        return fail(c, MPCPCG_ENOMEM, "cannot allocate the per-XCD gang lists of a %d-problem batch", B);
+      }
+    }
   }
   std::vector<mpc::wide::CrTask> tasks;
   for (int s = 1; s < maxN; s *= 2) {
@@ -796,9 +835,16 @@ int wide_run(mpcpcg_ctx *c, const std::vector<int64_t> &off, mpc::wide::WArgs &a
     mw::GangArgs ga;
     std::memset(&ga, 0, sizeof ga);
     ga.tws = c->w_tws; ga.gang = c->w_gang; ga.queue = c->w_queue;
-    ga.probs = w->d_gprobs; ga.tasks = w->d_gtasks; ga.ntasks = w->gntasks;
+    ga.ntasks = w->gntasks;
     ga.spin_limit = c->spin_ticks;
-    hipLaunchKernelGGL(fn, dim3(std::min(w->gntasks, cap)), dim3(kWKnots * 64), 0, s, a, ga);
+    int grid = std::min(w->gntasks, cap);
+    if (w->d_gxoff && c->xcd_pin) {  // gangs on one XCD each: the full persistent grid
+      ga.probs = w->d_gxprobs; ga.tasks = w->d_gxtasks; ga.xoff = w->d_gxoff; ga.l2x = 1;
+      grid = cap;
+    } else {
+      ga.probs = w->d_gprobs; ga.tasks = w->d_gtasks;
+    }
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kWKnots * 64), 0, s, a, ga);
     HIPCHK(c, hipGetLastError());
     hipLaunchKernelGGL((mw::wide_epilogue<kWNX, kWNU>), dim3((w->nknots + mw::kFormWaves - 1) / mw::kFormWaves),
                        dim3(mw::kFormWaves * 64), 0, s, a);

@@ -41,11 +41,15 @@ struct WTag {
 struct GangArgs {
   void *tws;              // WTag[ntasks]
   Gang *gang;             // [problems]
-  int *queue;             // [0] head, [1] workgroups finished, [2] launch generation
+  int *queue;             // [0] head, [1] workgroups finished, [2] launch generation,
+                          // [4 + x] head of XCD x's list
   const ProbDesc *probs;  // per problem: k0, N, t0 (first task), nparts, id
   const Task *tasks;      // longest problem first, the parts of a problem adjacent
+  const int32_t *xoff;    // [9] or nullptr: the tasks of XCD x are [xoff[x], xoff[x+1]),
+                          // popped by the workgroups running on XCD x only, so that every
+                          // gang runs on one XCD and its barriers use that XCD's L2
   int32_t ntasks;
-  int32_t pad;
+  int32_t l2x;            // 1 with xoff: barrier words through the XCD's L2
   int64_t spin_limit;     // wall-clock ticks before a wait gives up
 };
 
@@ -71,10 +75,37 @@ __global__ void __launch_bounds__(KW * 64) __attribute__((amdgpu_waves_per_eu(3,
   WTag *tws = reinterpret_cast<WTag *>(g.tws);
   const __amdgpu_buffer_rsrc_t wsr = ws_rsrc(g.tws);
   auto ws_off = [&](const void *p) { return (uint32_t)((const char *)p - (const char *)g.tws); };
+  // launch generation (advanced by the last workgroup of every launch), part of every tag
+  const uint64_t gen = (uint64_t)(uint32_t)uni(__hip_atomic_load(&g.queue[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  const bool l2x = g.l2x != 0;
+  auto put_pair = [&](uint32_t off, uint32_t tag, double v) {
+    if (l2x)
+      store_pair_l2(wsr, off, tag, v);
+    else
+      store_pair(wsr, off, tag, v);
+  };
+  auto get_pair = [&](uint32_t off) -> u32x4 {
+    u32x4 w;
+    if (l2x)
+      w = load_pair_l2(wsr, off);
+    else
+      w = load_pair(wsr, off);
+    return w;
+  };
 
   for (;;) {
     __syncthreads();
-    if (tid == 0) sh_task = atomicAdd(&g.queue[0], 1);
+    if (tid == 0) {
+      if (g.xoff) {
+        unsigned x;
+        asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(x));
+        x &= 7u;
+        const int t = g.xoff[x] + atomicAdd(&g.queue[4 + x], 1);
+        sh_task = t < g.xoff[x + 1] ? t : g.ntasks;  // this XCD's list is empty
+      } else {
+        sh_task = atomicAdd(&g.queue[0], 1);
+      }
+    }
     __syncthreads();
     const int task = uni(sh_task);
     if (task >= g.ntasks) break;
@@ -154,9 +185,9 @@ __global__ void __launch_bounds__(KW * 64) __attribute__((amdgpu_waves_per_eu(3,
     // a boundary row of channel c (first knot: side 0, last knot: side 1) to the gang
     auto put_row = [&](int c, double x) {
       if (multi && h == 0 && rowv) {
-        const uint32_t tag = (uint32_t)nsync + 1u;
-        if (wave == 0) store_pair(wsr, ws_off(tws[my_t].rows[nsync & 1][c][0][row]), tag, x);
-        if (wave == KW - 1) store_pair(wsr, ws_off(tws[my_t].rows[nsync & 1][c][1][row]), tag, x);
+        const uint32_t tag = loop_tag(gen, nsync);
+        if (wave == 0) put_pair(ws_off(tws[my_t].rows[nsync & 1][c][0][row]), tag, x);
+        if (wave == KW - 1) put_pair(ws_off(tws[my_t].rows[nsync & 1][c][1][row]), tag, x);
       }
     };
     auto poll_spin = [&](int &polls, long long t_start) -> bool {
@@ -187,14 +218,15 @@ __global__ void __launch_bounds__(KW * 64) __attribute__((amdgpu_waves_per_eu(3,
         return;
       }
       const int par = nsync & 1;
-      const uint32_t tag = (uint32_t)nsync + 1u;
+      const uint32_t tag = loop_tag(gen, nsync);
       if (wave == 0 && lane < nv) {  // this part's sums, its waves in order
         double ps = 0.0;
         for (int w = 0; w < KW; ++w) ps += red_w[lane][w];
-        store_pair(wsr, ws_off(tws[my_t].red[par][lane]), tag, ps);
+        put_pair(ws_off(tws[my_t].red[par][lane]), tag, ps);
       }
-      // the last part's words land ~1 us after the first part arrives
-      __builtin_amdgcn_s_sleep(24);
+      // device scope: the last part's words land ~1 us after the first part arrives; through
+      // one XCD's L2 a round takes ~0.4 us and polling at once is fastest
+      if (!l2x) __builtin_amdgcn_s_sleep(24);
       const long long t_start = wall_clock64();
       int polls = 0;
       bool ab = false;
@@ -214,15 +246,15 @@ __global__ void __launch_bounds__(KW * 64) __attribute__((amdgpu_waves_per_eu(3,
         while (true) {
           bool ok = true;
           if (want_red) {
-            rw0 = load_pair(wsr, ws_off(tws[pd.t0 + gp].red[par][0]));
+            rw0 = get_pair(ws_off(tws[pd.t0 + gp].red[par][0]));
             ok &= pair_has(rw0, tag);
             if (nv > 1) {
-              rw1 = load_pair(wsr, ws_off(tws[pd.t0 + gp].red[par][1]));
+              rw1 = get_pair(ws_off(tws[pd.t0 + gp].red[par][1]));
               ok &= pair_has(rw1, tag);
             }
           }
           if (want_halo) {
-            hq = load_pair(wsr, hoff);
+            hq = get_pair(hoff);
             ok &= pair_has(hq, tag);
           }
           if (__ballot(ok) == ~0ull) break;
@@ -313,7 +345,8 @@ __global__ void __launch_bounds__(KW * 64) __attribute__((amdgpu_waves_per_eu(3,
       hp[s][l] = hin[0][s][l];
     }
     const double tau = a.stop_abs ? (double)a.eps : (double)a.eps * (double)a.eps * eta_ref;
-    const int max_iter = a.max_iter > 0 ? a.max_iter : N * NX;
+    // two barriers per iteration: the cap keeps barrier indices within the tags' 24 bits
+    const int max_iter = min(a.max_iter > 0 ? a.max_iter : N * NX, 1 << 22);
     int status = MPCPCG_NOT_CONVERGED, it = 0;
     double res = rv;  // r of Algorithm 1 (this lane's row)
     eta_new = eta;
@@ -410,7 +443,19 @@ __global__ void __launch_bounds__(KW * 64) __attribute__((amdgpu_waves_per_eu(3,
   if (tid == 0) {
     const int d = __hip_atomic_fetch_add(&g.queue[1], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     if (d == (int)gridDim.x - 1) {
+      // a list whose XCD ran no workgroup of this launch (a placement the host did not
+      // expect) leaves its problems unsolved: they report TIMEOUT instead of stale stats
+      if (g.xoff) {
+        for (int x = 0; x < 8; ++x) {
+          const int popped = __hip_atomic_load(&g.queue[4 + x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          for (int t = g.xoff[x] + max(popped, 0); t < g.xoff[x + 1]; ++t) {
+            const Task tk = g.tasks[t];
+            if (tk.part == 0) put_stats(a.stats + g.probs[tk.prob].id, 0, MPCPCG_TIMEOUT, 0.0f);
+          }
+        }
+      }
       __hip_atomic_store(&g.queue[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int x = 0; x < 8; ++x) __hip_atomic_store(&g.queue[4 + x], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_fetch_add(&g.queue[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&g.queue[1], 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }

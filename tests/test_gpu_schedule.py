@@ -148,6 +148,38 @@ def test_single_solve_on_one_xcd_agrees_with_spread_gang(ctx, N):
     assert rel(outs[0]["dx"].cpu().numpy(), ref["dx"]) < 1e-5
 
 
+def test_wide_gangs_on_one_xcd_agree_with_the_global_queue():
+    # the 28-state gang PCG with per-XCD lists (barriers through each XCD's L2) and with the
+    # global queue (device-scope barriers): same arithmetic, same bits; ragged horizons,
+    # a single-knot problem and a batch with fewer problems than XCDs
+    from paper_2309_08079_amd.mpcpcg import Context
+    for Ns, seed0 in (([70, 3, 130, 1, 41, 96, 9, 64, 200, 17], 7700), ([90, 33], 7800)):
+        probs = synth.batch(Ns, nx=28, nu=14, seed0=seed0)
+        packed, off = synth.pack(probs)
+        c = Context(28, 14, max_total_knots=int(off[-1]), max_batch=len(Ns))
+        try:
+            c.mpcpcg_set_method("pcg")
+            d = dev(packed)
+            outs = []
+            for pin in (True, False):
+                c.mpcpcg_set_xcd_pinning(pin)
+                o = c.mpcpcg_solve_batched(d, off, eps=EPS)
+                torch.cuda.synchronize()
+                outs.append({k: v.clone() for k, v in o.items()})
+            for k in ("lam", "dx", "du", "stats"):
+                assert torch.equal(outs[0][k], outs[1][k]), (Ns, k)
+            st = stats(outs[0]["stats"])
+            ref = orc.solve_batch(packed, off, eps=EPS, threads=8)
+            lam = outs[0]["lam"].cpu().numpy()
+            for b in range(len(Ns)):
+                k0, k1 = off[b], off[b + 1]
+                assert st[b]["status"] == orc.OK, b
+                assert abs(int(st[b]["iters"]) - int(ref["iters"][b])) <= max(2, int(0.1 * ref["iters"][b])), b
+                assert rel(lam[k0:k1], ref["lam"][k0:k1]) < 1e-5, b
+        finally:
+            c.close()
+
+
 def test_cache_is_bounded_over_many_signatures(ctx):
     # 100 distinct horizon signatures through a context limited to 6 per cache: the
     # entries and their device memory stay bounded and every solve still matches the oracle
