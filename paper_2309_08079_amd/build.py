@@ -26,6 +26,8 @@ def flags():
 
 FLOORS_LIB = os.path.join(PKG, "libmpcpcg_floors.so")
 FLOORS_SOURCES = [os.path.join(CSRC, "floors.hip")]
+# debug build: LDS filled with NaN at the start of every task of the fused kernel
+POISON_LIB = os.path.join(PKG, "libmpcpcg_poison.so")
 
 
 def _compile(sources, lib, verbose, extra):
@@ -45,9 +47,10 @@ def _compile(sources, lib, verbose, extra):
 
 
 def build(verbose: bool = False, extra=()) -> str:
-    """Compile libmpcpcg.so and the benchmark's floor probes, libmpcpcg_floors.so (always
-    recompiles both)."""
+    """Compile libmpcpcg.so, its LDS-poisoning debug build libmpcpcg_poison.so and the
+    benchmark's floor probes, libmpcpcg_floors.so (always recompiles all three)."""
     _compile(FLOORS_SOURCES, FLOORS_LIB, verbose, extra)
+    _compile(SOURCES, POISON_LIB, verbose, list(extra) + ["-DMPC_LDS_POISON=1"])
     return _compile(SOURCES, LIB, verbose, extra)
 
 

@@ -73,6 +73,17 @@ struct TaskWS {       // per task; read by the other parts of the same gang
   double hs[2][2][kGroup];       // [side][channel][lane]
 };
 
+// Debug build (MPC_LDS_POISON=1, libmpcpcg_poison.so): every workgroup fills its LDS with a
+// NaN pattern at the start of each task, so that a read of LDS the task has not written
+// turns the outputs into NaN instead of silently reusing an earlier task's values.
+#ifndef MPC_LDS_POISON
+#define MPC_LDS_POISON 0
+#endif
+__device__ __forceinline__ void lds_poison(void *p, size_t bytes, int tid, int nt) {
+  uint32_t *w = reinterpret_cast<uint32_t *>(p);
+  for (size_t i = tid; i < bytes / 4; i += nt) w[i] = 0x7fc00000u;  // a quiet NaN, as float and as double
+}
+
 // Integral constant for the compile-time shape of a barrier.
 template <int V>
 struct IC {
@@ -285,6 +296,16 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       } else {
         task = (int)blockIdx.x;
       }
+    }
+    if constexpr (MPC_LDS_POISON) {
+      __syncthreads();
+      lds_poison(big, sizeof big, tid, NT);
+      lds_poison(ex_d, sizeof ex_d, tid, NT);
+      lds_poison(ex_f, sizeof ex_f, tid, NT);
+      lds_poison(red_w, sizeof red_w, tid, NT);
+      lds_poison(tot, sizeof tot, tid, NT);
+      lds_poison(rcp_sh, sizeof rcp_sh, tid, NT);
+      __syncthreads();
     }
     const Task tk = a.probs ? a.tasks[task] : Task{0, task};
     const ProbDesc pd = a.probs ? a.probs[tk.prob] : a.single;

@@ -19,7 +19,10 @@ METHODS = {"pcg": 0, "factor": 1, "auto": 2}   # MPCPCG_METHOD_PCG / _FACTOR / _
 EINVAL, EUNSUPPORTED, ENOMEM, EHIP = -1, -2, -3, -4
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmpcpcg.so")
+# the LDS-poisoning debug build of the same sources (see build.py)
+POISON_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmpcpcg_poison.so")
 _lib = None
+_libs = {}
 
 
 class MPCPCGError(RuntimeError):
@@ -56,11 +59,16 @@ STATS_DTYPE = np.dtype([("iters", np.int32), ("status", np.int32), ("final_ratio
                         ("reserved", np.int32)])
 
 
-def load_library(path: str = _LIB_PATH):
-    """Load libmpcpcg.so (built by ``paper_2309_08079_amd.build``)."""
+def load_library(path: str = None):
+    """Load libmpcpcg.so (built by ``paper_2309_08079_amd.build``), or another build of the
+    same sources at ``path``; each is loaded once."""
     global _lib
-    if _lib is not None:
-        return _lib
+    if path is None:
+        if _lib is not None:
+            return _lib
+        path = _LIB_PATH
+    if path in _libs:
+        return _libs[path]
     if not os.path.exists(path):
         raise MPCPCGError("libmpcpcg.so not found at %s; build it with "
                           "`python -m paper_2309_08079_amd.build`" % path)
@@ -98,7 +106,9 @@ def load_library(path: str = _LIB_PATH):
               "mpcpcg_set_xcd_pinning", "mpcpcg_set_cache_limit", "mpcpcg_cache_info",
               "mpcpcg_debug_set_wait", "mpcpcg_solve_noalloc"):
         getattr(lib, f).restype = C.c_int
-    _lib = lib
+    _libs[path] = lib
+    if _lib is None:
+        _lib = lib
     return lib
 
 
@@ -158,8 +168,8 @@ def stats_to_numpy(t):
 class Context:
     """Owns an mpcpcg_ctx on the current device."""
 
-    def __init__(self, nx=14, nu=7, max_total_knots=1 << 17, max_batch=4096):
-        self.lib = load_library()
+    def __init__(self, nx=14, nu=7, max_total_knots=1 << 17, max_batch=4096, lib_path=None):
+        self.lib = load_library(lib_path)
         self.nx, self.nu = nx, nu
         h = C.c_void_p()
         st = self.lib.mpcpcg_create(C.byref(h), nx, nu, int(max_total_knots), int(max_batch))
