@@ -58,6 +58,18 @@ __device__ __forceinline__ double group_sum_to_last(double v) {
   return v;
 }
 
+// group_sum_to_last of two values, their steps interleaved (each rounds as on its own).
+__device__ __forceinline__ void group_sums2(double &a, double &b) {
+  a += dpp_f64<kRowShr + 1>(a);
+  b += dpp_f64<kRowShr + 1>(b);
+  a += dpp_f64<kRowShr + 2>(a);
+  b += dpp_f64<kRowShr + 2>(b);
+  a += dpp_f64<kRowShr + 4>(a);
+  b += dpp_f64<kRowShr + 4>(b);
+  a += dpp_f64<kRowShr + 8>(a);
+  b += dpp_f64<kRowShr + 8>(b);
+}
+
 // 64-bit DPP move with a row mask: lanes of rows outside ROWS get 0.
 template <int CTRL, int ROWS>
 __device__ __forceinline__ double dpp_f64_rows(double v) {
@@ -67,19 +79,20 @@ __device__ __forceinline__ double dpp_f64_rows(double v) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 constexpr int kRowBcast15 = 0x142;  // DPP row_bcast:15 (lane 15 of a row to the next row)
-constexpr int kRowBcast31 = 0x143;  // DPP row_bcast:31 (lane 31 to rows 2 and 3)
 
-// Sum over the 64 lanes of the wave with a fixed reduction shape, (g0 + g1) + (g2 + g3) of
-// the four 16-lane row sums (identical rounding in every wave that calls it), carried
-// across rows by DPP row broadcasts; the result is uniform (read from lane 63).
-__device__ __forceinline__ double wave_sum_fast(double v) {
+// Two 32-lane sums at once: lanes 0..31 carry the terms of the first sum, lanes 32..63
+// those of the second.  Each is g0 + g1 of its two 16-lane row sums (fixed shape); both
+// results are uniform (read from lanes 31 and 63).  One reduction chain serves both sums.
+__device__ __forceinline__ void half_sums(double v, double &s0, double &s1) {
   double g = group_sum_to_last(v);
   g += dpp_f64_rows<kRowBcast15, 0xA>(g);  // rows 1, 3: + lane 15 of rows 0, 2
-  g += dpp_f64_rows<kRowBcast31, 0xC>(g);  // rows 2, 3: + lane 31 (g0 + g1)
   const uint64_t u = __builtin_bit_cast(uint64_t, g);
-  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, 63);
-  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), 63);
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+  const uint32_t lo0 = __builtin_amdgcn_readlane((uint32_t)u, 31);
+  const uint32_t hi0 = __builtin_amdgcn_readlane((uint32_t)(u >> 32), 31);
+  const uint32_t lo1 = __builtin_amdgcn_readlane((uint32_t)u, 63);
+  const uint32_t hi1 = __builtin_amdgcn_readlane((uint32_t)(u >> 32), 63);
+  s0 = __builtin_bit_cast(double, ((uint64_t)hi0 << 32) | lo0);
+  s1 = __builtin_bit_cast(double, ((uint64_t)hi1 << 32) | lo1);
 }
 
 // Sum over the 64 lanes of the wave with a fixed reduction shape (identical rounding in

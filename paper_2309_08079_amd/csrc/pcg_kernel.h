@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
   __shared__ __attribute__((aligned(16))) unsigned char big[kExBytes > kPlBytes ? kExBytes : kPlBytes];
   auto ex_m = reinterpret_cast<double (*)[NX][kGroup]>(big);
   float *const pl = reinterpret_cast<float *>(big);
-  __shared__ double red_w[2][2][NW];           // [phase][value][wave]
+  __shared__ __attribute__((aligned(16))) double red_g[2][KPW][2];  // [phase][knot slot][value]
   __shared__ double tot[2];
   __shared__ double rcp_sh[2];  // 1 / gamma_prev, 1 / alpha_prev of the PCG loop
   __shared__ int sh_task;
@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       lds_poison(big, sizeof big, tid, NT);
       lds_poison(ex_d, sizeof ex_d, tid, NT);
       lds_poison(ex_f, sizeof ex_f, tid, NT);
-      lds_poison(red_w, sizeof red_w, tid, NT);
+      lds_poison(red_g, sizeof red_g, tid, NT);
       lds_poison(tot, sizeof tot, tid, NT);
       lds_poison(rcp_sh, sizeof rcp_sh, tid, NT);
       __syncthreads();
@@ -374,6 +374,19 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       }
       return 0;
     };
+    // this part's totals of its NR per-knot partials (wave 0, after a workgroup barrier):
+    // lanes 0..31 add value 0 of knot slots wl, wl + 32, ..., lanes 32..63 value 1, then one
+    // packed reduction (fixed shape) gives both, uniform
+    auto part_sums = [&](int ph, int nr, double &s0, double &s1) {
+      const int vi = wl >> 5;
+      double v = 0.0;
+      if (vi < nr) {
+#pragma unroll
+        for (int k = 0; k < KPW; k += 32)
+          if (k + (wl & 31) < KPW) v += red_g[ph][k + (wl & 31)][vi];
+      }
+      half_sums(v, s0, s1);
+    };
     // the tagged words of the loop barriers: through one XCD's L2 when the gang runs there
     const bool l2x = a.l2x != 0;
     auto put_pair = [&](uint32_t off, uint32_t tag, double v) {
@@ -391,7 +404,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       return w;
     };
     // Loop barrier: ND double channels of halos, NR partial sums
-    // (read from red_w[ph] when the problem has one part); totals land in tot[].
+    // (read from red_g[ph] when the problem has one part); totals land in tot[].
     auto sync_point = [&](auto nd_c, auto nr_c, int ph) {
       constexpr int ND = decltype(nd_c)::value, NR = decltype(nr_c)::value;
       __syncthreads();
@@ -404,11 +417,10 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
           const uint32_t tag = loop_tag(gen, nsync);
           // test hook: the launch's first wait expects a tag that no part writes
           const uint32_t want_tag = (a.stall && nsync == 0) ? 0xffffffffu : tag;
-          if (NR > 0 && wl < NR) {  // this part's sum of value wl, its waves in order
-            double ps = 0.0;
-#pragma unroll
-            for (int w = 0; w < NW; ++w) ps += red_w[ph][wl][w];
-            put_pair(ws_off(tws[my_t].tg.red[par][wl]), tag, ps);
+          if (NR > 0) {  // this part's sums over its knots
+            double ps0, ps1;
+            part_sums(ph, NR, ps0, ps1);
+            if (wl < NR) put_pair(ws_off(tws[my_t].tg.red[par][wl]), tag, wl == 0 ? ps0 : ps1);
           }
           const int side = wl >> 4, l = wl & 15;
           const int nb = side == 0 ? part - 1 : part + 1;
@@ -416,7 +428,10 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
           const TagWS *hsrc = &tws[has ? my_t + (side == 0 ? -1 : 1) : my_t].tg;
           const int srcside = side == 0 ? 1 : 0;  // left neighbour's last knot / right's first
           u32x4 hq[ND > 0 ? ND : 1];
-          double v0 = 0.0, v1 = 0.0;
+          // lanes 0..31 read value 0 of 32 parts at a time, lanes 32..63 value 1 (when there
+          // is one), so one packed reduction below gives both totals
+          const int vi = wl >> 5;
+          double v = 0.0;
           int ab = 0, polls = 0;
           const long long t_start = wall_clock64();
           // Device scope: the last part's words land ~1 us after the first part arrives, so
@@ -425,20 +440,17 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
           // measured 10% faster on 256 x N=512 (and no slower for one problem).  Through
           // one XCD's L2 a round takes ~0.4 us, and polling at once measured fastest.
           if (!l2x) __builtin_amdgcn_s_sleep(24);
-          for (int g0 = 0; g0 < G && !ab; g0 += 64) {
-            const int g = g0 + wl;
-            const bool mine = NR > 0 && g < G;
+          for (int g0 = 0; g0 < G && !ab; g0 += 32) {
+            const int g = g0 + (wl & 31);
+            const bool mine = vi < NR && g < G;
             const bool halo = g0 == 0 && has;
             const TagWS *rsrc = &tws[pd.t0 + (mine ? g : 0)].tg;
-            u32x4 rw[NR > 0 ? NR : 1];
+            u32x4 rw = {0u, 0u, 0u, 0u};
             while (true) {
               bool ok = true;
               if (mine) {
-#pragma unroll
-                for (int v = 0; v < NR; ++v) {
-                  rw[v] = get_pair(ws_off(rsrc->red[par][v]));
-                  ok &= pair_has(rw[v], want_tag);
-                }
+                rw = get_pair(ws_off(rsrc->red[par][vi]));
+                ok &= pair_has(rw, want_tag);
               }
               if (halo) {
 #pragma unroll
@@ -452,17 +464,15 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
             }
             // totals over parts in a fixed order and a fixed-shape reduction, so every part
             // computes bit-identical totals
-            if (mine && !ab) {
-              v0 += pair_value(rw[0]);
-              if (NR > 1) v1 += pair_value(rw[NR > 1 ? 1 : 0]);
-            }
+            if (mine && !ab) v += pair_value(rw);
           }
           if (wl < 2 * kGroup && !ab) {
             const int dst = side == 0 ? 0 : KPW + 1;
 #pragma unroll
             for (int c = 0; c < ND; ++c) ex_d[c][dst][l] = has ? pair_value(hq[c]) : 0.0;
           }
-          const double w0 = wave_sum_fast(v0), w1 = wave_sum_fast(v1);
+          double w0, w1;
+          half_sums(v, w0, w1);
           if (wl == 0) {
             tot[0] = w0;
             tot[1] = w1;
@@ -473,14 +483,13 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         ++nsync;
         aborted = aborted || uni(sh_abort) != 0;
       } else {
-        if (tid == 0) {
-          double s0 = 0.0, s1 = 0.0;
-          for (int w = 0; w < NW; ++w) {
-            if (NR > 0) s0 += red_w[ph][0][w];
-            if (NR > 1) s1 += red_w[ph][1][w];
+        if (wave == 0) {
+          double s0, s1;
+          part_sums(ph, NR, s0, s1);
+          if (wl == 0) {
+            tot[0] = s0;
+            tot[1] = s1;
           }
-          tot[0] = s0;
-          tot[1] = s1;
         }
         __syncthreads();
       }
@@ -597,10 +606,16 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         put_pair(ws_off(tws[my_t].tg.hv[nsync & 1][c][side][lane]), loop_tag(gen, nsync), v);
       }
     };
-    // per-wave partial of a lane value (deterministic order), written to red_w[ph][v]
+    // per-knot partial of a lane value (fixed-shape sum over the knot group), written to
+    // red_g[ph][slot][v] by the group's last lane
     auto put_red = [&](int ph, int v, double x) {
-      const double s = wave_sum_fast(x);
-      if (wl == 0) red_w[ph][v][wave] = s;
+      const double g = group_sum_to_last(x);
+      if (lane == kGroup - 1) red_g[ph][slot][v] = g;
+    };
+    // both values at once (the two reduction chains interleave; one 16-byte LDS write)
+    auto put_red2 = [&](int ph, double x0, double x1) {
+      group_sums2(x0, x1);
+      if (lane == kGroup - 1) *reinterpret_cast<double2 *>(&red_g[ph][slot][0]) = make_double2(x0, x1);
     };
 
     // ================================================================== formation
@@ -954,8 +969,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         row_fma14_f64(a2, up, Sp);
         const double w = (a0 + a1) + a2;
         // (3) gam = r^T u, delta = w^T u; w two knots deep to the neighbours
-        put_red(0, 0, r * (double)u);
-        put_red(0, 1, w * (double)u);
+        put_red2(0, r * (double)u, w * (double)u);
         put_d2(w);
         sync_point(IC<2>{}, IC<2>{}, 0);
         const double gam = uni(tot[0]), del = uni(tot[1]);
