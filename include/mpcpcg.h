@@ -314,7 +314,7 @@ int mpcpcg_control_step(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
  * runs under HIP graph capture, tight serving loops, harnesses that forbid allocation.  It
  * takes no context and allocates nothing (no hipMalloc, hipFree, graph or allocating
  * library call).  Its scratch (Q^-1 and (R^-1 | R^-1 B^T) per knot, the exchange words of
- * the workgroups, the gang and queue counters) is one static device array of 7.83 MB that
+ * the workgroups, the gang and queue counters) is one static device array of 7.86 MB that
  * each GPU the library runs on holds until the process ends; the first call on a device
  * resolves that device's copy.  Every call clears the counters and exchange words it uses
  * with a small fill kernel on `stream` (no memset), so calls may be captured into a graph.

@@ -68,8 +68,9 @@ struct TaskWS {       // per task; read by the other parts of the same gang
   uint64_t pad[7];
   double hm[2][NX][kGroup];      // [side][row][col] D^-1 rows of the two boundary knots
   // setup exchange (flag stage 2, once Phi^-1 exists): the boundary knots' Phi^-1 rows and
-  // two halo channels (gamma at depths 1 and 2, or gamma and lambda_0 at depth 1)
-  float hp[2][NX][3 * NX];       // [side][row][col]
+  // two halo channels (gamma at depths 1 and 2, or gamma and lambda_0 at depth 1); a row is
+  // padded to 3 NX + 2 floats, a whole number of 16-byte words and the row stride in LDS
+  float hp[2][NX][3 * NX + 2];   // [side][row][col]
   double hs[2][2][kGroup];       // [side][channel][lane]
 };
 
@@ -120,6 +121,21 @@ __device__ __forceinline__ void store_pair_l2(__amdgpu_buffer_rsrc_t rs, uint32_
 }
 __device__ __forceinline__ u32x4 load_pair_l2(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
   return __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kL2Load);
+}
+// 16 bytes of plain data at device scope (the formation and setup exchanges)
+__device__ __forceinline__ void store16_dev(__amdgpu_buffer_rsrc_t rs, uint32_t off, u32x4 d) {
+  __builtin_amdgcn_raw_buffer_store_b128(d, rs, off, 0, kDeviceScope);
+}
+__device__ __forceinline__ u32x4 load16_dev(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kDeviceScope);
+}
+__device__ __forceinline__ u32x4 pack_d2(double x, double y) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, x), v = __builtin_bit_cast(uint64_t, y);
+  return u32x4{(uint32_t)u, (uint32_t)(u >> 32), (uint32_t)v, (uint32_t)(v >> 32)};
+}
+__device__ __forceinline__ u32x4 pack_f4(float x, float y, float z, float w) {
+  return u32x4{__builtin_bit_cast(uint32_t, x), __builtin_bit_cast(uint32_t, y), __builtin_bit_cast(uint32_t, z),
+               __builtin_bit_cast(uint32_t, w)};
 }
 // Tag of loop barrier n of a launch: (launch generation mod 256) << 24 | (n + 1), so that a
 // word left by an earlier launch never carries a live tag, whichever cache still holds it.
@@ -517,15 +533,21 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
             if (__ballot(seen) == ~0ull) break;
             if ((ab = poll_spin(polls, t_start))) break;
           }
-          if (wl < 2 * kGroup && !ab) {
+          // lane l of each half copies row l of the neighbour's boundary D^-1 (its 16-byte
+          // words all in flight at once)
+          if (wl < 2 * kGroup && (wl & 15) < NX && !ab) {
             const int side = wl >> 4, l = wl & 15;
             const int nbh = side == 0 ? part - 1 : part + 1;
             const bool has = nbh >= 0 && nbh < G;
             const TaskWS<NX> *src = &tws[has ? my_t + (side == 0 ? -1 : 1) : my_t];
             const int dst = side == 0 ? 0 : KPW + 1;
             const int srcside = side == 0 ? 1 : 0;
-            for (int rr = 0; rr < NX; ++rr)
-              ex_m[dst][rr][l] = has ? __hip_atomic_load(&src->hm[srcside][rr][l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+            const uint32_t o = ws_off(&src->hm[srcside][l][0]);
+            u32x4 q[kGroup / 2];
+#pragma unroll
+            for (int k = 0; k < kGroup / 2; ++k) q[k] = has ? load16_dev(wsr, o + 16 * k) : u32x4{0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int k = 0; k < kGroup / 2; ++k) *reinterpret_cast<u32x4 *>(&ex_m[dst][l][2 * k]) = q[k];
           }
           if (wl == 0) sh_abort = ab;
         }
@@ -562,24 +584,42 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
           if ((ab = poll_spin(polls, t_start))) break;
         }
         if (!ab) {
-          constexpr int kRowsF = NX * 3 * NX;
-          for (int t = wl; t < 2 * kRowsF; t += 64) {
-            const int side = t / kRowsF, rem = t % kRowsF, rr = rem / (3 * NX), cc = rem % (3 * NX);
+          // the neighbours' boundary rows, 16-byte words copied flat (the rows of hp and of
+          // pl have the same padded layout), then the two halo channels; every load of a
+          // lane is issued before any of them is used
+          static_assert(3 * NX + 2 == kPRow, "hp rows and Phi^-1 rows in LDS share a layout");
+          constexpr int kW = NX * kPRow / 4;                  // 16-byte words per side
+          constexpr int kPer = (2 * kW + 63) / 64;
+          u32x4 q[kPer];
+#pragma unroll
+          for (int i = 0; i < kPer; ++i) {
+            const int t = wl + 64 * i;
+            const int side = t < kW ? 0 : 1;
             const int nbh = side == 0 ? part - 1 : part + 1;
-            const bool has = nbh >= 0 && nbh < G;
+            const bool has = t < 2 * kW && nbh >= 0 && nbh < G;
             const TaskWS<NX> *src = &tws[has ? my_t + (side == 0 ? -1 : 1) : my_t];
-            pl[((KPW + side) * NX + rr) * kPRow + cc] =
-                has ? __hip_atomic_load(&src->hp[side == 0 ? 1 : 0][rr][cc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0f;
+            q[i] = has ? load16_dev(wsr, ws_off(&src->hp[side == 0 ? 1 : 0][0][0]) + 16 * (t - side * kW))
+                       : u32x4{0u, 0u, 0u, 0u};
           }
+          double hv[2] = {0.0, 0.0};
           if (wl < 2 * kGroup) {
             const int side = wl >> 4, l = wl & 15;
             const int nbh = side == 0 ? part - 1 : part + 1;
             const bool has = nbh >= 0 && nbh < G;
             const TaskWS<NX> *src = &tws[has ? my_t + (side == 0 ? -1 : 1) : my_t];
-            const int dst = side == 0 ? 0 : KPW + 1;
 #pragma unroll
             for (int c = 0; c < 2; ++c)
-              ex_d[c][dst][l] = has ? __hip_atomic_load(&src->hs[side == 0 ? 1 : 0][c][l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+              hv[c] = has ? __hip_atomic_load(&src->hs[side == 0 ? 1 : 0][c][l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+          }
+#pragma unroll
+          for (int i = 0; i < kPer; ++i) {
+            const int t = wl + 64 * i;
+            if (t < 2 * kW) *reinterpret_cast<u32x4 *>(pl + KPW * NX * kPRow + 4 * t) = q[i];
+          }
+          if (wl < 2 * kGroup) {
+            const int dst = (wl >> 4) == 0 ? 0 : KPW + 1;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) ex_d[c][dst][wl & 15] = hv[c];
           }
         }
         if (wl == 0) sh_abort = ab;
@@ -763,13 +803,10 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
 #pragma unroll
       for (int j = 0; j < NX; ++j) ex_m[slot + 1][lane][j] = Dd[j];
     }
-    if (multi && rowv) {
-      if (slot == 0)
-        for (int j = 0; j < NX; ++j)
-          __hip_atomic_store(&tws[my_t].hm[0][lane][j], Dd[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (slot == KPW - 1)
-        for (int j = 0; j < NX; ++j)
-          __hip_atomic_store(&tws[my_t].hm[1][lane][j], Dd[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (multi && rowv && (slot == 0 || slot == KPW - 1)) {
+      const uint32_t o = ws_off(&tws[my_t].hm[slot == 0 ? 0 : 1][lane][0]);
+#pragma unroll
+      for (int k = 0; k < NX / 2; ++k) store16_dev(wsr, o + 16 * k, pack_d2(Dd[2 * k], Dd[2 * k + 1]));
     }
     sync_form();
     // (7) Phi^-1_{b,b-1} = -D_b^-1 S_{b,b-1} D_{b-1}^-1, Phi^-1_{b,b+1} likewise
@@ -884,12 +921,19 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         const int side = slot <= 1 ? 0 : 1;
         if (slot == 0 || slot == KPW - 1) {
           if (rowv) {
+            float row[kPRow];
 #pragma unroll
             for (int j = 0; j < NX; ++j) {
-              __hip_atomic_store(&w.hp[side][lane][j], Pm[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              __hip_atomic_store(&w.hp[side][lane][NX + j], Pd[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              __hip_atomic_store(&w.hp[side][lane][2 * NX + j], Pp[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              row[j] = Pm[j];
+              row[NX + j] = Pd[j];
+              row[2 * NX + j] = Pp[j];
             }
+            row[3 * NX] = 0.0f;
+            row[3 * NX + 1] = 0.0f;
+            const uint32_t o = ws_off(&w.hp[side][lane][0]);
+#pragma unroll
+            for (int k = 0; k < kPRow / 4; ++k)
+              store16_dev(wsr, o + 16 * k, pack_f4(row[4 * k], row[4 * k + 1], row[4 * k + 2], row[4 * k + 3]));
           }
           __hip_atomic_store(&w.hs[side][0][lane], rhs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           if (warm) __hip_atomic_store(&w.hs[side][1][lane], lam, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
