@@ -420,13 +420,16 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       return w;
     };
     // Loop barrier: ND double channels of halos, NR partial sums
-    // (read from red_g[ph] when the problem has one part); totals land in tot[].
-    auto sync_point = [&](auto nd_c, auto nr_c, int ph) {
+    // (read from red_g[ph] when the problem has one part); totals land in tot[].  `after`
+    // runs in every wave right after the closing workgroup barrier, before the abort flag is
+    // read, so that the LDS reads it issues share one round trip with that read.
+    auto sync_point = [&](auto nd_c, auto nr_c, int ph, auto &&after) {
       constexpr int ND = decltype(nd_c)::value, NR = decltype(nr_c)::value;
       __syncthreads();
       if (multi && aborted) {
         // the gang has given up: no part waits any more (outputs are undefined)
         ++nsync;
+        after();
       } else if (multi) {
         if (wave == 0) {
           const int par = nsync & 1;
@@ -497,6 +500,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         }
         __syncthreads();
         ++nsync;
+        after();
         aborted = aborted || uni(sh_abort) != 0;
       } else {
         if (wave == 0) {
@@ -508,8 +512,10 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
           }
         }
         __syncthreads();
+        after();
       }
     };
+    auto nothing = [] {};
     // Formation barrier (barrier 0): the D^-1 rows of the two boundary knots (NX doubles
     // per lane) go through plain stores, then a completion wait and a flag
     // (launch generation << 32) | 1.  It runs once per solve, so it keeps the simpler
@@ -894,21 +900,31 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       // slot for the recomputed neighbour knots): two blocks are read from LDS up front and
       // the third while the first product runs, so that at most 28 of its values occupy
       // registers and only two LDS round trips are exposed
-      auto precond_row = [&](int ps, float xm, float x0v, float xp) {
-        const float *row = pl + (ps * NX + (rowv ? lane : 0)) * kPRow;
-        float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
-        float m0[NX], m1[NX], m2[NX];
+      auto phi_row = [&](int ps) { return pl + (ps * NX + (rowv ? lane : 0)) * kPRow; };
+      auto load_m01 = [&](const float *row, float (&m0)[NX], float (&m1)[NX]) {
 #pragma unroll
         for (int j = 0; j < NX; ++j) {
           m0[j] = row[j];
           m1[j] = row[NX + j];
         }
+      };
+      // the product with the first two blocks already in registers
+      auto precond_m01 = [&](const float *row, const float (&m0)[NX], const float (&m1)[NX], float xm, float x0v,
+                             float xp) {
+        float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f;
+        float m2[NX];
         row_fma14_f32(acc0, xm, m0);
 #pragma unroll
         for (int j = 0; j < NX; ++j) m2[j] = row[2 * NX + j];
         row_fma14_f32(acc1, x0v, m1);
         row_fma14_f32(acc2, xp, m2);
         return rowv ? (acc0 + acc1) + acc2 : 0.0f;
+      };
+      auto precond_row = [&](int ps, float xm, float x0v, float xp) {
+        const float *row = phi_row(ps);
+        float m0[NX], m1[NX];
+        load_m01(row, m0, m1);
+        return precond_m01(row, m0, m1, xm, x0v, xp);
       };
       // one barrier per iteration; the cap keeps barrier indices within the 24 bits the tags give them
       const int max_iter = (int)min((int64_t)(a.max_iter > 0 ? a.max_iter : (int64_t)N * NX), (int64_t)1 << 23);
@@ -962,7 +978,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         put_red(0, 0, rhs * (double)gt);
         __syncthreads();  // every halo read of the setup channels is done
         put_d2(r);
-        sync_point(IC<2>{}, IC<1>{}, 0);
+        sync_point(IC<2>{}, IC<1>{}, 0, nothing);
         eta_ref = uni(tot[0]);
         rm = ex_d[0][slot][lane];
         rp = ex_d[0][slot + 2][lane];
@@ -1006,17 +1022,28 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         __syncthreads();
         const double rg = uni(rcp_sh[0]), ra = uni(rcp_sh[1]);
         // (2) w = S u
+        // (the own block first: it needs no LDS value, so it runs while u of the
+        // neighbouring knots is read)
         const double um = (double)ex_f[slot][lane], up = (double)ex_f[slot + 2][lane];
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-        row_fma14_f64(a0, um, Sm);
         row_fma14_f64(a1, (double)u, Sd);
+        row_fma14_f64(a0, um, Sm);
         row_fma14_f64(a2, up, Sp);
         const double w = (a0 + a1) + a2;
         // (3) gam = r^T u, delta = w^T u; w two knots deep to the neighbours
         put_red2(0, r * (double)u, w * (double)u);
         put_d2(w);
-        sync_point(IC<2>{}, IC<2>{}, 0);
-        const double gam = uni(tot[0]), del = uni(tot[1]);
+        // after the barrier, one LDS round trip: the totals, w of the neighbouring knots
+        // (the halo copies at the part's ends) and w two knots out for the edge slots
+        double tg, td, wm, wp, wh2;
+        sync_point(IC<2>{}, IC<2>{}, 0, [&] {
+          tg = tot[0];
+          td = tot[1];
+          wm = ex_d[0][slot][lane];
+          wp = ex_d[0][slot + 2][lane];
+          wh2 = ex_d[1][slot == 0 ? 0 : KPW + 1][lane];
+        });
+        const double gam = uni(tg), del = uni(td);
         eta_new = gam;
         if (it == 0) {
           if (!warm) eta_ref = gam;  // lambda_0 = 0: r = gamma, so gam = gamma^T Phi^-1 gamma
@@ -1044,7 +1071,6 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         const double alpha = gam / pSp;
         // (4) recurrences on this knot and on the halo copies (depth 1 everywhere, depth 2
         //     at the part's ends)
-        const double wm = ex_d[0][slot][lane], wp = ex_d[0][slot + 2][lane];
         p = __builtin_fma(beta, p, (double)u);
         sv = __builtin_fma(beta, sv, w);
         sm = __builtin_fma(beta, sm, wm);
@@ -1054,8 +1080,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         rm = __builtin_fma(-alpha, sm, rm);
         rp = __builtin_fma(-alpha, sp, rp);
         if (multi && (slot == 0 || slot == KPW - 1)) {
-          const int side = slot == 0 ? 0 : 1;
-          s2 = __builtin_fma(beta, s2, ex_d[1][side ? KPW + 1 : 0][lane]);
+          s2 = __builtin_fma(beta, s2, wh2);
           r2 = __builtin_fma(-alpha, s2, r2);
         }
         gam_prev = gam;
@@ -1072,7 +1097,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       // adjoint): x rows use Q_b^-1 and S_{b,b+1} = -Q_b^-1 A_b^T; u rows of control b-1
       // use R_{b-1}^-1 and W = R_{b-1}^-1 B_{b-1}^T (both written during formation).
       put_d(0, lam);
-      sync_point(IC<1>{}, IC<0>{}, 0);
+      sync_point(IC<1>{}, IC<0>{}, 0, nothing);
       const double lp = ex_d[0][slot + 2][lane];
       double qmin = 0.0;   // q_b - lambda_b  (or gx_b - mu_b)
       if (act && rowv) {
@@ -1111,7 +1136,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         // adjoint: lam holds mu, xrow = nu1x_b, urow = nu1u_{b-1}
         const double mu = lam, n1x = xrow, n1u = urow;
         put_d(0, n1x);
-          sync_point(IC<1>{}, IC<0>{}, 1);
+          sync_point(IC<1>{}, IC<0>{}, 1, nothing);
         const double n1xm = ex_d[0][slot][lane];  // nu1x_{b-1}
         double dxb = 0.0, dxm = 0.0, lb = 0.0, dum = 0.0;
         if (act && rowv) {
