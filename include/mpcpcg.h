@@ -105,7 +105,9 @@ typedef struct {
 
 /* Create a context for problems of dimension (nx, nu).  max_total_knots bounds the
  * knots of one call (sum of N over a batch); max_batch bounds the problems of one call.
- * Allocates device workspace proportional to both on the current device. */
+ * Allocates device workspace proportional to both on the current device.  The parts'
+ * exchange records must fit 2 GiB: max_total_knots / 4 + max_batch <= 195,652 at (14, 7)
+ * and <= 1,016,800 at (28, 14); larger sizes return MPCPCG_EINVAL before any device call. */
 int mpcpcg_create(mpcpcg_ctx **ctx, int32_t nx, int32_t nu, int64_t max_total_knots,
                   int32_t max_batch);
 

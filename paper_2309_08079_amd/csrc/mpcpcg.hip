@@ -1029,6 +1029,10 @@ int mpcpcg_create(mpcpcg_ctx **out, int32_t nx, int32_t nu, int64_t max_total_kn
   const bool wide = (nx == kWNX && nu == kWNU);
   if (!wide && (nx != kNX || nu != kNU)) return MPCPCG_EUNSUPPORTED;
   if (max_total_knots < 1 || max_batch < 1 || max_batch > max_total_knots) return MPCPCG_EINVAL;
+  // the kernels address the parts' exchange records with 32-bit buffer offsets
+  const int64_t records = wide ? (int64_t)sizeof(mpc::wide::WTag) * (max_total_knots / kWKnots + max_batch)
+                               : (int64_t)tws_bytes() * (max_total_knots / 4 + max_batch);
+  if (records > 0x7fffffff) return MPCPCG_EINVAL;
   auto c = std::make_unique<mpcpcg_ctx>();
   c->nx = nx;
   c->nu = nu;

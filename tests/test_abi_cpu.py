@@ -135,7 +135,10 @@ int main(void) {
   int unsupported = mpcpcg_create(&ctx, 3, 1, 16, 1);
   int einval_method = mpcpcg_set_method(0, MPCPCG_METHOD_AUTO);
   int einval_ls = mpcpcg_line_search(0, 1, 0, 0, 0, 0, 0, 0, 0.0f, 0, 0, 0, 0, 0);
-  printf("%d %d %d %d %d %d %d %d %d\n", unsupported, einval_method, einval_ls, ctx == 0,
+  /* exchange records beyond 2 GiB (32-bit offsets in the kernels) */
+  int too_big = mpcpcg_create(&ctx, 14, 7, 4 * (195652LL - 1) + 4, 1);
+  int too_big_wide = mpcpcg_create(&ctx, 28, 14, 4 * 1016801LL, 1);
+  printf("%d %d %d %d %d %d %d %d %d %d %d\n", unsupported, einval_method, einval_ls, ctx == 0, too_big, too_big_wide,
          (int)sizeof(mpcpcg_problem), (int)sizeof(mpcpcg_opts), (int)sizeof(mpcpcg_stats),
          (int)sizeof(mpcpcg_chain_model), (int)sizeof(mpcpcg_trajectory));
   return 0;
@@ -159,10 +162,11 @@ def test_header_is_c_and_the_library_links(tmp_path):
     subprocess.run(cmd, check=True, capture_output=True)
     env = dict(os.environ, LD_LIBRARY_PATH=libdir + ":/opt/rocm/lib:" + os.environ.get("LD_LIBRARY_PATH", ""))
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True, env=env).stdout.split()
-    unsupported, einval_method, einval_ls, ctx_null = (int(v) for v in out[:4])
+    unsupported, einval_method, einval_ls, ctx_null, too_big, too_big_wide = (int(v) for v in out[:6])
     assert unsupported == mpcpcg.EUNSUPPORTED and einval_method == mpcpcg.EINVAL and einval_ls == mpcpcg.EINVAL
     assert ctx_null == 1
-    sizes = [int(v) for v in out[4:]]
+    assert too_big == mpcpcg.EINVAL and too_big_wide == mpcpcg.EINVAL
+    sizes = [int(v) for v in out[6:]]
     assert sizes == [ctypes.sizeof(mpcpcg.Problem), ctypes.sizeof(mpcpcg.Opts), mpcpcg.STATS_DTYPE.itemsize,
                      ctypes.sizeof(mpcpcg.ChainModel), ctypes.sizeof(mpcpcg.Trajectory)]
 
