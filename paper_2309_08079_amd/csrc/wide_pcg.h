@@ -68,10 +68,23 @@ __global__ void __launch_bounds__(KW * 64) __attribute__((amdgpu_waves_per_eu(3,
   __shared__ double tot[2];
   __shared__ int sh_task, sh_abort;
 
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int h = lane >> 5, row = lane & 31;
-  const bool rowv = row < NX;
-  const int r = rowv ? row : 0;
+  // Lane indices are re-derived through an opaque copy of threadIdx.x at the top of every
+  // PCG iteration (refresh below), so that the compiler recomputes the LDS addresses of the
+  // products instead of keeping them live across the loop, where the registers hold S and
+  // Phi^-1.
+  int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  int h = lane >> 5, row = lane & 31;
+  bool rowv = row < NX;
+  int r = rowv ? row : 0;
+  auto refresh = [&]() {
+    asm volatile("" : "+v"(tid));
+    wave = tid >> 6;
+    lane = tid & 63;
+    h = lane >> 5;
+    row = lane & 31;
+    rowv = row < NX;
+    r = rowv ? row : 0;
+  };
   WTag *tws = reinterpret_cast<WTag *>(g.tws);
   const __amdgpu_buffer_rsrc_t wsr = ws_rsrc(g.tws);
   auto ws_off = [&](const void *p) { return (uint32_t)((const char *)p - (const char *)g.tws); };
@@ -356,6 +369,7 @@ __global__ void __launch_bounds__(KW * 64) __attribute__((amdgpu_waves_per_eu(3,
       status = MPCPCG_OK;
     } else {
       for (it = 1; it <= max_iter && !aborted; ++it) {
+        refresh();
         // Upsilon = S p, upsilon = p^T Upsilon
         __syncthreads();
         put_vx(p);
