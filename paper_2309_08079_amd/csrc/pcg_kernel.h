@@ -726,13 +726,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         for (int j = 0; j < NU; ++j) Br[j] = (double)pb[j];
       }
       gj_inverse<NU>(Rr, lane);
-      mm_nn<NU, NU>(Br, Rr, U);
-      mm_nt<NU, NX>(U, Br, th2);
-#pragma unroll
-      for (int j = 0; j < NX; ++j) Sd[j] += th2[j];
-      double rprev = 0.0;
-      if (hasPrev && lane < NU && rv) rprev = (double)rv[(cb - 1) * NU + lane];
-      rhs -= row_dot<NU>(U, rprev);
+      // W first, stored at once, so that it is not live beside U and theta's update
       mm_nt<NU, NX>(Rr, Br, W);
       if (MODE != kForm && hasPrev && lane < kURows) {  // lane NU stores the zero pad row
         double *w = a.rinv_ws + (cb - 1) * (NU + NX) * kURows + lane;
@@ -741,6 +735,13 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
 #pragma unroll
         for (int j = 0; j < NX; ++j) w[(NU + j) * kURows] = W[j];
       }
+      mm_nn<NU, NU>(Br, Rr, U);
+      mm_nt<NU, NX>(U, Br, th2);
+#pragma unroll
+      for (int j = 0; j < NX; ++j) Sd[j] += th2[j];
+      double rprev = 0.0;
+      if (hasPrev && lane < NU && rv) rprev = (double)rv[(cb - 1) * NU + lane];
+      rhs -= row_dot<NU>(U, rprev);
     }
     {
       // (3) own knot: Q_b^-1 enters theta and gamma; (4) S_{b,b+1} = -Q_b^-1 A_b^T
@@ -755,9 +756,6 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
 #pragma unroll
         for (int j = 0; j < NX; ++j) Qi[j] = (j == lane) ? 1.0 : 0.0;
       }
-      // D_0^-1 = Q_0 exactly (the first diagonal block of S is Q_0^-1)
-#pragma unroll
-      for (int j = 0; j < NX; ++j) Dd[j] = Qi[j];
       gj_inverse<NX>(Qi, lane);
       if (MODE != kForm && act) {  // all 16 lanes: rows >= NX are zero, columns are whole lines
         double *w = a.qinv_ws + kb * NX * kGroup + lane;
@@ -787,17 +785,13 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
 #pragma unroll
       for (int j = 0; j < NX; ++j) Sp[j] = -Sx[j];
     }
-    // (5) D_b^-1 = theta_{b-1}^-1 for b >= 1; D_0^-1 = Q_0 exactly (Dd holds the Q_b row).
-    //     Knot slots past the horizon have S_bb = I, so their D^-1 = I stays finite.
-    //     Only the preconditioner needs it (not the factorisation path).
+    // (5) D_b^-1 = S_bb^-1 (theta_{b-1}^-1 for b >= 1, Q_0 up to rounding for b = 0).  Knot
+    //     slots past the horizon have S_bb = I, so their D^-1 = I stays finite.  Only the
+    //     preconditioner needs it (not the factorisation path).
     if constexpr (PHASE == 0) {
-      double Dt[NX];
 #pragma unroll
-      for (int j = 0; j < NX; ++j) Dt[j] = Sd[j];
-      gj_inverse<NX>(Dt, lane);
-      const bool keepQ0 = act && b == 0;
-#pragma unroll
-      for (int j = 0; j < NX; ++j) Dd[j] = keepQ0 ? Dd[j] : Dt[j];
+      for (int j = 0; j < NX; ++j) Dd[j] = Sd[j];
+      gj_inverse<NX>(Dd, lane);
     }
     }  // PHASE != 2 (formation)
     float Pm[NX], Pd[NX], Pp[NX];
