@@ -95,6 +95,16 @@ __device__ __forceinline__ void half_sums(double v, double &s0, double &s1) {
   s1 = __builtin_bit_cast(double, ((uint64_t)hi1 << 32) | lo1);
 }
 
+// Sum over lanes 0..31 (the first two 16-lane rows), g0 + g1 of the row sums: what
+// wave_sum gives when lanes 32..63 hold zeros, at half the cost.  Uniform result.
+__device__ __forceinline__ double sum_rows01(double v) {
+  const double g = group_sum_to_last(v);
+  const uint64_t u = __builtin_bit_cast(uint64_t, g);
+  const uint32_t lo0 = __builtin_amdgcn_readlane((uint32_t)u, 15), hi0 = __builtin_amdgcn_readlane((uint32_t)(u >> 32), 15);
+  const uint32_t lo1 = __builtin_amdgcn_readlane((uint32_t)u, 31), hi1 = __builtin_amdgcn_readlane((uint32_t)(u >> 32), 31);
+  return __builtin_bit_cast(double, ((uint64_t)hi0 << 32) | lo0) + __builtin_bit_cast(double, ((uint64_t)hi1 << 32) | lo1);
+}
+
 // Sum over the 64 lanes of the wave with a fixed reduction shape (identical rounding in
 // every wave that calls it); the result is returned in every lane.
 __device__ __forceinline__ double wave_sum(double v) {

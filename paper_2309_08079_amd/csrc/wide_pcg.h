@@ -191,8 +191,9 @@ __global__ void __launch_bounds__(KW * 64) __attribute__((amdgpu_waves_per_eu(3,
       return h == 0 ? acc + other : other + acc;
     };
     // this wave's knot's share of an inner product, summed over its rows in a fixed order
+    // (the rows live in lanes 0..31)
     auto put_red = [&](int v, double x) {
-      const double s = wave_sum((h == 0 && mine) ? x : 0.0);
+      const double s = sum_rows01((h == 0 && mine) ? x : 0.0);
       if (lane == 0) red_w[v][wave] = s;
     };
     // a boundary row of channel c (first knot: side 0, last knot: side 1) to the gang
@@ -280,7 +281,7 @@ __global__ void __launch_bounds__(KW * 64) __attribute__((amdgpu_waves_per_eu(3,
       }
       if (hw) hin[hc][hs][hrow] = (has && !ab) ? pair_value(hq) : 0.0;
       if (wave == 0) {
-        const double w0 = wave_sum(v0), w1 = wave_sum(v1);
+        const double w0 = wave_sum(v0), w1 = nv > 1 ? wave_sum(v1) : 0.0;
         if (lane == 0) {
           tot[0] = w0;
           tot[1] = w1;
