@@ -432,6 +432,9 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         after();
       } else if (multi) {
         if (wave == 0) {
+          // the whole workgroup waits for this wave until the totals are out: it issues
+          // ahead of the co-resident workgroups' waves meanwhile
+          __builtin_amdgcn_s_setprio(2);
           const int par = nsync & 1;
           const uint32_t tag = loop_tag(gen, nsync);
           // test hook: the launch's first wait expects a tag that no part writes
@@ -497,6 +500,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
             tot[1] = w1;
             sh_abort = ab;
           }
+          __builtin_amdgcn_s_setprio(0);
         }
         __syncthreads();
         ++nsync;
@@ -1000,11 +1004,14 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         const float u = precond_row(slot, (float)rm, (float)r, (float)rp);
         ex_f[slot + 1][lane] = u;
         if (edge_wave) {
+          // (the rest of the workgroup waits for the edge waves' second product)
+          __builtin_amdgcn_s_setprio(1);
           const bool left = slot == 0;
           const float ug = precond_row(left ? KPW : KPW + 1, (float)(left ? r2 : r), (float)(left ? rm : rp),
                                        (float)(left ? r : r2));
           if (slot == 0) ex_f[0][lane] = ug;
           if (slot == KPW - 1) ex_f[KPW + 1][lane] = ug;
+          __builtin_amdgcn_s_setprio(0);
         }
         if (wave == rcp_wave) {
           const double rg = 1.0 / gam_prev, ra = 1.0 / alpha_prev;
