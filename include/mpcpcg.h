@@ -174,9 +174,10 @@ int mpcpcg_tuned_schedule(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_of
                           int32_t *knots_per_group, int32_t *xcd_pinned);
 
 /* Default placement of batched PCG gangs when no tuned choice exists: 1 (default) runs all
- * workgroups of a problem on one XCD when the device reports eight XCDs and the batch has
- * at least eight problems that fit; 0 uses one global task queue.  mpcpcg_autotune times
- * both placements and keeps the faster per signature. */
+ * workgroups of a problem on one XCD when the device reports eight XCDs and every problem's
+ * workgroups fit one XCD's share of the co-resident grid (any batch size; a batch of fewer
+ * than eight problems leaves XCDs idle); 0 uses one global task queue.  mpcpcg_autotune
+ * times both placements and keeps the faster per signature. */
 int mpcpcg_set_xcd_pinning(mpcpcg_ctx *ctx, int32_t enable);
 
 /* Enable (1, default) or disable (0) hipGraph capture/replay in mpcpcg_solve_batched. */

@@ -445,16 +445,17 @@ int get_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, int kpw, Schedu
     return fail(c, MPCPCG_ENOMEM, "cannot allocate the schedule of a %d-problem batch", B);
   }
   for (int m = 0; m < 3; ++m) s->grid[m] = std::min(s->ntasks, cap);
-  // Per-XCD lists: workgroups are dispatched to the eight XCDs in turn, so a full
-  // persistent grid puts cap / 8 on each.  When every gang fits in that, each problem (in
-  // longest-first order) goes to the XCD with the least work so far, and all parts of a
-  // gang run on one XCD (each workgroup reads its XCD from the hardware and pops only that
-  // XCD's list).  Its loop barriers then exchange through that XCD's L2.  Needs a batch
-  // that fills all eight.
+  // Per-XCD lists: workgroups are dispatched to the eight XCDs in turn, so a grid of 8 m
+  // workgroups puts m on each (at most cap / 8 of them resident).  When every gang fits in
+  // cap / 8, each problem (in longest-first order) goes to the XCD with the least work so
+  // far, and all parts of a gang run on one XCD (each workgroup reads its XCD from the
+  // hardware and pops only that XCD's list).  Its loop barriers then exchange through that
+  // XCD's L2.  A batch of fewer than eight problems leaves some lists empty; the grid gives
+  // every XCD as many workgroups as the longest list has tasks, up to cap / 8.
   constexpr int kXcds = 8;
   int max_parts = 0;
   for (const auto &d : sorted) max_parts = std::max(max_parts, d.nparts);
-  if (c->xcd_ok && B >= kXcds && cap % kXcds == 0 && max_parts <= cap / kXcds) {
+  if (c->xcd_ok && cap % kXcds == 0 && max_parts <= cap / kXcds) {
     std::vector<std::vector<int>> lists(kXcds);
     std::vector<int64_t> load(kXcds, 0);
     for (const auto &d : sorted) {
@@ -480,7 +481,9 @@ int get_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, int kpw, Schedu
       (void)hipGetLastError();
       return fail(c, MPCPCG_ENOMEM, "cannot allocate the per-XCD lists of a %d-problem batch", B);
     }
-    s->xgrid = cap;
+    int longest = 0;
+    for (int x = 0; x < kXcds; ++x) longest = std::max(longest, xoff[x + 1] - xoff[x]);
+    s->xgrid = kXcds * std::min(longest, cap / kXcds);
   }
   make_room(c, c->sched, true);
   *out = c->sched.put(key, std::move(s));

@@ -331,8 +331,8 @@ def test_backward_with_primal_gradients(ctx):
 
 
 def test_batched_gangs_on_one_xcd_match_the_global_queue(ctx):
-    # a batch of >= 8 problems runs each gang on one XCD (per-XCD task lists); smaller
-    # batches use the global queue.  Placement must not change any problem's arithmetic:
+    # each gang runs on one XCD (per-XCD task lists; a 4-problem batch leaves half of them
+    # empty).  Placement must not change any problem's arithmetic:
     # the 8-problem batch and the same problems as two 4-problem batches agree bit for bit,
     # forward and adjoint.  Horizons 96 and 40 (6 and 3 parts of 16 knots), seeds 7001 + b.
     Ns = [96, 40, 96, 40, 96, 40, 96, 40]

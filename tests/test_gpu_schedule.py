@@ -102,26 +102,36 @@ def test_autotune_picks_a_shape_caches_it_and_matches_fixed_shape(ctx):
         ctx.mpcpcg_set_xcd_pinning(True)
     for key in ("lam", "dx", "du", "stats"):
         assert torch.equal(tuned[key], fixed[key]), key
-    # the tuned choice is kept per signature: another signature keeps the default
+    # the tuned choice is kept per signature: another signature keeps the default (16
+    # knots per workgroup, each gang on one XCD)
     other = [64, 64]
-    assert ctx.mpcpcg_tuned_schedule(np.cumsum([0] + other)) == (16, False)
+    assert ctx.mpcpcg_tuned_schedule(np.cumsum([0] + other)) == (16, True)
 
 
-def test_placements_agree_bit_for_bit(ctx):
-    # gangs on one XCD (per-XCD lists) and on the global queue run the same arithmetic
-    Ns = [96, 40, 96, 40, 96, 40, 96, 40, 200, 13]
+@pytest.mark.parametrize("Ns", [[96, 40, 96, 40, 96, 40, 96, 40, 200, 13], [512], [200, 13, 96]],
+                         ids=["ten", "lone512", "three"])
+def test_placements_agree_bit_for_bit(ctx, Ns):
+    # gangs on one XCD (per-XCD lists) and on the global queue run the same arithmetic,
+    # forward and adjoint; batches of fewer than eight problems leave some lists empty
     probs = synth.batch(Ns, seed0=7101)
     packed, off = synth.pack(probs)
     d = dev(packed)
-    outs = []
-    for pin in (True, False):
-        ctx.mpcpcg_set_xcd_pinning(pin)
-        o = ctx.mpcpcg_solve_batched(d, off, eps=EPS)
-        torch.cuda.synchronize()
-        outs.append({k: v.clone() for k, v in o.items()})
-    ctx.mpcpcg_set_xcd_pinning(True)
+    outs, grads = [], []
+    try:
+        for pin in (True, False):
+            ctx.mpcpcg_set_xcd_pinning(pin)
+            assert ctx.mpcpcg_tuned_schedule(off)[1] == pin
+            o = ctx.mpcpcg_solve_batched(d, off, eps=EPS)
+            g = ctx.mpcpcg_backward(d, off, o, 2 * o["lam"], eps=EPS)
+            torch.cuda.synchronize()
+            outs.append({k: v.clone() for k, v in o.items()})
+            grads.append({k: v.clone() for k, v in g.items()})
+    finally:
+        ctx.mpcpcg_set_xcd_pinning(True)
     for k in ("lam", "dx", "du", "stats"):
         assert torch.equal(outs[0][k], outs[1][k]), k
+    for k in ("dQ", "dq", "dR", "dA", "dB", "stats"):
+        assert torch.equal(grads[0][k], grads[1][k]), k
     check_against_oracle(outs[0], packed, off)
 
 
