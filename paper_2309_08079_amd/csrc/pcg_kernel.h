@@ -813,27 +813,28 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       for (int k = 0; k < NX / 2; ++k) store16_dev(wsr, o + 16 * k, pack_d2(Dd[2 * k], Dd[2 * k + 1]));
     }
     sync_form();
-    // (7) Phi^-1_{b,b-1} = -D_b^-1 S_{b,b-1} D_{b-1}^-1, Phi^-1_{b,b+1} likewise
+    // (7) Phi^-1_{b,b-1} = -D_b^-1 S_{b,b-1} D_{b-1}^-1, Phi^-1_{b,b+1} likewise.  X = D_b^-1
+    //     S_{b,b-1} is this lane's row; lane m reads row m of the neighbour's D^-1 from LDS
+    //     (two columns at a time) and each column's product broadcasts it across the knot
+    //     group, the terms added in row order
     {
+      const int dr = rowv ? lane : 0;
       double X[NX];
+      auto times_neighbour = [&](int ns, float (&P)[NX]) {
+#pragma unroll
+        for (int j = 0; j < NX; j += 2) {
+          const double2 d = *reinterpret_cast<const double2 *>(&ex_m[ns][dr][j]);
+          double c0 = 0.0, c1 = 0.0;
+          row_fma14_f64(c0, d.x, X);
+          row_fma14_f64(c1, d.y, X);
+          P[j] = (float)(-c0);
+          P[j + 1] = (float)(-c1);
+        }
+      };
       mm_nn<NX, NX>(Dd, Sm, X);
-#pragma unroll
-      for (int j = 0; j < NX; ++j) {
-        double s = 0.0;
-#pragma unroll
-        for (int m = 0; m < NX; ++m) s = __builtin_fma(X[m], ex_m[slot][m][j], s);
-        Pm[j] = (float)(-s);
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      times_neighbour(slot, Pm);
       mm_nn<NX, NX>(Dd, Sp, X);
-#pragma unroll
-      for (int j = 0; j < NX; ++j) {
-        double s = 0.0;
-#pragma unroll
-        for (int m = 0; m < NX; ++m) s = __builtin_fma(X[m], ex_m[slot + 2][m][j], s);
-        Pp[j] = (float)(-s);
-        __builtin_amdgcn_sched_barrier(0);
-      }
+      times_neighbour(slot + 2, Pp);
 #pragma unroll
       for (int j = 0; j < NX; ++j) Pd[j] = (float)Dd[j];
     }
