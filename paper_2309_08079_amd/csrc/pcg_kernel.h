@@ -122,12 +122,31 @@ __device__ __forceinline__ void store_pair_l2(__amdgpu_buffer_rsrc_t rs, uint32_
 __device__ __forceinline__ u32x4 load_pair_l2(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
   return __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kL2Load);
 }
-// 16 bytes of plain data at device scope (the formation and setup exchanges)
-__device__ __forceinline__ void store16_dev(__amdgpu_buffer_rsrc_t rs, uint32_t off, u32x4 d) {
-  __builtin_amdgcn_raw_buffer_store_b128(d, rs, off, 0, kDeviceScope);
+// 8 and 16 bytes of plain data for the formation and setup exchanges (data, a completion
+// wait, then a flag): at device scope, or through the XCD's L2 (plain stores, non-temporal
+// loads) for a gang whose parts all run on one XCD.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void store16_x(__amdgpu_buffer_rsrc_t rs, uint32_t off, u32x4 d, bool l2) {
+  if (l2)
+    __builtin_amdgcn_raw_buffer_store_b128(d, rs, off, 0, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b128(d, rs, off, 0, kDeviceScope);
 }
-__device__ __forceinline__ u32x4 load16_dev(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
-  return __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kDeviceScope);
+__device__ __forceinline__ u32x4 load16_x(__amdgpu_buffer_rsrc_t rs, uint32_t off, bool l2) {
+  return l2 ? __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kL2Load)
+            : __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, kDeviceScope);
+}
+__device__ __forceinline__ void store8_x(__amdgpu_buffer_rsrc_t rs, uint32_t off, uint64_t v, bool l2) {
+  const u32x2 d = {(uint32_t)v, (uint32_t)(v >> 32)};
+  if (l2)
+    __builtin_amdgcn_raw_buffer_store_b64(d, rs, off, 0, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(d, rs, off, 0, kDeviceScope);
+}
+__device__ __forceinline__ uint64_t load8_x(__amdgpu_buffer_rsrc_t rs, uint32_t off, bool l2) {
+  const u32x2 d = l2 ? __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, kL2Load)
+                     : __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, kDeviceScope);
+  return ((uint64_t)d.y << 32) | d.x;
 }
 __device__ __forceinline__ u32x4 pack_d2(double x, double y) {
   const uint64_t u = __builtin_bit_cast(uint64_t, x), v = __builtin_bit_cast(uint64_t, y);
@@ -532,14 +551,14 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
         // test hook: wait for an epoch that no part ever writes, so every wait gives up
         const uint64_t need = a.stall ? ~0ull : epoch;
         if (wave == 0) {
-          if (wl == 0) __hip_atomic_store(&tws[my_t].flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (wl == 0) store8_x(wsr, ws_off(&tws[my_t].flag), epoch, l2x);
           const long long t_start = wall_clock64();
           int ab = 0, polls = 0;
           // only the two neighbours' rows are needed
           const int nb = wl == 0 ? part - 1 : part + 1;
           const bool want = wl < 2 && nb >= 0 && nb < G;
           while (true) {
-            const bool seen = !want || __hip_atomic_load(&tws[pd.t0 + nb].flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need;
+            const bool seen = !want || load8_x(wsr, ws_off(&tws[pd.t0 + (want ? nb : 0)].flag), l2x) >= need;
             if (__ballot(seen) == ~0ull) break;
             if ((ab = poll_spin(polls, t_start))) break;
           }
@@ -555,7 +574,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
             const uint32_t o = ws_off(&src->hm[srcside][l][0]);
             u32x4 q[kGroup / 2];
 #pragma unroll
-            for (int k = 0; k < kGroup / 2; ++k) q[k] = has ? load16_dev(wsr, o + 16 * k) : u32x4{0u, 0u, 0u, 0u};
+            for (int k = 0; k < kGroup / 2; ++k) q[k] = has ? load16_x(wsr, o + 16 * k, l2x) : u32x4{0u, 0u, 0u, 0u};
 #pragma unroll
             for (int k = 0; k < kGroup / 2; ++k) *reinterpret_cast<u32x4 *>(&ex_m[dst][l][2 * k]) = q[k];
           }
@@ -583,13 +602,13 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       }
       const uint64_t epoch = (gen << 32) | 2u;
       if (wave == 0) {
-        if (wl == 0) __hip_atomic_store(&tws[my_t].flag, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (wl == 0) store8_x(wsr, ws_off(&tws[my_t].flag), epoch, l2x);
         const long long t_start = wall_clock64();
         int ab = 0, polls = 0;
         const int nb = wl == 0 ? part - 1 : part + 1;
         const bool want = wl < 2 && nb >= 0 && nb < G;
         while (true) {
-          const bool seen = !want || __hip_atomic_load(&tws[pd.t0 + nb].flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epoch;
+          const bool seen = !want || load8_x(wsr, ws_off(&tws[pd.t0 + (want ? nb : 0)].flag), l2x) >= epoch;
           if (__ballot(seen) == ~0ull) break;
           if ((ab = poll_spin(polls, t_start))) break;
         }
@@ -608,7 +627,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
             const int nbh = side == 0 ? part - 1 : part + 1;
             const bool has = t < 2 * kW && nbh >= 0 && nbh < G;
             const TaskWS<NX> *src = &tws[has ? my_t + (side == 0 ? -1 : 1) : my_t];
-            q[i] = has ? load16_dev(wsr, ws_off(&src->hp[side == 0 ? 1 : 0][0][0]) + 16 * (t - side * kW))
+            q[i] = has ? load16_x(wsr, ws_off(&src->hp[side == 0 ? 1 : 0][0][0]) + 16 * (t - side * kW), l2x)
                        : u32x4{0u, 0u, 0u, 0u};
           }
           double hv[2] = {0.0, 0.0};
@@ -619,7 +638,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
             const TaskWS<NX> *src = &tws[has ? my_t + (side == 0 ? -1 : 1) : my_t];
 #pragma unroll
             for (int c = 0; c < 2; ++c)
-              hv[c] = has ? __hip_atomic_load(&src->hs[side == 0 ? 1 : 0][c][l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+              hv[c] = has ? __builtin_bit_cast(double, load8_x(wsr, ws_off(&src->hs[side == 0 ? 1 : 0][c][l]), l2x)) : 0.0;
           }
 #pragma unroll
           for (int i = 0; i < kPer; ++i) {
@@ -810,7 +829,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
     if (multi && rowv && (slot == 0 || slot == KPW - 1)) {
       const uint32_t o = ws_off(&tws[my_t].hm[slot == 0 ? 0 : 1][lane][0]);
 #pragma unroll
-      for (int k = 0; k < NX / 2; ++k) store16_dev(wsr, o + 16 * k, pack_d2(Dd[2 * k], Dd[2 * k + 1]));
+      for (int k = 0; k < NX / 2; ++k) store16_x(wsr, o + 16 * k, pack_d2(Dd[2 * k], Dd[2 * k + 1]), l2x);
     }
     sync_form();
     // (7) Phi^-1_{b,b-1} = -D_b^-1 S_{b,b-1} D_{b-1}^-1, Phi^-1_{b,b+1} likewise.  X = D_b^-1
@@ -948,12 +967,12 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
             const uint32_t o = ws_off(&w.hp[side][lane][0]);
 #pragma unroll
             for (int k = 0; k < kPRow / 4; ++k)
-              store16_dev(wsr, o + 16 * k, pack_f4(row[4 * k], row[4 * k + 1], row[4 * k + 2], row[4 * k + 3]));
+              store16_x(wsr, o + 16 * k, pack_f4(row[4 * k], row[4 * k + 1], row[4 * k + 2], row[4 * k + 3]), l2x);
           }
-          __hip_atomic_store(&w.hs[side][0][lane], rhs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (warm) __hip_atomic_store(&w.hs[side][1][lane], lam, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          store8_x(wsr, ws_off(&w.hs[side][0][lane]), __builtin_bit_cast(uint64_t, rhs), l2x);
+          if (warm) store8_x(wsr, ws_off(&w.hs[side][1][lane]), __builtin_bit_cast(uint64_t, lam), l2x);
         } else if (!warm) {
-          __hip_atomic_store(&w.hs[side][1][lane], rhs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          store8_x(wsr, ws_off(&w.hs[side][1][lane]), __builtin_bit_cast(uint64_t, rhs), l2x);
         }
       }
       ex_d[0][slot + 1][lane] = rhs;
