@@ -155,6 +155,32 @@ int mpcpcg_backward(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
                     float *dB, float *dq, float *dr, float *dx0, float *de, float *dgamma,
                     mpcpcg_stats *stats, hipStream_t stream);
 
+/* Forward solve that keeps its preconditioner for the adjoint, and the adjoint that reads
+ * it.  The adjoint system S mu = y has the forward's matrix (S is symmetric, Section III-B)
+ * and therefore its preconditioner Phi^-1 (Section IV-A).
+ * mpcpcg_solve_batched_keep is mpcpcg_solve_batched with PCG (Algorithm 1), whatever the
+ * context's method, that also writes Phi^-1 of every knot (FP32) to the record `factors`.
+ * mpcpcg_backward_reuse is mpcpcg_backward with PCG that forms S as usual but reads
+ * Phi^-1 from the record instead of inverting the diagonal blocks of S, exchanging them
+ * between workgroups and forming the off-diagonal blocks again; its results equal
+ * mpcpcg_backward's bit for bit.  `factors` is a device buffer owned by the caller,
+ * 256-byte aligned, of mpcpcg_factor_bytes(ctx, knot_off[batch]) bytes (2,688 per knot);
+ * the caller keeps it and the packed problem unchanged between the two calls (the record
+ * is not checked against the problem).  Both calls return EINVAL on an (28, 14) context,
+ * for a NULL or misaligned record, and for the argument errors of the plain calls.
+ * mpcpcg_factor_bytes returns -1 for a NULL or (28, 14) context or total_knots < 1. */
+int64_t mpcpcg_factor_bytes(const mpcpcg_ctx *ctx, int64_t total_knots);
+int mpcpcg_solve_batched_keep(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
+                              const mpcpcg_problem *packed, const mpcpcg_opts *opts, float *lambda,
+                              float *dx, float *du, mpcpcg_stats *stats, void *factors,
+                              hipStream_t stream);
+int mpcpcg_backward_reuse(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
+                          const mpcpcg_problem *packed, const mpcpcg_opts *opts, const float *lambda,
+                          const float *dx, const float *du, const float *dL_dlambda,
+                          const float *dL_ddx, const float *dL_ddu, float *dQ, float *dR, float *dA,
+                          float *dB, float *dq, float *dr, float *dx0, float *de, float *dgamma,
+                          mpcpcg_stats *stats, const void *factors, hipStream_t stream);
+
 /* Schedule control for the batched calls.
  * mpcpcg_set_knots_per_group fixes the knots handled by one workgroup (one of 4, 8, 16,
  * 24, 32, 48; 0 restores the automatic choice).  mpcpcg_autotune times every

@@ -73,13 +73,13 @@ struct Schedule {
   Task *d_xtasks = nullptr;
   int32_t *d_xoff = nullptr;
   int xgrid = 0;
-  hipGraph_t graph[3][2] = {};
-  hipGraphExec_t exec[3][2] = {};
-  hipGraphNode_t node[3][2] = {};
-  KArgs args[3][2];
-  int grid[3] = {0, 0, 0};
+  hipGraph_t graph[4][2] = {};
+  hipGraphExec_t exec[4][2] = {};
+  hipGraphNode_t node[4][2] = {};
+  KArgs args[4][2];
+  int grid[4] = {0, 0, 0, 0};
   ~Schedule() {
-    for (int m = 0; m < 3; ++m)
+    for (int m = 0; m < 4; ++m)
       for (int x = 0; x < 2; ++x) {
         if (exec[m][x]) (void)hipGraphExecDestroy(exec[m][x]);
         if (graph[m][x]) (void)hipGraphDestroy(graph[m][x]);
@@ -256,11 +256,16 @@ void make_room(mpcpcg_ctx *c, Cache &cache, bool drop_graphs) {
   }
 }
 
+// launch mode of the adjoint that reads the forward's factor record (phase 3 of the
+// adjoint kernel) beside mpc::kForm / kForward / kAdjoint
+constexpr int kAdjointKept = 3;
+
 template <int KPW>
 KernelFn kernel_for(int mode) {
   switch (mode) {
     case mpc::kForm: return mpc::pcg_kernel<kNX, kNU, KPW, mpc::kForm>;
     case mpc::kForward: return mpc::pcg_kernel<kNX, kNU, KPW, mpc::kForward>;
+    case kAdjointKept: return mpc::pcg_kernel<kNX, kNU, KPW, mpc::kAdjoint, 3>;
     default: return mpc::pcg_kernel<kNX, kNU, KPW, mpc::kAdjoint>;
   }
 }
@@ -425,10 +430,12 @@ int get_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, int kpw, Schedu
   int cap = 0;
   int st = capacity(c, kpw, mpc::kForward, &cap);
   if (st) return st;
-  int capb = 0;
-  st = capacity(c, kpw, mpc::kAdjoint, &capb);
-  if (st) return st;
-  cap = std::min(cap, capb);
+  for (int m : {(int)mpc::kAdjoint, kAdjointKept}) {
+    int capb = 0;
+    st = capacity(c, kpw, m, &capb);
+    if (st) return st;
+    cap = std::min(cap, capb);
+  }
   for (const auto &d : probs)
     if (d.nparts > cap)
       return fail(c, MPCPCG_EINVAL, "a horizon of %d knots needs %d co-resident workgroups; the device holds %d", d.N, d.nparts, cap);
@@ -444,7 +451,7 @@ int get_schedule(mpcpcg_ctx *c, const std::vector<int64_t> &off, int kpw, Schedu
     (void)hipGetLastError();
     return fail(c, MPCPCG_ENOMEM, "cannot allocate the schedule of a %d-problem batch", B);
   }
-  for (int m = 0; m < 3; ++m) s->grid[m] = std::min(s->ntasks, cap);
+  for (int m = 0; m < 4; ++m) s->grid[m] = std::min(s->ntasks, cap);
   // Per-XCD lists: workgroups are dispatched to the eight XCDs in turn, so a grid of 8 m
   // workgroups puts m on each (at most cap / 8 of them resident).  When every gang fits in
   // cap / 8, each problem (in longest-first order) goes to the XCD with the least work so
@@ -1231,6 +1238,72 @@ int mpcpcg_backward(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const mpcp
   a.dgamma = dgamma; a.stats = stats;
   if (fac) return run_factor(c, a, mpc::kAdjoint, sc, 0, s);
   return launch_batched(c, sc, a, mpc::kAdjoint, tu.pin, s);
+}
+
+// Factor record of a forward solve, read back by its adjoint: Phi^-1 (FP32) of K knots by
+// columns in the factorisation workspace's layout.
+int64_t fac_bytes(int64_t K) { return K * 3 * kNX * mpc::kGroup * (int64_t)sizeof(float); }
+
+int check_record(mpcpcg_ctx *c, const void *rec) {
+  if (c->wide) return fail(c, MPCPCG_EINVAL, "factor records are kept on the (14, 7) path only");
+  if (!rec) return fail(c, MPCPCG_EINVAL, "factors is NULL");
+  if (reinterpret_cast<uintptr_t>(rec) % 256) return fail(c, MPCPCG_EINVAL, "factors must be 256-byte aligned");
+  return MPCPCG_OK;
+}
+
+int64_t mpcpcg_factor_bytes(const mpcpcg_ctx *c, int64_t total_knots) {
+  if (!c || c->wide || total_knots < 1) return -1;
+  return fac_bytes(total_knots);
+}
+
+int mpcpcg_solve_batched_keep(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const mpcpcg_problem *p,
+                              const mpcpcg_opts *o, float *lambda, float *dx, float *du,
+                              mpcpcg_stats *stats, void *factors, hipStream_t s) {
+  if (!c) return MPCPCG_EINVAL;
+  int st = validate_batch(c, batch, off, p);
+  if (st) return st;
+  if ((st = check_opts(c, o))) return st;
+  if (!lambda || !dx || !stats || (off[batch] > batch && !du))
+    return fail(c, MPCPCG_EINVAL, "lambda, dx, du and stats must be non-NULL");
+  if ((st = check_record(c, factors))) return st;
+  std::vector<int64_t> key(off, off + batch + 1);
+  const Tuned tu = pick(c, key);
+  Schedule *sc = nullptr;
+  if ((st = get_schedule(c, key, tu.kpw, &sc))) return st;
+  KArgs a = base_args(c, p, o);
+  a.lam = lambda; a.dx = dx; a.du = du; a.stats = stats;
+  a.fac_p = static_cast<float *>(factors);
+  a.fac_mode = 1;
+  return launch_batched(c, sc, a, mpc::kForward, tu.pin, s);
+}
+
+int mpcpcg_backward_reuse(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const mpcpcg_problem *p,
+                          const mpcpcg_opts *o, const float *lambda, const float *dx, const float *du,
+                          const float *gl, const float *gx, const float *gu, float *dQ, float *dR,
+                          float *dA, float *dB, float *dq, float *dr, float *dx0, float *de,
+                          float *dgamma, mpcpcg_stats *stats, const void *factors, hipStream_t s) {
+  if (!c) return MPCPCG_EINVAL;
+  int st = validate_batch(c, batch, off, p);
+  if (st) return st;
+  if ((st = check_opts(c, o))) return st;
+  const bool ctrl = off[batch] > batch;
+  if (!lambda || !dx || !gl || !dQ || !dq || !dx0 || !stats)
+    return fail(c, MPCPCG_EINVAL, "lambda, dx, dL_dlambda, dQ, dq, dx0 and stats must be non-NULL");
+  if (ctrl && (!du || !dR || !dA || !dB || !dr))
+    return fail(c, MPCPCG_EINVAL, "du, dR, dA, dB and dr must be non-NULL when a horizon exceeds one knot");
+  if ((st = check_record(c, factors))) return st;
+  std::vector<int64_t> key(off, off + batch + 1);
+  const Tuned tu = pick(c, key);
+  Schedule *sc = nullptr;
+  if ((st = get_schedule(c, key, tu.kpw, &sc))) return st;
+  KArgs a = base_args(c, p, o);
+  a.warm = 0;
+  a.lam_in = lambda; a.dx_in = dx; a.du_in = du;
+  a.gl = gl; a.gx = gx; a.gu = gu;
+  a.dQ = dQ; a.dR = dR; a.dA = dA; a.dB = dB; a.dq = dq; a.dr = dr; a.dx0 = dx0; a.de = de;
+  a.dgamma = dgamma; a.stats = stats;
+  a.fac_p = static_cast<float *>(const_cast<void *>(factors));
+  return launch_batched(c, sc, a, kAdjointKept, tu.pin, s);
 }
 
 int mpcpcg_set_knots_per_group(mpcpcg_ctx *c, int32_t k) {

@@ -198,6 +198,12 @@ struct KArgs {
   // factorisation path: S rows [knots][NX][3 NX] and rhs [knots][NX] written by phase 1,
   // lambda [knots][NX] read by phase 2
   double *s_ws, *rhs_ws, *lam_ws;  // factorisation workspace (layout: fws_index)
+  // factor record of a forward solve (written when fac_mode = 1): Phi^-1 (FP32) by columns
+  // (layout: fws_index), read back by its adjoint (PHASE 3) instead of inverting S_bb,
+  // exchanging D^-1 between parts and forming the off-diagonal blocks again
+  float *fac_p;
+  int32_t fac_mode;
+  int32_t pad_fac;
   // options
   float eps;
   int32_t max_iter;
@@ -240,7 +246,7 @@ constexpr int waves_per_eu() { return KPW == 32 ? 2 : 3; }
 // The formation-only and epilogue-only kernels of the factorisation path hold no PCG state:
 // two waves per SIMD give them the registers of the formation without spills.
 template <int KPW, int PHASE>
-constexpr int phase_waves_per_eu() { return PHASE ? 2 : waves_per_eu<KPW>(); }
+constexpr int phase_waves_per_eu() { return (PHASE == 1 || PHASE == 2) ? 2 : waves_per_eu<KPW>(); }
 // Rows of a control block as stored by columns (NU = 7 rows padded to 8: half a line).
 constexpr int kURows = 8;
 
@@ -252,9 +258,11 @@ __device__ __forceinline__ int64_t fws_index(int64_t k, int t, int c, int r) {
   return ((k * 3 + t) * NX + c) * kGroup + r;
 }
 
-// PHASE 0: formation, PCG and epilogue fused.  PHASE 1 (factorisation path): formation only,
-// S rows and the right-hand side written to s_ws / rhs_ws.  PHASE 2: formation, lambda
-// read from lam_ws (the block-tridiagonal solve), then the epilogue.
+// PHASE 0: formation, PCG and epilogue fused (a forward solve with fac_mode 1 also writes
+// its factor record).  PHASE 1 (factorisation path): formation only, S rows and the
+// right-hand side written to s_ws / rhs_ws.  PHASE 2: formation, lambda read from lam_ws
+// (the block-tridiagonal solve), then the epilogue.  PHASE 3 (adjoint): S formed as in
+// PHASE 0, Phi^-1 read from the forward's factor record, then PCG and epilogue.
 template <int NX, int NU, int KPW, int MODE, int PHASE = 0>
 __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_eu(phase_waves_per_eu<KPW, PHASE>(), phase_waves_per_eu<KPW, PHASE>())))
     pcg_kernel(const KArgs a) {
@@ -698,6 +706,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
     const float *qv = (MODE == kAdjoint) ? a.gx : a.q;
     const float *rv = (MODE == kAdjoint) ? a.gu : a.r;
     double Dd[NX];
+    float Pm[NX], Pd[NX], Pp[NX];
     if constexpr (PHASE == 2) {
       // the epilogue needs only S_{b,b+1} (the rest of its inputs are in the workspace)
       const double *sp = a.s_ws + fws_index<NX>(act ? kb : 0, 2, 0, lane);
@@ -817,7 +826,6 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       gj_inverse<NX>(Dd, lane);
     }
     }  // PHASE != 2 (formation)
-    float Pm[NX], Pd[NX], Pp[NX];
     if constexpr (PHASE == 0) {
     // (6) exchange D^-1 rows with the neighbouring knots (the one cross-knot dependency of
     //     the formation; section IV-A, Symmetric Stair preconditioner: of the whole
@@ -857,11 +865,43 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
 #pragma unroll
       for (int j = 0; j < NX; ++j) Pd[j] = (float)Dd[j];
     }
-    }  // PHASE == 0
+    } else if constexpr (PHASE == 3) {
+      // (5)-(7) replaced: Phi^-1 as the forward formed it (knot slots past the horizon: the
+      // blocks the formation gives them, D_b^-1 = I and zero off-diagonal blocks)
+      if (act) {
+        const float *fp = a.fac_p + fws_index<NX>(kb, 0, 0, lane);
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+          Pm[j] = __builtin_nontemporal_load(fp + j * kGroup);
+          Pd[j] = __builtin_nontemporal_load(fp + (NX + j) * kGroup);
+          Pp[j] = __builtin_nontemporal_load(fp + (2 * NX + j) * kGroup);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+          Pm[j] = 0.0f;
+          Pd[j] = (j == lane) ? 1.0f : 0.0f;
+          Pp[j] = 0.0f;
+        }
+      }
+    }  // PHASE 0 forms Phi^-1, PHASE 3 reads it
     if (!rowv) {
 #pragma unroll
       for (int j = 0; j < NX; ++j) { Sm[j] = 0.0; Sd[j] = 0.0; Sp[j] = 0.0; Pm[j] = 0.f; Pd[j] = 0.f; Pp[j] = 0.f; }
       rhs = 0.0;
+    }
+    if constexpr (MODE == kForward && PHASE == 0) {
+      if (a.fac_mode == 1 && act) {
+        // the factor record (Phi^-1): all 16 lanes store (rows >= NX hold zeros), whole
+        // lines, streamed past the caches (the adjoint reads it once)
+        float *fp = a.fac_p + fws_index<NX>(kb, 0, 0, lane);
+#pragma unroll
+        for (int j = 0; j < NX; ++j) {
+          __builtin_nontemporal_store(Pm[j], fp + j * kGroup);
+          __builtin_nontemporal_store(Pd[j], fp + (NX + j) * kGroup);
+          __builtin_nontemporal_store(Pp[j], fp + (2 * NX + j) * kGroup);
+        }
+      }
     }
     if constexpr (PHASE == 1) {
       if (act) {
@@ -1210,7 +1250,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
           a.dr[(cb - 1) * NU + lane] = (float)n1u;
         }
       }
-      if (PHASE == 0 && tid == 0 && part == 0)
+      if ((PHASE == 0 || PHASE == 3) && tid == 0 && part == 0)
         put_stats(a.stats + pd.id, it, status,
                   eta_ref > 0.0 ? (float)__builtin_sqrt(eta_new > 0.0 ? eta_new / eta_ref : 0.0) : 0.0f);
     }

@@ -95,6 +95,10 @@ def load_library(path: str = None):
     lib.mpcpcg_solve_noalloc.argtypes = [P, O, vp, vp, vp, vp, vp]
     lib.mpcpcg_noalloc_last_error.argtypes = []
     lib.mpcpcg_noalloc_last_error.restype = C.c_char_p
+    lib.mpcpcg_factor_bytes.argtypes = [vp, C.c_int64]
+    lib.mpcpcg_factor_bytes.restype = C.c_int64
+    lib.mpcpcg_solve_batched_keep.argtypes = [vp, i32, i64p, P, O, vp, vp, vp, vp, vp, vp]
+    lib.mpcpcg_backward_reuse.argtypes = [vp, i32, i64p, P, O] + [vp] * 6 + [vp] * 9 + [vp, vp, vp]
     M, T = C.POINTER(ChainModel), C.POINTER(Trajectory)
     lib.mpcpcg_linearize.argtypes = [vp, i32, i64p, M, T] + [vp] * 6 + [vp]
     lib.mpcpcg_line_search.argtypes = [vp, i32, i64p, M, T, vp, vp, vp, C.c_float] + [vp] * 4 + [vp]
@@ -104,7 +108,8 @@ def load_library(path: str = None):
               "mpcpcg_set_graph", "mpcpcg_autotune", "mpcpcg_set_method", "mpcpcg_linearize",
               "mpcpcg_line_search", "mpcpcg_control_step", "mpcpcg_tuned_schedule",
               "mpcpcg_set_xcd_pinning", "mpcpcg_set_cache_limit", "mpcpcg_cache_info",
-              "mpcpcg_debug_set_wait", "mpcpcg_solve_noalloc"):
+              "mpcpcg_debug_set_wait", "mpcpcg_solve_noalloc", "mpcpcg_solve_batched_keep",
+              "mpcpcg_backward_reuse"):
         getattr(lib, f).restype = C.c_int
     _libs[path] = lib
     if _lib is None:
@@ -117,6 +122,12 @@ def _ptr(t):
         return None
     if not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
         raise MPCPCGError("expected a contiguous float32 device tensor")
+    return t.data_ptr()
+
+
+def _record(t):
+    if not t.is_cuda or not t.is_contiguous():
+        raise MPCPCGError("the factor record must be a contiguous device tensor")
     return t.data_ptr()
 
 
@@ -171,6 +182,7 @@ class Context:
     def __init__(self, nx=14, nu=7, max_total_knots=1 << 17, max_batch=4096, lib_path=None):
         self.lib = load_library(lib_path)
         self.nx, self.nu = nx, nu
+        self.method = "pcg"
         h = C.c_void_p()
         st = self.lib.mpcpcg_create(C.byref(h), nx, nu, int(max_total_knots), int(max_batch))
         if st != OK:
@@ -224,8 +236,18 @@ class Context:
             "mpcpcg_solve")
         return dict(lam=lam, dx=dx, du=du, stats=stats)
 
+    def mpcpcg_factor_bytes(self, total_knots):
+        n = self.lib.mpcpcg_factor_bytes(self.h, int(total_knots))
+        if n < 0:
+            raise MPCPCGError("mpcpcg_factor_bytes: no factor record on this context")
+        return n
+
+    def factor_record(self, total_knots, device):
+        """A device buffer for the factor record of a batch of total_knots knots."""
+        return torch.empty(self.mpcpcg_factor_bytes(total_knots), dtype=torch.uint8, device=device)
+
     def mpcpcg_solve_batched(self, packed, knot_off, eps=1e-6, max_iter=0, lam0=None, out=None,
-                             stop="relative"):
+                             stop="relative", factors=None):
         off = np.ascontiguousarray(knot_off, dtype=np.int64)
         B = len(off) - 1
         K = int(off[-1])
@@ -237,14 +259,18 @@ class Context:
         dx = o["dx"] if "dx" in o else torch.empty((K, self.nx), device=dev)
         du = o["du"] if "du" in o else torch.empty((max(K - B, 0), self.nu), device=dev)
         stats = o["stats"] if "stats" in o else torch.zeros((B, 4), dtype=torch.int32, device=dev)
-        self._check(self.lib.mpcpcg_solve_batched(
-            self.h, B, off.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(_problem(packed, self.nx, self.nu)),
-            C.byref(_opts(eps, max_iter, lam0 is not None, stop)), _ptr(lam), _ptr(dx),
-            _ptr(du) if du.numel() else None, stats.data_ptr(), _stream()), "mpcpcg_solve_batched")
+        args = (self.h, B, off.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(_problem(packed, self.nx, self.nu)),
+                C.byref(_opts(eps, max_iter, lam0 is not None, stop)), _ptr(lam), _ptr(dx),
+                _ptr(du) if du.numel() else None, stats.data_ptr())
+        if factors is None:
+            self._check(self.lib.mpcpcg_solve_batched(*args, _stream()), "mpcpcg_solve_batched")
+        else:
+            self._check(self.lib.mpcpcg_solve_batched_keep(*args, _record(factors), _stream()),
+                        "mpcpcg_solve_batched_keep")
         return dict(lam=lam, dx=dx, du=du, stats=stats)
 
     def mpcpcg_backward(self, packed, knot_off, fwd, gl, gx=None, gu=None, eps=1e-6, max_iter=0,
-                        out=None, stop="relative"):
+                        out=None, stop="relative", factors=None):
         off = np.ascontiguousarray(knot_off, dtype=np.int64)
         B = len(off) - 1
         K = int(off[-1])
@@ -258,12 +284,16 @@ class Context:
                  dx0=z("dx0", (B, nx)), de=z("de", (M, nx)), dgamma=z("dgamma", (K, nx)))
         stats = o["stats"] if "stats" in o else torch.zeros((B, 4), dtype=torch.int32, device=dev)
         opt = lambda t: _ptr(t) if t is not None and t.numel() else None
-        self._check(self.lib.mpcpcg_backward(
-            self.h, B, off.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(_problem(packed, nx, nu)),
-            C.byref(_opts(eps, max_iter, False, stop)), _ptr(fwd["lam"]), _ptr(fwd["dx"]), opt(fwd["du"]),
-            _ptr(gl), opt(gx), opt(gu),
-            *[opt(g[k]) for k in ("dQ", "dR", "dA", "dB", "dq", "dr", "dx0", "de", "dgamma")],
-            stats.data_ptr(), _stream()), "mpcpcg_backward")
+        args = (self.h, B, off.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(_problem(packed, nx, nu)),
+                C.byref(_opts(eps, max_iter, False, stop)), _ptr(fwd["lam"]), _ptr(fwd["dx"]), opt(fwd["du"]),
+                _ptr(gl), opt(gx), opt(gu),
+                *[opt(g[k]) for k in ("dQ", "dR", "dA", "dB", "dq", "dr", "dx0", "de", "dgamma")],
+                stats.data_ptr())
+        if factors is None:
+            self._check(self.lib.mpcpcg_backward(*args, _stream()), "mpcpcg_backward")
+        else:
+            self._check(self.lib.mpcpcg_backward_reuse(*args, _record(factors), _stream()),
+                        "mpcpcg_backward_reuse")
         g["stats"] = stats
         return g
 
@@ -275,6 +305,7 @@ class Context:
         if method not in METHODS:
             raise MPCPCGError("method must be one of %s, not %r" % (sorted(METHODS), method))
         self._check(self.lib.mpcpcg_set_method(self.h, METHODS[method]), "mpcpcg_set_method")
+        self.method = method
 
     def mpcpcg_set_graph(self, enable):
         self._check(self.lib.mpcpcg_set_graph(self.h, int(bool(enable))), "mpcpcg_set_graph")
@@ -420,6 +451,9 @@ class MPCPCGFunction(torch.autograd.Function):
 
     Forward: mpcpcg_solve_batched.  Backward: mpcpcg_backward (adjoint PCG with the same
     stopping rule); returns gradients for Q, R, A, B, q, r, x0, e (symmetric part for Q, R).
+    On a (14, 7) context with the PCG method the forward keeps its preconditioner Phi^-1
+    (2.7 KB per knot, held until backward) and the backward reads it instead of forming it
+    again.
     Both directions read the solver's stats and raise MPCPCGError if any problem did not
     converge (NOT_CONVERGED, BREAKDOWN or TIMEOUT), so that no unconverged iterate or
     undefined output flows into autograd.
@@ -430,7 +464,10 @@ class MPCPCGFunction(torch.autograd.Function):
         packed = dict(Q=Q.contiguous(), R=R.contiguous(), A=A.contiguous(), B=B.contiguous(),
                       q=q.contiguous(), r=r.contiguous(), x0=x0.contiguous(),
                       e=None if e is None else e.contiguous())
-        out = mctx.mpcpcg_solve_batched(packed, knot_off, eps=eps, max_iter=max_iter)
+        fctx.factors = None
+        if mctx.method == "pcg" and mctx.nx == 14:
+            fctx.factors = mctx.factor_record(int(np.asarray(knot_off)[-1]), q.device)
+        out = mctx.mpcpcg_solve_batched(packed, knot_off, eps=eps, max_iter=max_iter, factors=fctx.factors)
         check_stats(out["stats"], "MPCPCGFunction forward (mpcpcg_solve_batched)")
         fctx.mctx, fctx.off, fctx.eps, fctx.max_iter = mctx, np.asarray(knot_off, dtype=np.int64), eps, max_iter
         fctx.packed = packed
@@ -446,7 +483,8 @@ class MPCPCGFunction(torch.autograd.Function):
         g = fctx.mctx.mpcpcg_backward(fctx.packed, fctx.off, dict(lam=lam, dx=dx, du=du),
                                       zero_like(glam, lam), None if gdx is None else gdx.contiguous(),
                                       None if gdu is None else gdu.contiguous(), eps=fctx.eps,
-                                      max_iter=fctx.max_iter)
+                                      max_iter=fctx.max_iter, factors=fctx.factors)
+        fctx.factors = None
         check_stats(g["stats"], "MPCPCGFunction backward (mpcpcg_backward)")
         return (None, None, None, g["dQ"], g["dR"], g["dA"], g["dB"], g["dq"], g["dr"], g["dx0"],
                 g["de"] if fctx.has_e else None, None)
