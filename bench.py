@@ -30,8 +30,8 @@ SEED0 = 6001
 # Algorithmic work ("Algorithmic work"): FP64/FP32 flops per unit.
 FLOP_PER_KNOT_ITER = 2492      # S p (1176) + Phi^-1 r (1176) + 2 dots (56) + 3 axpys (84)
 FLOP_PER_KNOT_FORM = 39102     # Q^-1, R^-1, theta, theta^-1, two Phi^-1 blocks, gamma
-FLOP_PER_KNOT_FORM_S = 22638   # the same without theta^-1 and the Phi^-1 blocks (16,464), which
-                               # the adjoint reads from the forward's record
+FLOP_PER_KNOT_FORM_S = 16464   # the same without Q^-1, R^-1, theta^-1 and the Phi^-1 blocks
+                               # (22,638), which the adjoint reads from the forward's record
 FLOP_PER_KNOT_RECON = 1078     # dx (two 14x14 matvecs) + du (14x7 + 7x7 matvecs)
 FLOP_PER_KNOT_GRAD = 1960      # dQ, dA (two outer products each), dB, dR
 PEAK_VALU_TFLOPS = 78.6        # FP64 vector FMA issue rate of MI355X (= non-packed FP32)

@@ -159,12 +159,13 @@ int mpcpcg_backward(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
  * it.  The adjoint system S mu = y has the forward's matrix (S is symmetric, Section III-B)
  * and therefore its preconditioner Phi^-1 (Section IV-A).
  * mpcpcg_solve_batched_keep is mpcpcg_solve_batched with PCG (Algorithm 1), whatever the
- * context's method, that also writes Phi^-1 of every knot (FP32) to the record `factors`.
- * mpcpcg_backward_reuse is mpcpcg_backward with PCG that forms S as usual but reads
- * Phi^-1 from the record instead of inverting the diagonal blocks of S, exchanging them
- * between workgroups and forming the off-diagonal blocks again; its results equal
- * mpcpcg_backward's bit for bit.  `factors` is a device buffer owned by the caller,
- * 256-byte aligned, of mpcpcg_factor_bytes(ctx, knot_off[batch]) bytes (2,688 per knot);
+ * context's method, that also writes to the record `factors` Phi^-1 of every knot (FP32)
+ * and the inverses of Q and R it forms (FP64).  mpcpcg_backward_reuse is mpcpcg_backward
+ * with PCG that forms S from those inverses and reads Phi^-1 from the record instead of
+ * inverting Q, R and the diagonal blocks of S, exchanging the latter between workgroups
+ * and forming the off-diagonal blocks again; its results equal mpcpcg_backward's bit for
+ * bit.  `factors` is a device buffer owned by the caller, 256-byte aligned, of
+ * mpcpcg_factor_bytes(ctx, knot_off[batch]) bytes (5,824 per knot);
  * the caller keeps it and the packed problem unchanged between the two calls (the record
  * is not checked against the problem).  Both calls return EINVAL on an (28, 14) context,
  * for a NULL or misaligned record, and for the argument errors of the plain calls.

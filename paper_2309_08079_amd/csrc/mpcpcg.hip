@@ -1240,9 +1240,29 @@ int mpcpcg_backward(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const mpcp
   return launch_batched(c, sc, a, mpc::kAdjoint, tu.pin, s);
 }
 
-// Factor record of a forward solve, read back by its adjoint: Phi^-1 (FP32) of K knots by
-// columns in the factorisation workspace's layout.
-int64_t fac_bytes(int64_t K) { return K * 3 * kNX * mpc::kGroup * (int64_t)sizeof(float); }
+// Factor record of a forward solve, read back by its adjoint, for K knots: Phi^-1 (FP32) by
+// columns in the factorisation workspace's layout, then the epilogue's Q^-1 and
+// (R^-1 | R^-1 B^T) rows in the context workspace's layouts, each region 256-byte aligned.
+struct FacLayout {
+  int64_t p, q, r, total;
+};
+FacLayout fac_layout(int64_t K) {
+  auto al = [](int64_t x) { return (x + 255) / 256 * 256; };
+  FacLayout L;
+  L.p = 0;
+  L.q = L.p + al(K * 3 * kNX * mpc::kGroup * (int64_t)sizeof(float));
+  L.r = L.q + al(K * kNX * mpc::kGroup * (int64_t)sizeof(double));
+  L.total = L.r + al(K * (kNU + kNX) * mpc::kURows * (int64_t)sizeof(double));
+  return L;
+}
+
+void set_record(KArgs &a, const void *rec, int64_t K) {
+  const FacLayout L = fac_layout(K);
+  char *b = static_cast<char *>(const_cast<void *>(rec));
+  a.fac_p = reinterpret_cast<float *>(b + L.p);
+  a.qinv_ws = reinterpret_cast<double *>(b + L.q);
+  a.rinv_ws = reinterpret_cast<double *>(b + L.r);
+}
 
 int check_record(mpcpcg_ctx *c, const void *rec) {
   if (c->wide) return fail(c, MPCPCG_EINVAL, "factor records are kept on the (14, 7) path only");
@@ -1253,7 +1273,7 @@ int check_record(mpcpcg_ctx *c, const void *rec) {
 
 int64_t mpcpcg_factor_bytes(const mpcpcg_ctx *c, int64_t total_knots) {
   if (!c || c->wide || total_knots < 1) return -1;
-  return fac_bytes(total_knots);
+  return fac_layout(total_knots).total;
 }
 
 int mpcpcg_solve_batched_keep(mpcpcg_ctx *c, int32_t batch, const int64_t *off, const mpcpcg_problem *p,
@@ -1272,7 +1292,7 @@ int mpcpcg_solve_batched_keep(mpcpcg_ctx *c, int32_t batch, const int64_t *off, 
   if ((st = get_schedule(c, key, tu.kpw, &sc))) return st;
   KArgs a = base_args(c, p, o);
   a.lam = lambda; a.dx = dx; a.du = du; a.stats = stats;
-  a.fac_p = static_cast<float *>(factors);
+  set_record(a, factors, off[batch]);
   a.fac_mode = 1;
   return launch_batched(c, sc, a, mpc::kForward, tu.pin, s);
 }
@@ -1302,7 +1322,7 @@ int mpcpcg_backward_reuse(mpcpcg_ctx *c, int32_t batch, const int64_t *off, cons
   a.gl = gl; a.gx = gx; a.gu = gu;
   a.dQ = dQ; a.dR = dR; a.dA = dA; a.dB = dB; a.dq = dq; a.dr = dr; a.dx0 = dx0; a.de = de;
   a.dgamma = dgamma; a.stats = stats;
-  a.fac_p = static_cast<float *>(const_cast<void *>(factors));
+  set_record(a, factors, off[batch]);
   return launch_batched(c, sc, a, kAdjointKept, tu.pin, s);
 }
 

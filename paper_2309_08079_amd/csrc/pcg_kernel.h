@@ -200,7 +200,9 @@ struct KArgs {
   double *s_ws, *rhs_ws, *lam_ws;  // factorisation workspace (layout: fws_index)
   // factor record of a forward solve (written when fac_mode = 1): Phi^-1 (FP32) by columns
   // (layout: fws_index), read back by its adjoint (PHASE 3) instead of inverting S_bb,
-  // exchanging D^-1 between parts and forming the off-diagonal blocks again
+  // exchanging D^-1 between parts and forming the off-diagonal blocks again; qinv_ws and
+  // rinv_ws then point into the same record, and the adjoint reads Q^-1 and R^-1 there
+  // instead of inverting Q and R
   float *fac_p;
   int32_t fac_mode;
   int32_t pad_fac;
@@ -262,7 +264,8 @@ __device__ __forceinline__ int64_t fws_index(int64_t k, int t, int c, int r) {
 // its factor record).  PHASE 1 (factorisation path): formation only, S rows and the
 // right-hand side written to s_ws / rhs_ws.  PHASE 2: formation, lambda read from lam_ws
 // (the block-tridiagonal solve), then the epilogue.  PHASE 3 (adjoint): S formed as in
-// PHASE 0, Phi^-1 read from the forward's factor record, then PCG and epilogue.
+// PHASE 0 from the inverses of Q and R read from the forward's factor record, Phi^-1 read
+// from it as well, then PCG and epilogue.
 template <int NX, int NU, int KPW, int MODE, int PHASE = 0>
 __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_eu(phase_waves_per_eu<KPW, PHASE>(), phase_waves_per_eu<KPW, PHASE>())))
     pcg_kernel(const KArgs a) {
@@ -729,7 +732,16 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
 #pragma unroll
         for (int j = 0; j < NX; ++j) Qm[j] = (j == lane) ? 1.0 : 0.0;
       }
-      gj_inverse<NX>(Qm, lane);
+      if constexpr (PHASE == 3) {
+        // Q_{b-1}^-1 as knot b-1 inverted it in the forward (the same inputs and steps)
+        if (hasPrev) {
+          const double *w = a.qinv_ws + (kb - 1) * NX * kGroup + lane;
+#pragma unroll
+          for (int j = 0; j < NX; ++j) Qm[j] = w[j * kGroup];
+        }
+      } else {
+        gj_inverse<NX>(Qm, lane);
+      }
       mm_nn<NX, NX>(Ar, Qm, T);
 #pragma unroll
       for (int j = 0; j < NX; ++j) Sm[j] = -T[j];
@@ -757,15 +769,24 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
 #pragma unroll
         for (int j = 0; j < NU; ++j) Br[j] = (double)pb[j];
       }
-      gj_inverse<NU>(Rr, lane);
-      // W first, stored at once, so that it is not live beside U and theta's update
-      mm_nt<NU, NX>(Rr, Br, W);
-      if (MODE != kForm && hasPrev && lane < kURows) {  // lane NU stores the zero pad row
-        double *w = a.rinv_ws + (cb - 1) * (NU + NX) * kURows + lane;
+      if constexpr (PHASE == 3) {
+        // R_{b-1}^-1 (and R^-1 B^T for the epilogue) as the forward formed them
+        if (hasPrev && lane < kURows) {
+          const double *w = a.rinv_ws + (cb - 1) * (NU + NX) * kURows + lane;
 #pragma unroll
-        for (int j = 0; j < NU; ++j) w[j * kURows] = Rr[j];
+          for (int j = 0; j < NU; ++j) Rr[j] = w[j * kURows];
+        }
+      } else {
+        gj_inverse<NU>(Rr, lane);
+        // W first, stored at once, so that it is not live beside U and theta's update
+        mm_nt<NU, NX>(Rr, Br, W);
+        if (MODE != kForm && hasPrev && lane < kURows) {  // lane NU stores the zero pad row
+          double *w = a.rinv_ws + (cb - 1) * (NU + NX) * kURows + lane;
 #pragma unroll
-        for (int j = 0; j < NX; ++j) w[(NU + j) * kURows] = W[j];
+          for (int j = 0; j < NU; ++j) w[j * kURows] = Rr[j];
+#pragma unroll
+          for (int j = 0; j < NX; ++j) w[(NU + j) * kURows] = W[j];
+        }
       }
       mm_nn<NU, NU>(Br, Rr, U);
       mm_nt<NU, NX>(U, Br, th2);
@@ -788,11 +809,19 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
 #pragma unroll
         for (int j = 0; j < NX; ++j) Qi[j] = (j == lane) ? 1.0 : 0.0;
       }
-      gj_inverse<NX>(Qi, lane);
-      if (MODE != kForm && act) {  // all 16 lanes: rows >= NX are zero, columns are whole lines
-        double *w = a.qinv_ws + kb * NX * kGroup + lane;
+      if constexpr (PHASE == 3) {
+        if (act) {  // Q_b^-1 as the forward formed it
+          const double *w = a.qinv_ws + kb * NX * kGroup + lane;
 #pragma unroll
-        for (int j = 0; j < NX; ++j) w[j * kGroup] = Qi[j];
+          for (int j = 0; j < NX; ++j) Qi[j] = w[j * kGroup];
+        }
+      } else {
+        gj_inverse<NX>(Qi, lane);
+        if (MODE != kForm && act) {  // all 16 lanes: rows >= NX are zero, columns are whole lines
+          double *w = a.qinv_ws + kb * NX * kGroup + lane;
+#pragma unroll
+          for (int j = 0; j < NX; ++j) w[j * kGroup] = Qi[j];
+        }
       }
 #pragma unroll
       for (int j = 0; j < NX; ++j) Sd[j] += Qi[j];

@@ -452,8 +452,8 @@ class MPCPCGFunction(torch.autograd.Function):
     Forward: mpcpcg_solve_batched.  Backward: mpcpcg_backward (adjoint PCG with the same
     stopping rule); returns gradients for Q, R, A, B, q, r, x0, e (symmetric part for Q, R).
     On a (14, 7) context with the PCG method the forward keeps its preconditioner Phi^-1
-    (2.7 KB per knot, held until backward) and the backward reads it instead of forming it
-    again.
+    and the inverses of Q and R (5.8 KB per knot, held until backward), and the backward
+    reads them instead of forming them again.
     Both directions read the solver's stats and raise MPCPCGError if any problem did not
     converge (NOT_CONVERGED, BREAKDOWN or TIMEOUT), so that no unconverged iterate or
     undefined output flows into autograd.
