@@ -295,12 +295,28 @@ bool valid_kpw(int k) {
   return false;
 }
 
+// Workgroups of the fused kernel counted as resident on one compute unit at once.  The
+// occupancy query counts registers per compute unit, but a workgroup's waves go to the four
+// SIMDs in turn, so one of W waves takes ceil(W / 4) wave slots on some SIMD; at
+// waves_per_eu slots per SIMD that allows waves_per_eu / ceil(W / 4) workgroups.  For 24
+// knots (6 waves at three per SIMD) this gives one where the query reports two, and the
+// measurements agree with one: the batched 24-knot launch on 256 x N = 512 runs 2.3x
+// slower than the 16-knot one at the same knots per compute unit by the query, and a single
+// solve of 43 parts of 24 knots placed on one XCD (32 compute units) timed out waiting for
+// parts that never started.
+int resident_per_cu(int occupancy, int kpw) {
+  const int waves = kpw * mpc::kGroup / 64;
+  const int per_simd = kpw == 32 ? 2 : 3;  // the kernel's waves per SIMD (waves_per_eu)
+  const int by_simd = waves <= 4 ? per_simd * (4 / waves) : per_simd / ((waves + 3) / 4);
+  return std::min(occupancy, by_simd);
+}
+
 // resident workgroups of this kernel on the whole device
 int capacity(mpcpcg_ctx *c, int kpw, int mode, int *out) {
   int nb = 0;
   HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(
                 &nb, reinterpret_cast<const void *>(kernel_for(kpw, mode)), kpw * mpc::kGroup, 0));
-  *out = nb * c->cus;
+  *out = resident_per_cu(nb, kpw) * c->cus;
   return MPCPCG_OK;
 }
 
@@ -1025,7 +1041,7 @@ void na_setup(NaDevice &d, int dev) {
       d.rc = na_fail(MPCPCG_EHIP, "occupancy query failed on device %d", dev);
       return;
     }
-    d.cap[i] = nb * prop.multiProcessorCount;
+    d.cap[i] = resident_per_cu(nb, k) * prop.multiProcessorCount;
   }
 }
 

@@ -135,6 +135,22 @@ def test_placements_agree_bit_for_bit(ctx, Ns):
     check_against_oracle(outs[0], packed, off)
 
 
+def test_single_solve_of_more_parts_than_an_xcd_holds(ctx):
+    # 24-knot workgroups (six waves) are resident one per compute unit, so a 43-part single
+    # solve (N = 1024) does not fit one XCD's 32 compute units and must spread over the
+    # device; it converges and matches the oracle (seed 2000 + N)
+    N = 1024
+    p = synth.problem(N, seed=2000 + N)
+    ctx.mpcpcg_set_knots_per_group(24)
+    try:
+        out = ctx.mpcpcg_solve(dev(p), eps=EPS)
+        torch.cuda.synchronize()
+    finally:
+        ctx.mpcpcg_set_knots_per_group(0)
+    packed, off = synth.pack([p])
+    check_against_oracle(out, packed, off)
+
+
 @pytest.mark.parametrize("N", [40, 100, 512])
 def test_single_solve_on_one_xcd_agrees_with_spread_gang(ctx, N):
     # a single solve whose gang runs on one XCD exchanges its loop barriers through that
