@@ -31,6 +31,20 @@ using mpc::Task;
 constexpr int kNX = 14, kNU = 7;        // register-resident fused path
 constexpr int kWNX = 28, kWNU = 14;     // generic (workspace-staged) path
 constexpr int kKpwChoices[] = {4, 8, 16, 24, 32, 48};
+
+// Knots per workgroup of a single solve on a context with default settings: one workgroup
+// when the horizon fits (no gang barrier; the smallest such shape has the cheapest workgroup
+// barriers), else the smallest of 16, 32 and 48 whose gang has at most 32 parts (one XCD,
+// one poll per barrier), else 32.  Measured on MI355X (us per N = 512 / 640 / 768 / 1024 /
+// 1536 / 2048 solve): 16 knots 257 / 317 / 314 / 331 / 395 / -, 32 knots 273 / 288 / 278 /
+// 287 / 402 / 408, 48 knots 317 / 335 / 321 / 328 / 338 / 453.
+int default_single_kpw(int64_t N) {
+  for (int k : kKpwChoices)
+    if (N <= k) return k;
+  for (int k : {16, 32, 48})
+    if ((N + k - 1) / k <= 32) return k;
+  return 32;
+}
 constexpr int kNumKpw = (int)(sizeof(kKpwChoices) / sizeof(kKpwChoices[0]));
 
 // Device arrays owned by a cached schedule: freed with it.
@@ -357,11 +371,7 @@ KArgs base_args(mpcpcg_ctx *c, const mpcpcg_problem *p, const mpcpcg_opts *o) {
 
 int single_kpw(mpcpcg_ctx *c, int N) {
   if (c->kpw_override) return c->kpw_override;
-  // one workgroup when it fits (no gang barrier; the smallest such shape has the cheapest
-  // workgroup barriers), else the 3-waves/SIMD shape
-  for (int k : kKpwChoices)
-    if (N <= k) return k;
-  return 16;
+  return default_single_kpw(N);
 }
 
 int launch_single(mpcpcg_ctx *c, KArgs &a, int N, int kpw, int mode, hipStream_t s) {
@@ -1695,9 +1705,9 @@ int mpcpcg_solve_noalloc(const mpcpcg_problem *p, const mpcpcg_opts *o, float *l
   std::call_once(d.once, [&] { na_setup(d, dev); });
   if (d.rc) return d.rc;
   const int N = p->N;
-  int kpw = 16, ki = 2;  // the shape mpcpcg_solve takes on a context with default settings
-  for (int i = 0; i < kNumKpw; ++i)
-    if (N <= kKpwChoices[i]) { kpw = kKpwChoices[i]; ki = i; break; }
+  const int kpw = default_single_kpw(N);  // the shape mpcpcg_solve takes by default
+  int ki = 0;
+  while (kKpwChoices[ki] != kpw) ++ki;
   const int g = (N + kpw - 1) / kpw;
   if (g > kNaMaxParts || g > d.cap[ki])
     return na_fail(MPCPCG_EINVAL, "horizon N=%d needs %d co-resident workgroups; the device holds %d", N, g, d.cap[ki]);
