@@ -189,6 +189,7 @@ struct mpcpcg_ctx {
   int max_batch = 0;
   int64_t max_tasks = 0;
   int kpw_override = 0;
+  int fwd_cap[kNumKpw] = {};  // resident forward workgroups per shape of kKpwChoices (0: not queried yet)
   int use_graph = 1;
   // per-XCD task lists: only on a device that reports eight XCDs (one partition spanning
   // the whole MI355X), where workgroups are dispatched to the XCDs in turn
@@ -413,6 +414,37 @@ int validate_batch(mpcpcg_ctx *c, int batch, const int64_t *off, const mpcpcg_pr
 
 // Schedule of the batched PCG launch for a signature: a fixed shape if one is set, else the
 // autotuned choice, else 16 knots per workgroup with the context's default placement.
+// Default shape of a batch with no tuned choice: 16 knots per workgroup (three workgroups
+// per compute unit) unless the longest horizon needs more than 32 parts of 16 knots, where
+// every barrier then polls twice.  Then 32 or 48 knots (one workgroup per compute unit) may
+// cost fewer rounds x iteration time; the estimate takes every problem as the longest, the
+// gangs that fit one XCD's share at once, and 1.27x the iteration time for two polls, as
+// measured on MI355X (forward ms, 16 / 32 knots: 4 x N = 1024 0.349 / 0.307, 48 x N = 1024
+// 2.22 / 1.74, 8 x N = 768 0.334 / 0.301, 32 x N = 768 0.771 / 1.142).
+int default_batch_kpw(mpcpcg_ctx *c, const Sig &off) {
+  const int B = (int)off.size() - 1;
+  int64_t nmax = 0;
+  for (int b = 0; b < B; ++b) nmax = std::max(nmax, off[b + 1] - off[b]);
+  if ((nmax + 15) / 16 <= 32) return 16;
+  int best = 16;
+  double best_cost = 0.0;
+  for (int i = 0; i < kNumKpw; ++i) {
+    const int k = kKpwChoices[i];
+    if (k != 16 && k != 32 && k != 48) continue;
+    if (!c->fwd_cap[i] && capacity(c, k, mpc::kForward, &c->fwd_cap[i]) != MPCPCG_OK) return 16;
+    const int64_t g = (nmax + k - 1) / k;
+    const int64_t per_xcd = c->fwd_cap[i] / 8;
+    if (g > per_xcd || per_xcd < 1) continue;
+    const int64_t at_once = 8 * (per_xcd / g);
+    const double cost = (double)((B + at_once - 1) / at_once) * (g > 32 ? 1.27 : 1.0);
+    if (best_cost == 0.0 || cost < best_cost) {
+      best = k;
+      best_cost = cost;
+    }
+  }
+  return best;
+}
+
 Tuned pick(mpcpcg_ctx *c, const Sig &off) {
   Tuned t;
   t.pin = c->xcd_pin;
@@ -421,6 +453,7 @@ Tuned pick(mpcpcg_ctx *c, const Sig &off) {
     return t;
   }
   if (const Tuned *u = c->tuned.get(off)) return *u;
+  t.kpw = default_batch_kpw(c, off);
   return t;
 }
 

@@ -135,6 +135,26 @@ def test_placements_agree_bit_for_bit(ctx, Ns):
     check_against_oracle(outs[0], packed, off)
 
 
+def test_default_shape_of_long_horizons(ctx):
+    # a batch whose longest horizon needs more than 32 parts of 16 knots takes 32 knots per
+    # workgroup by default (one poll per barrier); forward and adjoint against the oracle's
+    # forward -> adjoint (horizons 1024, 700, 1024, 33; seeds 7301 + b)
+    Ns = [1024, 700, 1024, 33]
+    probs = synth.batch(Ns, seed0=7301)
+    packed, off = synth.pack(probs)
+    d = dev(packed)
+    assert ctx.mpcpcg_tuned_schedule(off) == (32, True)
+    out = ctx.mpcpcg_solve_batched(d, off, eps=EPS)
+    g = ctx.mpcpcg_backward(d, off, out, 2 * out["lam"], eps=EPS)
+    torch.cuda.synchronize()
+    check_against_oracle(out, packed, off)
+    fo = orc.solve_batch(packed, off, eps=EPS, threads=8)
+    ref = orc.backward_batch(packed, off, fo, 2 * fo["lam"], None, None, eps=EPS, threads=8)
+    assert (stats(g["stats"])["status"] == 0).all()
+    for k in ("dQ", "dA", "dB", "dR", "dq", "dr"):
+        assert rel(g[k].cpu().numpy(), ref[k]) < 1e-4, k
+
+
 def test_single_solve_of_more_parts_than_an_xcd_holds(ctx):
     # 24-knot workgroups (six waves) are resident one per compute unit, so a 43-part single
     # solve (N = 1024) does not fit one XCD's 32 compute units and must spread over the
