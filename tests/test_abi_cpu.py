@@ -138,6 +138,11 @@ int main(void) {
   /* exchange records beyond 2 GiB (32-bit offsets in the kernels) */
   int too_big = mpcpcg_create(&ctx, 14, 7, 4 * (195652LL - 1) + 4, 1);
   int too_big_wide = mpcpcg_create(&ctx, 28, 14, 4 * 1016801LL, 1);
+  /* the factor record calls: no context */
+  long long fac_bytes = (long long)mpcpcg_factor_bytes(0, 512);
+  int keep = mpcpcg_solve_batched_keep(0, 1, 0, 0, 0, 0, 0, 0, 0, 0, 0);
+  int reuse = mpcpcg_backward_reuse(0, 1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0);
+  printf("%lld %d %d\n", fac_bytes, keep, reuse);
   printf("%d %d %d %d %d %d %d %d %d %d %d\n", unsupported, einval_method, einval_ls, ctx == 0, too_big, too_big_wide,
          (int)sizeof(mpcpcg_problem), (int)sizeof(mpcpcg_opts), (int)sizeof(mpcpcg_stats),
          (int)sizeof(mpcpcg_chain_model), (int)sizeof(mpcpcg_trajectory));
@@ -162,6 +167,9 @@ def test_header_is_c_and_the_library_links(tmp_path):
     subprocess.run(cmd, check=True, capture_output=True)
     env = dict(os.environ, LD_LIBRARY_PATH=libdir + ":/opt/rocm/lib:" + os.environ.get("LD_LIBRARY_PATH", ""))
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True, env=env).stdout.split()
+    fac_bytes, keep, reuse = (int(v) for v in out[:3])
+    assert fac_bytes == -1 and keep == mpcpcg.EINVAL and reuse == mpcpcg.EINVAL
+    out = out[3:]
     unsupported, einval_method, einval_ls, ctx_null, too_big, too_big_wide = (int(v) for v in out[:6])
     assert unsupported == mpcpcg.EUNSUPPORTED and einval_method == mpcpcg.EINVAL and einval_ls == mpcpcg.EINVAL
     assert ctx_null == 1
