@@ -167,7 +167,9 @@ int mpcpcg_backward(mpcpcg_ctx *ctx, int32_t batch, const int64_t *knot_off,
  * bit.  `factors` is a device buffer owned by the caller, 256-byte aligned, of
  * mpcpcg_factor_bytes(ctx, knot_off[batch]) bytes (5,824 per knot);
  * the caller keeps it and the packed problem unchanged between the two calls (the record
- * is not checked against the problem).  Both calls return EINVAL on an (28, 14) context,
+ * is not checked against the problem).  The record of a problem whose forward solve
+ * reported MPCPCG_TIMEOUT is undefined (other statuses leave it whole: Phi^-1 does not
+ * depend on the iteration).  Both calls return EINVAL on an (28, 14) context,
  * for a NULL or misaligned record, and for the argument errors of the plain calls.
  * mpcpcg_factor_bytes returns -1 for a NULL or (28, 14) context or total_knots < 1. */
 int64_t mpcpcg_factor_bytes(const mpcpcg_ctx *ctx, int64_t total_knots);
