@@ -27,7 +27,8 @@ BATCH = 256
 EPS = 1e-6
 SEED0 = 6001
 
-# Algorithmic work ("Algorithmic work"): FP64/FP32 flops per unit.
+# Algorithmic work: FP64/FP32 flops per unit (per knot and iteration, formation, primal step,
+# gradients).
 FLOP_PER_KNOT_ITER = 2492      # S p (1176) + Phi^-1 r (1176) + 2 dots (56) + 3 axpys (84)
 FLOP_PER_KNOT_FORM = 39102     # Q^-1, R^-1, theta, theta^-1, two Phi^-1 blocks, gamma
 FLOP_PER_KNOT_FORM_S = 16464   # the same without Q^-1, R^-1, theta^-1 and the Phi^-1 blocks
@@ -667,8 +668,8 @@ def main():
         ingest_counters(args.ingest_counters)
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus %d requested); batched problems "
-              "are independent and would shard by problem across GPUs, see DESIGN.md" % args.gpus,
+        print("bench.py: runs on one GPU only (--gpus %d requested); batched problems are "
+              "independent and would shard by problem across GPUs" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
