@@ -76,6 +76,30 @@ def test_batch_adjoint_and_warm_start_equal_regular_build(ctxs):
     same(wm[0], wm[1], ("lam", "dx", "du", "stats"))
 
 
+@pytest.mark.parametrize("kpw", [0, 4])
+def test_kept_record_adjoint_equals_regular_build(ctxs, kpw):
+    # the adjoint that reads the forward's factor record instead of forming Phi^-1 skips the
+    # D^-1 exchange through LDS: it must still read no LDS it has not written
+    a, b = ctxs
+    Ns = [1, 5, 33, 64, 100, 2, 17, 129, 16, 48]
+    packed, off = synth.pack(synth.batch(Ns, seed0=8950))
+    d = dev(packed)
+    fw, bw = [], []
+    for c in (a, b):
+        c.mpcpcg_set_knots_per_group(kpw)
+        try:
+            rec = c.factor_record(int(off[-1]), d["q"].device)
+            f = c.mpcpcg_solve_batched(d, off, eps=EPS, factors=rec)
+            g = c.mpcpcg_backward(d, off, f, 2 * f["lam"], eps=EPS, factors=rec)
+            torch.cuda.synchronize()
+        finally:
+            c.mpcpcg_set_knots_per_group(0)
+        fw.append({k: v.clone() for k, v in f.items()})
+        bw.append({k: v.clone() for k, v in g.items()})
+    same(fw[0], fw[1], ("lam", "dx", "du", "stats"))
+    same(bw[0], bw[1], ("dQ", "dR", "dA", "dB", "dq", "dr", "dx0", "stats"))
+
+
 @pytest.mark.parametrize("N", [1, 33, 70])
 def test_form_schur_equals_regular_build(ctxs, N):
     a, b = ctxs
