@@ -1,9 +1,10 @@
 """The LDS-poisoning debug build (libmpcpcg_poison.so: every workgroup of the fused kernel
 fills its LDS with a NaN pattern at the start of each task) against the regular build, bit
 for bit, on single solves across horizons and workgroup shapes, a ragged batch, the adjoint
-(also the one that reads the forward's factor record), a warm start and the Schur formation.  A read of LDS that a task has not written first would
-turn that task's outputs into NaN (or change them), so equal finite bits show that no
-formation, PCG or epilogue step reads stale LDS."""
+(also the one that reads the forward's factor record), a warm start and the Schur formation.
+A read of LDS that a task has not written first would turn that task's outputs into NaN (or
+change them), so equal finite bits show that no formation, PCG or epilogue step reads stale
+LDS."""
 import numpy as np
 import pytest
 
