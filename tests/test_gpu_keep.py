@@ -62,18 +62,22 @@ def assert_same(x, y, keys):
         assert torch.equal(x[k], y[k]), k
 
 
-@pytest.mark.parametrize("kpw", [0, 4, 16])
-def test_kept_factors_give_the_same_bits(ctx, kpw):
+@pytest.mark.parametrize("kpw,pin", [(0, True), (4, True), (16, True), (16, False)])
+def test_kept_factors_give_the_same_bits(ctx, kpw, pin):
     # ragged horizons: one knot, under one part, exactly one part, parts plus a ragged
-    # tail, several parts (seeds 8101 + b); automatic and fixed workgroup shapes
+    # tail, several parts (seeds 8101 + b); automatic and fixed workgroup shapes, gangs on
+    # one XCD each and on the global queue
     Ns = [1, 5, 16, 17, 40, 96, 200, 13]
     packed, off = synth.pack(synth.batch(Ns, seed0=8101))
     d = dev(packed)
     ctx.mpcpcg_set_knots_per_group(kpw)
+    ctx.mpcpcg_set_xcd_pinning(pin)
     try:
+        assert ctx.mpcpcg_tuned_schedule(off)[1] == pin
         f0, g0, f1, g1, _ = plain_and_kept(ctx, d, off)
     finally:
         ctx.mpcpcg_set_knots_per_group(0)
+        ctx.mpcpcg_set_xcd_pinning(True)
     assert_same(f0, f1, ("lam", "dx", "du", "stats"))
     assert_same(g0, g1, GRADS)
 
