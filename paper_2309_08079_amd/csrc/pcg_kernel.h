@@ -1287,11 +1287,15 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
     // ------------------------------------------------------------- gang teardown
     // Every part has read all it needs once all G have arrived here, so the last one out
     // zeroes the gang's tagged words (no stale tag survives into a later solve) and resets
-    // the gang state.
+    // the gang state.  The arrival is a relaxed count after a wait for this wave's stores:
+    // the only values another part reads after it (part 0's stats, the abort flag) are
+    // device-scope stores of this wave, so they have landed before the count moves, and an
+    // acquire-release count would also write back the whole L2 at every task's end.
     if (multi) {
       __syncthreads();
       if (tid == 0) {
-        const int d = __hip_atomic_fetch_add(&gang->done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_s_waitcnt(0);
+        const int d = __hip_atomic_fetch_add(&gang->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         sh_task = d == G - 1;
       }
       __syncthreads();
@@ -1318,7 +1322,8 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
               __hip_atomic_store(status_word, (int)MPCPCG_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
           __hip_atomic_store(&gang->abort, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(&gang->done, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          // (the next solve of this gang record is in a later launch)
+          __hip_atomic_store(&gang->done, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
     }
