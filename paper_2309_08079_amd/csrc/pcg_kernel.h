@@ -1336,7 +1336,10 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
   // unsolved, and those report TIMEOUT instead of stale stats.
   __syncthreads();
   if (tid == 0) {
-    const int d = __hip_atomic_fetch_add(&a.queue[1], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    // relaxed, as the gang count: the queue counters are atomics, the stats device-scope
+    // stores of this wave, and the next launch starts after this one's end
+    __builtin_amdgcn_s_waitcnt(0);
+    const int d = __hip_atomic_fetch_add(&a.queue[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (d == (int)gridDim.x - 1) {
       if (a.persistent && a.xoff && a.stats) {
         for (int x = 0; x < 8; ++x) {
@@ -1350,7 +1353,7 @@ __global__ void __launch_bounds__(KPW * kGroup) __attribute__((amdgpu_waves_per_
       __hip_atomic_store(&a.queue[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       for (int x = 0; x < 8; ++x) __hip_atomic_store(&a.queue[4 + x], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_fetch_add(&a.queue[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&a.queue[1], 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&a.queue[1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }

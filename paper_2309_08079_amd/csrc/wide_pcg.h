@@ -432,7 +432,10 @@ __global__ void __launch_bounds__(KW * 64) __attribute__((amdgpu_waves_per_eu(3,
     if (multi) {
       __syncthreads();
       if (tid == 0) {
-        const int d = __hip_atomic_fetch_add(&gang->done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        // a relaxed count after the barrier, which waited for every wave's stores (part 0's
+        // stats, the abort flag): no L2 write-back at every task's end
+        __builtin_amdgcn_s_waitcnt(0);
+        const int d = __hip_atomic_fetch_add(&gang->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         sh_task = d == G - 1;
       }
       __syncthreads();
@@ -447,7 +450,7 @@ __global__ void __launch_bounds__(KW * 64) __attribute__((amdgpu_waves_per_eu(3,
           if (ab) __hip_atomic_store(reinterpret_cast<int *>(a.stats + pd.id) + 1, (int)MPCPCG_TIMEOUT,
                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           __hip_atomic_store(&gang->abort, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(&gang->done, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&gang->done, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }
     }
@@ -456,7 +459,8 @@ __global__ void __launch_bounds__(KW * 64) __attribute__((amdgpu_waves_per_eu(3,
   // ---- launch teardown: the last workgroup out resets the queue
   __syncthreads();
   if (tid == 0) {
-    const int d = __hip_atomic_fetch_add(&g.queue[1], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0);
+    const int d = __hip_atomic_fetch_add(&g.queue[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (d == (int)gridDim.x - 1) {
       // a list whose XCD ran no workgroup of this launch (a placement the host did not
       // expect) leaves its problems unsolved: they report TIMEOUT instead of stale stats
@@ -472,7 +476,7 @@ __global__ void __launch_bounds__(KW * 64) __attribute__((amdgpu_waves_per_eu(3,
       __hip_atomic_store(&g.queue[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       for (int x = 0; x < 8; ++x) __hip_atomic_store(&g.queue[4 + x], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_fetch_add(&g.queue[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&g.queue[1], 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&g.queue[1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
