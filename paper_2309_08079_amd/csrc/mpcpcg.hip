@@ -578,13 +578,15 @@ int ensure_factor_ws(mpcpcg_ctx *c) {
 
 // Whether a call takes the factorisation path: always for MPCPCG_METHOD_FACTOR; for
 // MPCPCG_METHOD_AUTO by a cost model measured on MI355X (nx = 14, microseconds):
-//   PCG: rounds of resident problems (12,288 knots each), each ~40 + iters x (3.3 + 2.0 f)
-//        with f the fraction of the device the batch fills; iters ~100 for cold starts and
+//   PCG: rounds of resident problems (12,288 knots each), each ~40 + iters x (2.1 + 0.7 f)
+//        with f the fraction of the device the batch fills (2.2 us per iteration for one
+//        N = 512 solve, ~318 us per round of 256 x N = 512); iters ~100 for cold starts and
 //        ~45 for warm-started receding-horizon solves;
-//   factorisation: its two parallel phases, ~25 + 138 per 12,288 knots, plus the cyclic
+//   factorisation: its two parallel phases, ~25 + 58 per 12,288 knots, plus the cyclic
 //        reduction, one workgroup per problem: ~25 + 0.55 N for the longest horizon alone,
 //        up to 2.2x that when every CU holds a problem; a lone problem, whose first levels
-//        spread over the device, ~49 + 20.5 (log2 N - 4) in all.
+//        spread over the device, ~49 + 20.5 (log2 N - 4) in all, against ~95 + 2.1 iters
+//        for its PCG solve.
 // The adjoint (warm = false) is priced as a cold solve.
 bool use_factor(mpcpcg_ctx *c, const std::vector<int64_t> &off, bool warm) {
   if (c->method == MPCPCG_METHOD_PCG) return false;
@@ -597,11 +599,13 @@ bool use_factor(mpcpcg_ctx *c, const std::vector<int64_t> &off, bool warm) {
   const double rounds = std::ceil(knots / per_round);
   const double fill = std::min(1.0, knots / per_round);
   const double iters = warm ? 45.0 : 100.0;
-  const double t_pcg = rounds * (40.0 + iters * (3.3 + 2.0 * fill));
-  if (B == 1) return 49.0 + 20.5 * std::max(0.0, std::log2((double)nmax) - 4.0) < t_pcg;
+  const double t_pcg = rounds * (40.0 + iters * (2.1 + 0.7 * fill));
+  // a lone solve also pays its launch and setup outside the rounds: ~95 us end to end
+  // beside the iterations (warm N = 128 receding-horizon solves take ~0.19 ms at p50)
+  if (B == 1) return 49.0 + 20.5 * std::max(0.0, std::log2((double)nmax) - 4.0) < 95.0 + iters * 2.1;
   const double load = 1.0 + 1.2 * (double)std::min<int64_t>(B, c->cus) / (double)c->cus;
   const double t_cr = (25.0 + 0.55 * (double)nmax) * load * std::ceil((double)B / (double)c->cus);
-  const double t_fac = 25.0 + 138.0 * knots / per_round + t_cr;
+  const double t_fac = 25.0 + 58.0 * knots / per_round + t_cr;
   return t_fac < t_pcg;
 }
 
